@@ -1,0 +1,202 @@
+"""Pins of the oracle's estimator: the rendering equation with the incident
+light split into visible environment light plus indirect light (Eqs.
+pbr_render, incident, sec_bouce), direct light by RIS (Eq. restir) and
+indirect light by BRDF-sampled continuation (Eq. mc_indir)."""
+import numpy as np
+import pytest
+
+from paper_2406_16360_amd import synth
+
+
+def _view(eye, w=16, h=16, spp=1, fov=40.0, target=(0, 0, 0)):
+    return synth.View(c2w=synth.look_at(eye, target), fov_y_deg=fov, w=w, h=h, spp=spp)
+
+
+def test_white_furnace_exact(oracle_lib):
+    """Albedo-1 Lambertian convex sphere under constant L with cosine-sampled
+    candidates only: every sample returns exactly L (hit or miss)."""
+    L = 1.5
+    sc = synth.furnace_scene(L)
+    o = oracle_lib.Oracle(sc)
+    v = _view([0.3, 0.5, 3.0], w=24, h=24, spp=2)
+    wl = synth.Workload("f", sc, [v], synth.Options(bounces=3, ris_m=6, ris_m_brdf=6, brdf=0, seed=9))
+    rgb, _ = o.render(wl.views, wl.opts, synth.all_items(wl))
+    assert np.abs(rgb - L).max() < 1e-12
+
+
+def test_white_furnace_mixed_candidates_mean(oracle_lib):
+    """With environment candidates mixed in, each sample is random but the
+    mean is still L (unbiased RIS)."""
+    L = 1.5
+    sc = synth.furnace_scene(L)
+    o = oracle_lib.Oracle(sc)
+    v = _view([0.0, 0.0, 3.0], w=4, h=4, spp=20000, fov=10.0)
+    wl = synth.Workload("f", sc, [v], synth.Options(bounces=2, ris_m=8, ris_m_brdf=3, brdf=0, seed=3))
+    rgb, _ = o.render(wl.views, wl.opts, synth.all_items(wl))
+    m = rgb.mean(0)
+    se = rgb.std(0) / np.sqrt(rgb.shape[0])
+    assert np.all(np.abs(m - L) < 4 * se + 1e-12)
+
+
+def test_plane_irradiance(oracle_lib):
+    """Unoccluded plane under constant L: irradiance pi L, so the pixel is
+    albedo * L exactly per sample with cosine-sampled candidates."""
+    a = (0.3, 0.5, 0.7)
+    L = 2.0
+    sc = synth.plane_scene(a, L)
+    o = oracle_lib.Oracle(sc)
+    v = _view([0.0, 3.0, 2.0], w=16, h=16, spp=2)
+    wl = synth.Workload("p", sc, [v], synth.Options(bounces=2, ris_m=4, ris_m_brdf=4, brdf=0, seed=1))
+    rgb, _ = o.render(wl.views, wl.opts, synth.all_items(wl))
+    assert np.abs(rgb - np.array(a, np.float32).astype(np.float64) * L).max() < 1e-12
+
+
+def _small_scene(seed=21, lobe=8.0):
+    rng = np.random.default_rng(seed)
+    sp, sf = synth.icosphere(1, 1.0)
+    gp, gf, _ = synth.ground_plane(-1.05, 4.0)
+    pos, faces, _ = synth.merge([(sp, sf, np.zeros((sp.shape[0], 2), np.float32)),
+                                 (gp, gf, np.zeros((4, 2), np.float32))])
+    nv = pos.shape[0]
+    vmat = np.concatenate([rng.uniform(0.2, 0.9, (nv, 3)), rng.uniform(0.2, 0.9, (nv, 1)),
+                           rng.uniform(0.0, 1.0, (nv, 1))], 1).astype(np.float32)
+    env = synth.hdr_env(8, 16, rng, [(lobe, 20.0)])
+    env = (0.5 * env).astype(np.float32)
+    return synth.Scene(pos=pos, faces=faces, env=env, mat_mode=0, vmat=vmat)
+
+
+def _brute_lambert(o, sc, view, pixels, n, B, rng):
+    """Independent brute-force estimator (numpy RNG, cosine sampling, Lambert
+    only): at each vertex one cosine-sampled direction for the visible env
+    light (estimate a * L * V) and one for the continuation (throughput *= a).
+    Only the pinned intersection routine is shared with the oracle."""
+    out = np.zeros((len(pixels), 3))
+    var = np.zeros((len(pixels), 3))
+    c2w = np.asarray(view.c2w, np.float64)
+    th = np.tan(0.5 * np.deg2rad(view.fov_y_deg))
+    env = np.maximum(sc.env.astype(np.float64), 0.0)
+    eh, ew = env.shape[:2]
+
+    def env_L(d):
+        theta = np.arccos(np.clip(d[:, 1], -1, 1))
+        phi = np.arctan2(d[:, 0], -d[:, 2])
+        col = np.clip(np.floor((phi / (2 * np.pi) + 0.5) * ew).astype(int), 0, ew - 1)
+        row = np.clip(np.floor(theta / np.pi * eh).astype(int), 0, eh - 1)
+        return env[row, col]
+
+    def cosine(nrm, m):
+        u1, u2 = rng.random(m), rng.random(m)
+        r, ph = np.sqrt(u1), 2 * np.pi * u2
+        local = np.stack([r * np.cos(ph), r * np.sin(ph), np.sqrt(1 - u1)], -1)
+        # any orthonormal frame: the cosine density is rotation invariant
+        a = np.where(np.abs(nrm[:, :1]) > 0.9, np.array([[0.0, 1.0, 0.0]]), np.array([[1.0, 0.0, 0.0]]))
+        t = np.cross(a, nrm)
+        t /= np.linalg.norm(t, axis=1, keepdims=True)
+        b = np.cross(nrm, t)
+        return local[:, :1] * t + local[:, 1:2] * b + local[:, 2:] * nrm
+
+    pos = sc.pos.astype(np.float64)
+    F = sc.faces
+    for pi_, p in enumerate(pixels):
+        x, y = p % view.w, p // view.w
+        u0, u1 = rng.random(n), rng.random(n)
+        nx = 2 * (x + u0) / view.w - 1
+        ny = 1 - 2 * (y + u1) / view.h
+        dc = np.stack([nx * th * view.w / view.h, ny * th, -np.ones(n)], -1)
+        d = dc @ c2w[:3, :3].T
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        o_ = np.tile(c2w[:3, 3], (n, 1))
+        C = np.zeros((n, 3))
+        T = np.ones((n, 3))
+        alive = np.ones(n, bool)
+        for k in range(B):
+            prim, t, b1, b2 = o.trace(o_, d)
+            miss = alive & (prim < 0)
+            if k == 0:
+                C[miss] = env_L(d[miss])
+            alive &= prim >= 0
+            idx = np.nonzero(alive)[0]
+            if idx.size == 0:
+                break
+            f = F[prim[idx]]
+            v0, v1, v2 = pos[f[:, 0]], pos[f[:, 1]], pos[f[:, 2]]
+            bb1, bb2 = b1[idx, None], b2[idx, None]
+            hp = (1 - bb1 - bb2) * v0 + bb1 * v1 + bb2 * v2
+            ng = np.cross(v1 - v0, v2 - v0)
+            ng /= np.linalg.norm(ng, axis=1, keepdims=True)
+            flip = (ng * d[idx]).sum(1) > 0
+            ng[flip] *= -1
+            alb = np.clip((1 - bb1 - bb2) * sc.vmat[f[:, 0], :3] + bb1 * sc.vmat[f[:, 1], :3]
+                          + bb2 * sc.vmat[f[:, 2], :3], 0, 1)
+            mu = np.clip((1 - bb1 - bb2) * sc.vmat[f[:, 0], 4:5] + bb1 * sc.vmat[f[:, 1], 4:5]
+                         + bb2 * sc.vmat[f[:, 2], 4:5], 0, 1)
+            kd = (1 - mu) * alb
+            eps = 1e-4 * np.maximum(1.0, np.abs(hp).max(1, keepdims=True))
+            org = hp + eps * ng
+            wl = cosine(ng, idx.size)
+            occ = o.trace(org, wl, any_hit=True)[0] >= 0
+            C[idx] += T[idx] * kd * env_L(wl) * (~occ)[:, None]
+            if k == B - 1:
+                break
+            wc = cosine(ng, idx.size)
+            T[idx] *= kd
+            o_[idx], d[idx] = org, wc
+        out[pi_] = C.mean(0)
+        var[pi_] = C.var(0) / n
+    return out, var
+
+
+@pytest.mark.parametrize("ris_m,ris_m_brdf,rr", [(8, 4, -1), (8, 0, -1), (6, 6, 1)])
+def test_unbiased_vs_bruteforce_lambert(oracle_lib, ris_m, ris_m_brdf, rr):
+    sc = _small_scene()
+    o = oracle_lib.Oracle(sc)
+    n = 100000
+    view = _view([1.0, 1.2, 2.6], w=8, h=8, spp=n)
+    pixels = [9, 20, 27, 36, 45, 54]
+    wl = synth.Workload("u", sc, [view], synth.Options(bounces=3, ris_m=ris_m, ris_m_brdf=ris_m_brdf,
+                                                       rr_start=rr, brdf=0, seed=77))
+    means, vars_ = [], []
+    for p in pixels:
+        items = np.stack([np.zeros(n, np.int32), np.full(n, p, np.int32), np.arange(n, dtype=np.int32)], -1)
+        rgb, _ = o.render(wl.views, wl.opts, items)
+        means.append(rgb.mean(0))
+        vars_.append(rgb.var(0) / n)
+    bf, bvar = _brute_lambert(o, sc, view, pixels, n, 3, np.random.default_rng(5))
+    z = (np.array(means) - bf) / np.sqrt(np.array(vars_) + bvar + 1e-30)
+    assert np.abs(z).max() < 4.5, z
+
+
+def test_unbiased_ggx_candidate_mixes(oracle_lib):
+    """With the GGX lobe on, env-only, BRDF-only and mixed candidate sets
+    (and Russian roulette) estimate the same expectation."""
+    sc = _small_scene(seed=5, lobe=4.0)
+    o = oracle_lib.Oracle(sc)
+    n = 60000
+    view = _view([1.0, 1.2, 2.6], w=8, h=8, spp=n)
+    pixels = [20, 27, 36, 45]
+    res = []
+    for m, mb, rr in [(1, 1, -1), (8, 0, -1), (8, 4, -1), (16, 12, 1)]:
+        wl = synth.Workload("u", sc, [view], synth.Options(bounces=3, ris_m=m, ris_m_brdf=mb, rr_start=rr,
+                                                           brdf=1, seed=101 + m + mb))
+        mm, vv = [], []
+        for p in pixels:
+            items = np.stack([np.zeros(n, np.int32), np.full(n, p, np.int32), np.arange(n, dtype=np.int32)], -1)
+            rgb, _ = o.render(wl.views, wl.opts, items)
+            mm.append(rgb.mean(0))
+            vv.append(rgb.var(0) / n)
+        res.append((np.array(mm), np.array(vv)))
+    base_m, base_v = res[2]
+    for mm, vv in res[:2] + res[3:]:
+        z = (mm - base_m) / np.sqrt(vv + base_v + 1e-30)
+        assert np.abs(z).max() < 4.5, z
+
+
+def test_deterministic_and_hash(oracle_lib):
+    w = synth.config1()
+    o = oracle_lib.Oracle(w.scene)
+    items = synth.sample_items(w, 3000, 1)
+    a, ha = o.render(w.views, w.opts, items, nthreads=1)
+    b, hb = o.render(w.views, w.opts, items, nthreads=8)
+    assert np.array_equal(a, b) and np.array_equal(ha, hb)
+    # the same pixel's different samples take different decisions
+    assert len(np.unique(ha)) > 100
