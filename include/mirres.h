@@ -1,0 +1,188 @@
+/*
+ * mirres.h — C ABI of the MI355X (gfx950) differentiable path tracer with
+ * reservoir-resampled environment lighting: the rendering hot path of MIRReS
+ * (arXiv 2406.16360).
+ *
+ * The problem statement (Sec. 3 "Method overview"): given a triangle mesh,
+ * spatially-varying materials, an HDR environment map and calibrated
+ * cameras, render images with physically based path tracing and
+ * back-propagate image-space gradients to the materials and the environment
+ * map.  Here:
+ *   - rendering equation, Sec. 3 Eq. pbr_render, with the incident light
+ *     split into visible environment light plus indirect light (Eq. incident);
+ *   - direct light by resampled importance sampling with a streaming weighted
+ *     reservoir (Sec. 4.1, Eq. restir; Appendix A "Spatial-temporal reuse"
+ *     for the reservoir update), over environment-map and BRDF candidates;
+ *   - indirect light by BRDF-sampled multi-bounce continuation truncated
+ *     after `bounces` surface vertices (Sec. 4.2, Eqs. mc_indir, sec_bouce);
+ *   - visibility by explicit ray-mesh intersection over a linear BVH
+ *     (Appendix A "Visibility estimation");
+ *   - gradients of the detached-sampling path functional (Sec. 4.2 detaches
+ *     indirect rays; grad_mode selects that or the full path).
+ *
+ * Conventions shared by every entry point
+ *   Memory     Arrays named d_* and every pointer inside mrs_scene / mrs_grads
+ *              / mrs_options debug fields are DEVICE pointers, caller-owned,
+ *              contiguous, float32 / int32 / uint32.  mrs_view arrays and the
+ *              structs themselves are HOST memory, read during the call only.
+ *              The library owns only mrs_bvh, mrs_tape and an internal
+ *              workspace; release them with the *_destroy calls.
+ *   Streams    `stream` is a hipStream_t (NULL = default stream).  All work
+ *              is enqueued on it; calls return before the GPU finishes, except
+ *              mrs_build_bvh, which waits for its own stream.
+ *   Errors     Every call returns an mrs_status; nothing throws across the
+ *              ABI.  mrs_last_error() gives a message for the last failing
+ *              call on the calling thread (valid until the next call).
+ *              Arguments are validated on the host before any GPU work.
+ *   Layouts    mesh positions [nv][3], faces [nf][3] (int32 vertex indices),
+ *              uv [nv][2]; per-vertex materials [nv][5] = (albedo r, g, b,
+ *              roughness, metallic); textures albedo [th][tw][3],
+ *              roughness [th][tw], metallic [th][tw] (row 0 at v = 0,
+ *              bilinear, wrap); env [eh][ew][3] linear HDR, equirectangular,
+ *              +y up, row 0 at the +y pole.  Images are packed per view at
+ *              pixel_offset: [sum_v W_v * H_v][3], row-major, row 0 on top.
+ *   Random     Every uniform is Philox4x32-10 (Salmon et al., SC'11) with
+ *              key = seed and counter = (pixel, sample_offset + sample, view,
+ *              (vertex << 16) | block); the output is bit-deterministic for
+ *              fixed inputs.
+ */
+#ifndef MIRRES_H
+#define MIRRES_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MRS_OK = 0,
+    MRS_EINVAL = -1,        /* invalid argument (message says which) */
+    MRS_ENOMEM = -2,        /* device or pinned-host allocation failed */
+    MRS_EHIP = -3,          /* a HIP runtime call failed */
+    MRS_EOVERFLOW = -4,     /* a size exceeds a documented limit */
+    MRS_EUNSUPPORTED = -5   /* option combination not implemented */
+} mrs_status;
+
+enum { MRS_MAT_VERTEX = 0, MRS_MAT_TEXTURE = 1 };
+enum { MRS_BRDF_LAMBERT = 0, MRS_BRDF_LAMBERT_GGX = 1 };
+enum { MRS_BG_ENV = 0, MRS_BG_BLACK = 1 };
+enum { MRS_GRAD_FULL = 0, MRS_GRAD_PRIMARY = 1 };
+enum { MRS_TAPE_AUTO = 0, MRS_TAPE_ON = 1, MRS_TAPE_OFF = 2 };
+
+#define MRS_MAX_BOUNCES 8
+#define MRS_MAX_VIEWS 65536
+
+typedef struct mrs_bvh mrs_bvh;     /* opaque, library-owned */
+typedef struct mrs_tape mrs_tape;   /* opaque, library-owned */
+
+/* Scene: mesh, materials, lighting (Sec. 3: mesh {V, F}, material m,
+ * environment map L_env).  All pointers are device pointers. */
+typedef struct {
+    const float   *pos;   int32_t nv;     /* [nv][3] */
+    const int32_t *faces; int32_t nf;     /* [nf][3] */
+    const float   *uv;                    /* [nv][2]; required for MRS_MAT_TEXTURE */
+    const mrs_bvh *bvh;                   /* from mrs_build_bvh over the same pos/faces */
+    int32_t        mat_mode;              /* MRS_MAT_VERTEX or MRS_MAT_TEXTURE */
+    const float   *vmat;                  /* [nv][5] for MRS_MAT_VERTEX */
+    const float   *albedo;                /* [th][tw][3] */
+    const float   *rough;                 /* [th][tw] */
+    const float   *metal;                 /* [th][tw] */
+    int32_t        tw, th;
+    const float   *env;                   /* [eh][ew][3] */
+    int32_t        ew, eh;
+} mrs_scene;
+
+/* Pinhole camera (Sec. 3 "Rendering": camera ray o + t d).  c2w is
+ * row-major camera-to-world; the camera looks down -z with +y up.
+ * pixel_offset places this view's pixels in the packed image. */
+typedef struct {
+    float    c2w[16];
+    float    fov_y_deg;
+    int32_t  w, h, spp;
+    uint32_t sample_offset;
+    int64_t  pixel_offset;
+} mrs_view;
+
+typedef struct {
+    int32_t  bounces;        /* B in [1, MRS_MAX_BOUNCES]: surface vertices with NEE (Sec. 4.2: 3) */
+    int32_t  ris_m;          /* M >= 1 RIS candidates per vertex (Eq. restir's m) */
+    int32_t  ris_m_brdf;     /* M_b in [0, M]: BRDF candidates; the other M - M_b sample the env */
+    int32_t  rr_start;       /* -1: no Russian roulette; else roulette after vertex k >= rr_start */
+    uint64_t seed;           /* Philox key */
+    int32_t  brdf;           /* MRS_BRDF_* */
+    int32_t  background;     /* MRS_BG_*: radiance of camera rays that miss */
+    int32_t  grad_mode;      /* MRS_GRAD_*: FULL (all vertices) or PRIMARY (Sec. 4.2 detach) */
+    int32_t  tape_mode;      /* MRS_TAPE_*: keep per-vertex records for the adjoint or recompute */
+    int64_t  tape_budget;    /* bytes the tape may use in AUTO mode; 0 = half of free device memory */
+    int32_t  pool;           /* paths in flight; 0 = library default */
+    int32_t  block;          /* threads per block of the trace/shade kernels; 0 = default (256) */
+    float   *debug_sample_rgb;   /* nullable device [S][3]: per-sample radiance, S = sum W*H*spp */
+    uint32_t*debug_hash;         /* nullable device [S]: per-sample decision hash */
+} mrs_options;
+
+/* Gradient outputs (device, ACCUMULATED with +=; the caller zeroes them).
+ * Any pointer may be NULL to skip that group.  Shapes follow mrs_scene. */
+typedef struct {
+    float *vmat;     /* [nv][5] */
+    float *albedo;   /* [th][tw][3] */
+    float *rough;    /* [th][tw] */
+    float *metal;    /* [th][tw] */
+    float *env;      /* [eh][ew][3] */
+} mrs_grads;
+
+/* Builds a linear BVH (Karras, HPG 2012; the paper's LBVH, Appendix A) over
+ * the triangles.  d_pos [nv][3] and d_faces [nf][3] are device arrays; the
+ * BVH keeps its own copy of the triangles in leaf order, so the inputs may be
+ * freed afterwards.  Degenerate triangles are kept and never hit.  Waits for
+ * `stream` before returning.  Errors: MRS_EINVAL (null, nv/nf <= 0, nf >
+ * 2^27), MRS_ENOMEM, MRS_EHIP. */
+mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
+                         void *stream, mrs_bvh **out);
+void       mrs_bvh_destroy(mrs_bvh *bvh);
+
+/* BVH statistics (host): number of triangles, nodes, tree depth. */
+mrs_status mrs_bvh_info(const mrs_bvh *bvh, int32_t *nf, int32_t *nodes, int32_t *depth);
+
+/* Ray-mesh intersection for a batch of n rays (Eq. intersect; Appendix A
+ * visibility test).  d_orig, d_dir: device float [n][3].  Closest hit
+ * (any_hit = 0): d_hit [n][4] = (t, b1, b2, face id as int32 bits) with the
+ * smallest t > 0, ties to the lower face id, face id -1 on a miss; b1, b2 are
+ * the barycentric weights of the face's 2nd and 3rd vertex.  Any hit
+ * (any_hit = 1): only the face id slot is meaningful (-1 none, >= 0 some
+ * hit).  Errors: MRS_EINVAL (null pointers, n < 0), MRS_EHIP. */
+mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const float *d_dir, int64_t n, int32_t any_hit,
+                     float *d_hit, void *stream);
+
+/* Renders n_views views (Eq. pbr_render estimated per sample with RIS direct
+ * light and BRDF-sampled indirect light) into d_image [sum W*H][3] (float32,
+ * overwritten at each view's pixel_offset; other pixels untouched).  Each
+ * pixel is the mean over its spp samples.  If tape_out is non-NULL and the
+ * tape policy keeps a tape, *tape_out receives the per-vertex records for
+ * mrs_render_backward (else *tape_out = NULL).  Errors: MRS_EINVAL (bad
+ * sizes, options, or a BVH built for another triangle count), MRS_EOVERFLOW
+ * (more than 2^32 - 1 samples), MRS_ENOMEM, MRS_EHIP. */
+mrs_status mrs_render(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
+                      const mrs_options *opt, float *d_image, mrs_tape **tape_out, void *stream);
+
+/* Adjoint path replay: accumulates the gradient of sum_pixels
+ * d_grad_image . image with respect to the materials and env texels into
+ * `grads`.  Uses `tape` (from mrs_render with identical arguments) when
+ * non-NULL, else re-renders chunk by chunk into a bounded tape
+ * (recompute).  Errors: MRS_EINVAL (including a tape recorded for different
+ * views, samples, bounces or seed), MRS_ENOMEM, MRS_EHIP. */
+mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
+                               const mrs_options *opt, const float *d_grad_image,
+                               const mrs_grads *grads, const mrs_tape *tape, void *stream);
+
+/* Bytes a tape for these views/options would take (host arithmetic). */
+int64_t    mrs_tape_bytes(const mrs_view *views, int32_t n_views, const mrs_options *opt);
+void       mrs_tape_destroy(mrs_tape *tape);
+
+/* Frees the library's internal device workspace (it regrows on demand). */
+void        mrs_release_workspace(void);
+const char *mrs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

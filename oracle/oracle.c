@@ -115,6 +115,19 @@ static uint32_t fnv_word(uint32_t h, uint32_t w) {
 }
 #define FNV_BASIS 2166136261u
 
+/* The decision hash of a sample is the XOR of one hash per event, so the
+ * events may be recorded in any order:
+ *   miss at vertex k            fnv(k, 0xFFFFFFFF)
+ *   surface vertex k            fnv(k, face id, selected candidate or ~0, continuation code)
+ *                               code 0: last vertex, 1: continued, 2: no valid
+ *                               continuation sample, 3: killed by roulette
+ *   shadow ray of vertex k      fnv(k | 0x10000, 1 if unoccluded else 0) */
+static uint32_t ev_miss(uint32_t k) { return fnv_word(fnv_word(FNV_BASIS, k), 0xFFFFFFFFu); }
+static uint32_t ev_vertex(uint32_t k, uint32_t prim, uint32_t sel, uint32_t code) {
+    return fnv_word(fnv_word(fnv_word(fnv_word(FNV_BASIS, k), prim), sel), code);
+}
+static uint32_t ev_nee(uint32_t k, uint32_t vis) { return fnv_word(fnv_word(FNV_BASIS, k | 0x10000u), vis); }
+
 /* ------------------------------------------------------------------ */
 /* context                                                             */
 /* ------------------------------------------------------------------ */
@@ -458,15 +471,30 @@ void orc_destroy(orc_ctx *c) {
 }
 
 /* ------------------------------------------------------------------ */
-/* shading frame (Duff et al., JCGT 2017, branchless ONB) with the sign  */
-/* taken as +1 for n_z >= 0 (so -0 counts as +)                         */
+/* shading frame: the branchless orthonormal basis of Duff et al. (JCGT  */
+/* 2017, sign +1 for z >= 0) built for m = R n and mapped back with R,   */
+/* where R = (1/9)[[1,4,8],[4,7,-4],[8,-4,1]] is a fixed symmetric       */
+/* orthogonal matrix.  Every such basis switches branch on some plane of */
+/* normals; with R that plane (8x - 4y + z = 0) contains no axis-aligned  */
+/* or symmetric face normal of the synthetic meshes, so float and double */
+/* evaluations take the same branch except within rounding of it.       */
 /* ------------------------------------------------------------------ */
+static const double FRAME_R[3][3] = { { 1.0 / 9, 4.0 / 9, 8.0 / 9 },
+                                      { 4.0 / 9, 7.0 / 9, -4.0 / 9 },
+                                      { 8.0 / 9, -4.0 / 9, 1.0 / 9 } };
+static void rmul(const double v[3], double r[3]) {
+    for (int i = 0; i < 3; ++i) r[i] = FRAME_R[i][0] * v[0] + FRAME_R[i][1] * v[1] + FRAME_R[i][2] * v[2];
+}
 void orc_frame(const double n[3], double t[3], double b[3]) {
-    double sg = n[2] >= 0.0 ? 1.0 : -1.0;
-    double a = -1.0 / (sg + n[2]);
-    double bb = n[0] * n[1] * a;
-    t[0] = 1.0 + sg * n[0] * n[0] * a; t[1] = sg * bb; t[2] = -sg * n[0];
-    b[0] = bb; b[1] = sg + n[1] * n[1] * a; b[2] = -n[1];
+    double m[3], tl[3], bl[3];
+    rmul(n, m);
+    double sg = m[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (sg + m[2]);
+    double bb = m[0] * m[1] * a;
+    tl[0] = 1.0 + sg * m[0] * m[0] * a; tl[1] = sg * bb; tl[2] = -sg * m[0];
+    bl[0] = bb; bl[1] = sg + m[1] * m[1] * a; bl[2] = -m[1];
+    rmul(tl, t);
+    rmul(bl, b);
 }
 
 /* ------------------------------------------------------------------ */
@@ -607,36 +635,45 @@ static int mix_sample(const double n[3], const double t[3], const double b[3], c
 /* ------------------------------------------------------------------ */
 /* surface interaction and material fetch                              */
 /* ------------------------------------------------------------------ */
+/* Interpolation in affine form, so that equal inputs give that value
+ * exactly (a material at a clamp boundary stays on it): per-vertex values
+ * x0 + b1 (x1 - x0) + b2 (x2 - x0); textures bilinear as nested lerps
+ * lerp(lerp(x00, x10, fx), lerp(x01, x11, fx), fy), lerp(a, b, f) = a + f (b - a). */
 typedef struct {
-    int32_t idx[4]; double w[4]; int nw;   /* texel or vertex indices and weights */
+    int32_t idx[4];   /* vertices v0, v1, v2 or texels (i0,j0), (i1,j0), (i0,j1), (i1,j1) */
+    double f1, f2;    /* (b1, b2) or (fx, fy) */
+    int nw;
 } interp;
 
 static long long wrapi(long long i, long long n) { long long r = i % n; return r < 0 ? r + n : r; }
 
 static void material_interp(const orc_ctx *c, int32_t prim, double b1, double b2, interp *ip) {
     const int32_t *fv = c->s.faces + 3 * (size_t)prim;
-    double b0 = 1.0 - b1 - b2;
     if (c->s.mat_mode == 0) {
         ip->nw = 3;
         ip->idx[0] = fv[0]; ip->idx[1] = fv[1]; ip->idx[2] = fv[2];
-        ip->w[0] = b0; ip->w[1] = b1; ip->w[2] = b2;
+        ip->f1 = b1; ip->f2 = b2;
         return;
     }
     const float *uv = c->s.uv;
-    double u = b0 * uv[2 * (size_t)fv[0]] + b1 * uv[2 * (size_t)fv[1]] + b2 * uv[2 * (size_t)fv[2]];
-    double v = b0 * uv[2 * (size_t)fv[0] + 1] + b1 * uv[2 * (size_t)fv[1] + 1] + b2 * uv[2 * (size_t)fv[2] + 1];
+    double u0 = uv[2 * (size_t)fv[0]], u1 = uv[2 * (size_t)fv[1]], u2 = uv[2 * (size_t)fv[2]];
+    double v0 = uv[2 * (size_t)fv[0] + 1], v1 = uv[2 * (size_t)fv[1] + 1], v2 = uv[2 * (size_t)fv[2] + 1];
+    double u = u0 + b1 * (u1 - u0) + b2 * (u2 - u0);
+    double v = v0 + b1 * (v1 - v0) + b2 * (v2 - v0);
     /* bilinear, texel centres at (i + 1/2) / W, wrap addressing */
     double x = u * c->s.tw - 0.5, y = v * c->s.th - 0.5;
     double x0 = floor(x), y0 = floor(y);
-    double fx = x - x0, fy = y - y0;
     long long i0 = wrapi((long long)x0, c->s.tw), i1 = wrapi((long long)x0 + 1, c->s.tw);
     long long j0 = wrapi((long long)y0, c->s.th), j1 = wrapi((long long)y0 + 1, c->s.th);
     ip->nw = 4;
-    ip->idx[0] = (int32_t)(j0 * c->s.tw + i0); ip->w[0] = (1 - fx) * (1 - fy);
-    ip->idx[1] = (int32_t)(j0 * c->s.tw + i1); ip->w[1] = fx * (1 - fy);
-    ip->idx[2] = (int32_t)(j1 * c->s.tw + i0); ip->w[2] = (1 - fx) * fy;
-    ip->idx[3] = (int32_t)(j1 * c->s.tw + i1); ip->w[3] = fx * fy;
+    ip->idx[0] = (int32_t)(j0 * c->s.tw + i0);
+    ip->idx[1] = (int32_t)(j0 * c->s.tw + i1);
+    ip->idx[2] = (int32_t)(j1 * c->s.tw + i0);
+    ip->idx[3] = (int32_t)(j1 * c->s.tw + i1);
+    ip->f1 = x - x0; ip->f2 = y - y0;
 }
+
+static dual dlerp(dual a, dual b, double f) { return dadd(a, dscale(dsub(b, a), f)); }
 
 /* parameter kinds for derivative seeds */
 enum { PK_NONE = -1, PK_VMAT = 0, PK_ALBEDO, PK_ROUGH, PK_METAL, PK_ENV };
@@ -658,16 +695,18 @@ static dual param_value(const orc_ctx *c, int kind, int64_t idx, seed_t sd) {
 /* material at a hit as duals, clamped: albedo, metallic in [0,1], roughness
  * in [R_MIN, 1] */
 static void material_d(const orc_ctx *c, const interp *ip, seed_t sd, dual m[5]) {
-    for (int ch = 0; ch < 5; ++ch) m[ch] = dc(0.0);
-    for (int k = 0; k < ip->nw; ++k) {
-        for (int ch = 0; ch < 5; ++ch) {
-            dual x;
-            if (c->s.mat_mode == 0) x = param_value(c, PK_VMAT, (int64_t)ip->idx[k] * 5 + ch, sd);
-            else if (ch < 3) x = param_value(c, PK_ALBEDO, (int64_t)ip->idx[k] * 3 + ch, sd);
-            else if (ch == 3) x = param_value(c, PK_ROUGH, ip->idx[k], sd);
-            else x = param_value(c, PK_METAL, ip->idx[k], sd);
-            m[ch] = dadd(m[ch], dscale(x, ip->w[k]));
+    for (int ch = 0; ch < 5; ++ch) {
+        dual x[4];
+        for (int k = 0; k < ip->nw; ++k) {
+            if (c->s.mat_mode == 0) x[k] = param_value(c, PK_VMAT, (int64_t)ip->idx[k] * 5 + ch, sd);
+            else if (ch < 3) x[k] = param_value(c, PK_ALBEDO, (int64_t)ip->idx[k] * 3 + ch, sd);
+            else if (ch == 3) x[k] = param_value(c, PK_ROUGH, ip->idx[k], sd);
+            else x[k] = param_value(c, PK_METAL, ip->idx[k], sd);
         }
+        if (ip->nw == 3)
+            m[ch] = dadd(x[0], dadd(dscale(dsub(x[1], x[0]), ip->f1), dscale(dsub(x[2], x[0]), ip->f2)));
+        else
+            m[ch] = dlerp(dlerp(x[0], x[1], ip->f1), dlerp(x[2], x[3], ip->f1), ip->f2);
     }
     for (int ch = 0; ch < 3; ++ch) m[ch] = dclamp(m[ch], 0.0, 1.0);
     m[3] = dclamp(m[3], R_MIN, 1.0);
@@ -731,14 +770,14 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
     camera_ray(vw, pixel % vw->w, pixel / vw->w, u[0], u[1], o, d);
     double T[3] = { 1, 1, 1 };
     rgb[0] = rgb[1] = rgb[2] = 0.0;
-    uint32_t h = FNV_BASIS;
+    uint32_t h = 0;
     rec->nv = 0; rec->miss_tex = -1;
     for (int a = 0; a < 3; ++a) rec->d[a] = d[a];
     for (int k = 1; k <= opt->bounces; ++k) {
         cnt[ORC_C_CLOSEST_RAYS]++;
         hitrec hr = trace_closest(c, o, d, 0, &cnt[ORC_C_CLOSEST_NODES], &cnt[ORC_C_CLOSEST_TRIS]);
         if (hr.prim < 0) {
-            h = fnv_word(h, 0xFFFFFFFFu);
+            h ^= ev_miss((uint32_t)k);
             if (k == 1) {
                 cnt[ORC_C_PRIMARY_MISS]++;
                 if (opt->background == 0) {
@@ -750,7 +789,6 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
             break;
         }
         cnt[ORC_C_HITS]++;
-        h = fnv_word(h, (uint32_t)hr.prim);
         vtx *V = &rec->v[rec->nv++];
         V->prim = hr.prim; V->b1 = hr.b1; V->b2 = hr.b2;
         V->nee = 0; V->W = 0.0; V->ytex = -1; V->q = 0.0; V->rr = 1.0;
@@ -807,28 +845,25 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
                 }
             }
         }
-        h = fnv_word(h, (uint32_t)sel);
         if (sel >= 0) {
             V->W = wsum / phat_y;
             cnt[ORC_C_SHADOW_RAYS]++;
             int occl = trace_any(c, org, V->y, 0, &cnt[ORC_C_SHADOW_NODES], &cnt[ORC_C_SHADOW_TRIS]);
-            h = fnv_word(h, occl ? 0u : 1u);
+            h ^= ev_nee((uint32_t)k, occl ? 0u : 1u);
             if (!occl) {
                 cnt[ORC_C_NEE_VISIBLE]++;
                 V->nee = 1;
                 double cy = dot3(V->n, V->y);
                 for (int ch = 0; ch < 3; ++ch) rgb[ch] += T[ch] * Ly[ch] * fy[ch] * cy * V->W;
             }
-        } else {
-            h = fnv_word(h, 2u);
         }
-        if (k == opt->bounces) { h = fnv_word(h, 0u); break; }
+        if (k == opt->bounces) { h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 0u); break; }
         /* --- continuation (Eq. mc_indir): BRDF mixture sample ------------- */
         uniforms4(opt->seed, (uint32_t)pixel, S, (uint32_t)vi, (uint32_t)k, 0xFFFFu, u);
         double wi[3];
         int lobe = co > 0.0 ? mix_sample(V->n, tf, bf, V->wo, m, spec, u[0], u[1], u[2], wi) : 0;
         double q = lobe ? mix_pdf(V->n, V->wo, wi, m, spec) : 0.0;
-        if (!lobe || !(q > 0.0)) { h = fnv_word(h, 2u); break; }
+        if (!lobe || !(q > 0.0)) { h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 2u); break; }
         double f[3];
         brdf_eval_plain(V->n, V->wo, wi, m, spec, f);
         double ci = dot3(V->n, wi);
@@ -837,11 +872,11 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
         for (int a = 0; a < 3; ++a) V->wi[a] = wi[a];
         if (opt->rr_start >= 0 && k >= opt->rr_start) {
             double qr = fmin(0.95, fmax(T[0], fmax(T[1], T[2])));
-            if (!(qr > 0.0) || !(u[3] < qr)) { h = fnv_word(h, 3u); break; }
+            if (!(qr > 0.0) || !(u[3] < qr)) { h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 3u); break; }
             for (int ch = 0; ch < 3; ++ch) T[ch] /= qr;
             V->rr = 1.0 / qr;
         }
-        h = fnv_word(h, 1u);
+        h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 1u);
         for (int a = 0; a < 3; ++a) { o[a] = org[a]; d[a] = wi[a]; }
     }
     *hash = h;

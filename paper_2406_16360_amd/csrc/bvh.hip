@@ -1,0 +1,378 @@
+// Linear BVH builder for gfx950 (the paper builds an LBVH with its own
+// kernels, Appendix A "Visibility estimation"; construction after Karras,
+// "Maximizing parallelism in the construction of BVHs, octrees and k-d
+// trees", HPG 2012):
+//   triangle boxes -> centroid bounds -> 63-bit Morton codes -> sort of
+//   (code, index) pairs -> binary radix tree from longest common prefixes ->
+//   bottom-up boxes with per-node arrival counters -> node layout with both
+//   child boxes per node, small subtrees collapsed into leaves of <= 4
+//   triangles, triangles copied in leaf order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "device.h"
+#include "runtime.h"
+
+namespace mrs {
+
+namespace {
+
+__global__ void k_tri_bounds(const float *__restrict__ pos, const int32_t *__restrict__ faces, int nf,
+                             float4 *__restrict__ lo, float4 *__restrict__ hi) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    V3 a = ld3(pos + 3 * (size_t)faces[3 * (size_t)f]);
+    V3 b = ld3(pos + 3 * (size_t)faces[3 * (size_t)f + 1]);
+    V3 c = ld3(pos + 3 * (size_t)faces[3 * (size_t)f + 2]);
+    lo[f] = make_float4(fminf(a.x, fminf(b.x, c.x)), fminf(a.y, fminf(b.y, c.y)), fminf(a.z, fminf(b.z, c.z)), 0.f);
+    hi[f] = make_float4(fmaxf(a.x, fmaxf(b.x, c.x)), fmaxf(a.y, fmaxf(b.y, c.y)), fmaxf(a.z, fmaxf(b.z, c.z)), 0.f);
+}
+
+// centroid bounds: one block-level reduction per block, then one block
+// reduces the partials.  out[2 * blk] = min, out[2 * blk + 1] = max.
+__global__ void k_centroid_bounds(const float4 *__restrict__ lo, const float4 *__restrict__ hi, int n,
+                                  float4 *__restrict__ out) {
+    __shared__ float smin[3][256], smax[3][256];
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float4 l = lo[i], h = hi[i];
+        float c[3] = {0.5f * (l.x + h.x), 0.5f * (l.y + h.y), 0.5f * (l.z + h.z)};
+        for (int a = 0; a < 3; ++a) { mn[a] = fminf(mn[a], c[a]); mx[a] = fmaxf(mx[a], c[a]); }
+    }
+    for (int a = 0; a < 3; ++a) { smin[a][threadIdx.x] = mn[a]; smax[a][threadIdx.x] = mx[a]; }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                smin[a][threadIdx.x] = fminf(smin[a][threadIdx.x], smin[a][threadIdx.x + s]);
+                smax[a][threadIdx.x] = fmaxf(smax[a][threadIdx.x], smax[a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = make_float4(smin[0][0], smin[1][0], smin[2][0], 0.f);
+        out[2 * blockIdx.x + 1] = make_float4(smax[0][0], smax[1][0], smax[2][0], 0.f);
+    }
+}
+
+__device__ __forceinline__ uint64_t spread21(uint64_t x) {
+    x &= 0x1FFFFFull;
+    x = (x | x << 32) & 0x1F00000000FFFFull;
+    x = (x | x << 16) & 0x1F0000FF0000FFull;
+    x = (x | x << 8) & 0x100F00F00F00F00Full;
+    x = (x | x << 4) & 0x10C30C30C30C30C3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ void k_morton(const float4 *__restrict__ lo, const float4 *__restrict__ hi, int n, int npow2,
+                         const float4 *__restrict__ bounds, uint64_t *__restrict__ keys, uint32_t *__restrict__ ids) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow2) return;
+    if (i >= n) { keys[i] = ~0ull; ids[i] = 0xFFFFFFFFu; return; }
+    float4 bl = bounds[0], bh = bounds[1];
+    float4 l = lo[i], h = hi[i];
+    float c[3] = {0.5f * (l.x + h.x), 0.5f * (l.y + h.y), 0.5f * (l.z + h.z)};
+    float blo[3] = {bl.x, bl.y, bl.z}, bhi[3] = {bh.x, bh.y, bh.z};
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        float ext = bhi[a] - blo[a];
+        float t = ext > 0.f ? (c[a] - blo[a]) / ext : 0.5f;
+        t = fminf(fmaxf(t, 0.f), 1.f);
+        q[a] = (uint64_t)fminf(t * 2097152.0f, 2097151.0f);
+    }
+    keys[i] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+    ids[i] = (uint32_t)i;
+}
+
+// one merge step of a bitonic sort over (key, id) pairs (ids break ties)
+__global__ void k_bitonic(uint64_t *__restrict__ keys, uint32_t *__restrict__ ids, int npow2, int j, int k) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow2) return;
+    int p = i ^ j;
+    if (p <= i) return;
+    uint64_t ka = keys[i], kb = keys[p];
+    uint32_t ia = ids[i], ib = ids[p];
+    bool a_gt_b = ka > kb || (ka == kb && ia > ib);
+    bool up = (i & k) == 0;
+    if (a_gt_b == up) { keys[i] = kb; keys[p] = ka; ids[i] = ib; ids[p] = ia; }
+}
+
+// the same step for all j < 512 inside a block, in LDS
+__global__ void k_bitonic_local(uint64_t *__restrict__ keys, uint32_t *__restrict__ ids, int npow2, int k, int jmax) {
+    __shared__ uint64_t sk[1024];
+    __shared__ uint32_t si[1024];
+    int base = blockIdx.x * 1024;
+    for (int t = threadIdx.x; t < 1024; t += blockDim.x) { sk[t] = keys[base + t]; si[t] = ids[base + t]; }
+    __syncthreads();
+    for (int j = jmax; j > 0; j >>= 1) {
+        for (int t = threadIdx.x; t < 1024; t += blockDim.x) {
+            int p = t ^ j;
+            if (p > t) {
+                uint64_t ka = sk[t], kb = sk[p];
+                uint32_t ia = si[t], ib = si[p];
+                bool a_gt_b = ka > kb || (ka == kb && ia > ib);
+                bool up = ((base + t) & k) == 0;
+                if (a_gt_b == up) { sk[t] = kb; sk[p] = ka; si[t] = ib; si[p] = ia; }
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < 1024; t += blockDim.x) { keys[base + t] = sk[t]; ids[base + t] = si[t]; }
+}
+
+// longest common prefix of sorted keys i and j; -1 outside [0, n); equal keys
+// fall back to the indices (Karras 2012, Sec. 4)
+__device__ __forceinline__ int delta(const uint64_t *__restrict__ keys, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = keys[i], b = keys[j];
+    if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+    return __clzll(a ^ b);
+}
+
+// internal node i covers the sorted range [first, last]; children are
+// internal nodes (id < n - 1) or leaves (id = n - 1 + leaf index)
+__global__ void k_karras(const uint64_t *__restrict__ keys, int n, int32_t *__restrict__ child,
+                         int32_t *__restrict__ parent, int2 *__restrict__ range) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = delta(keys, n, i, i - d);
+    int lmax = 2;
+    while (delta(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int l = 0;
+    for (int t = lmax / 2; t >= 1; t /= 2)
+        if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    int j = i + l * d;
+    int dnode = delta(keys, n, i, j);
+    int s = 0, t, div = 2;
+    do {
+        t = (l + div - 1) / div;
+        if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+        div *= 2;
+    } while (t > 1);
+    int g = i + s * d + min(d, 0);
+    int first = min(i, j), last = max(i, j);
+    int lc = (first == g) ? (n - 1 + g) : g;
+    int rc = (last == g + 1) ? (n - 1 + g + 1) : g + 1;
+    child[2 * i] = lc;
+    child[2 * i + 1] = rc;
+    parent[lc] = i;
+    parent[rc] = i;
+    range[i] = make_int2(first, last);
+}
+
+// bottom-up boxes: the second thread to reach a node merges its children
+__global__ void k_boxes(const float4 *__restrict__ tlo, const float4 *__restrict__ thi,
+                        const uint32_t *__restrict__ ids, int n, const int32_t *__restrict__ child,
+                        const int32_t *__restrict__ parent, int32_t *__restrict__ flags,
+                        float4 *__restrict__ blo, float4 *__restrict__ bhi) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int leaf = n - 1 + k;
+    uint32_t f = ids[k];
+    blo[leaf] = tlo[f];
+    bhi[leaf] = thi[f];
+    __threadfence();
+    int node = parent[leaf];
+    while (node >= 0) {
+        if (atomicAdd(&flags[node], 1) == 0) return;
+        __threadfence();
+        int a = child[2 * node], b = child[2 * node + 1];
+        float4 la = blo[a], lb = blo[b], ha = bhi[a], hb = bhi[b];
+        blo[node] = make_float4(fminf(la.x, lb.x), fminf(la.y, lb.y), fminf(la.z, lb.z), 0.f);
+        bhi[node] = make_float4(fmaxf(ha.x, hb.x), fmaxf(ha.y, hb.y), fmaxf(ha.z, hb.z), 0.f);
+        __threadfence();
+        node = parent[node];
+    }
+}
+
+// boxes are widened by a relative epsilon so the FP32 slab test stays
+// conservative for every triangle inside
+__device__ __forceinline__ float pad_lo(float x) { return x - (fabsf(x) * 4e-7f + 1e-30f); }
+__device__ __forceinline__ float pad_hi(float x) { return x + (fabsf(x) * 4e-7f + 1e-30f); }
+
+__device__ __forceinline__ int32_t child_ref(int c, int n, const int2 *__restrict__ range) {
+    if (c >= n - 1) return ~(((c - (n - 1)) << 3) | 0);
+    int2 r = range[c];
+    int cnt = r.y - r.x + 1;
+    if (cnt <= kLeafMax) return ~((r.x << 3) | (cnt - 1));
+    return c;
+}
+
+__global__ void k_layout(int n, const int32_t *__restrict__ child, const int2 *__restrict__ range,
+                         const float4 *__restrict__ blo, const float4 *__restrict__ bhi, BvhNode *__restrict__ nodes) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= max(n - 1, 1)) return;
+    BvhNode nd;
+    if (n == 1) {   // a single triangle: root with one leaf and an empty child
+        float4 l = blo[0], h = bhi[0];
+        nd.n0 = make_float4(pad_lo(l.x), pad_hi(h.x), pad_lo(l.y), pad_hi(h.y));
+        nd.n1 = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        nd.n2 = make_float4(pad_lo(l.z), pad_hi(h.z), INFINITY, -INFINITY);
+        nd.n3 = make_int4(~0, ~0, 0, 0);
+        nodes[0] = nd;
+        return;
+    }
+    int a = child[2 * i], b = child[2 * i + 1];
+    float4 la = blo[a], ha = bhi[a], lb = blo[b], hb = bhi[b];
+    nd.n0 = make_float4(pad_lo(la.x), pad_hi(ha.x), pad_lo(la.y), pad_hi(ha.y));
+    nd.n1 = make_float4(pad_lo(lb.x), pad_hi(hb.x), pad_lo(lb.y), pad_hi(hb.y));
+    nd.n2 = make_float4(pad_lo(la.z), pad_hi(ha.z), pad_lo(lb.z), pad_hi(hb.z));
+    nd.n3 = make_int4(child_ref(a, n, range), child_ref(b, n, range), 0, 0);
+    nodes[i] = nd;
+}
+
+__global__ void k_tris(const float *__restrict__ pos, const int32_t *__restrict__ faces,
+                       const uint32_t *__restrict__ ids, int n, TriRec *__restrict__ tris) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t f = ids[k];
+    V3 a = ld3(pos + 3 * (size_t)faces[3 * (size_t)f]);
+    V3 b = ld3(pos + 3 * (size_t)faces[3 * (size_t)f + 1]);
+    V3 c = ld3(pos + 3 * (size_t)faces[3 * (size_t)f + 2]);
+    TriRec t;
+    t.a = make_float4(a.x, a.y, a.z, __int_as_float((int)f));
+    t.b = make_float4(b.x, b.y, b.z, 0.f);
+    t.c = make_float4(c.x, c.y, c.z, 0.f);
+    tris[k] = t;
+}
+
+// depth of every leaf (walk to the root); the maximum bounds the stack
+__global__ void k_depth(const int32_t *__restrict__ parent, int n, int32_t *__restrict__ out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int d = 0, node = parent[n - 1 + k];
+    while (node >= 0 && d < 1 << 20) { ++d; node = parent[node]; }
+    atomicMax(out, d);
+}
+
+__global__ void k_check_faces(const int32_t *__restrict__ faces, int nf, int nv, int32_t *__restrict__ bad) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    for (int k = 0; k < 3; ++k) {
+        int v = faces[3 * (size_t)f + k];
+        if (v < 0 || v >= nv) { atomicOr(bad, 1); return; }
+    }
+}
+
+inline int blocks(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+}  // namespace mrs
+
+using namespace mrs;
+
+extern "C" mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
+                                    void *stream, mrs_bvh **out) {
+    clear_error();
+    if (!out) return fail(MRS_EINVAL, "mrs_build_bvh: out is NULL");
+    *out = nullptr;
+    if (!d_pos || !d_faces) return fail(MRS_EINVAL, "mrs_build_bvh: null mesh pointer");
+    if (nv <= 0 || nf <= 0) return fail(MRS_EINVAL, "mrs_build_bvh: nv and nf must be positive");
+    if (nf > (1 << 27)) return fail(MRS_EOVERFLOW, "mrs_build_bvh: more than 2^27 triangles");
+    hipStream_t s = (hipStream_t)stream;
+    int n = nf;
+    int npow2 = 1024;
+    while (npow2 < n) npow2 *= 2;
+    DevBuf tlo, thi, keys, ids, child, parent, range, flags, blo, bhi, part, depth, bad;
+    mrs_bvh *b = new mrs_bvh();
+    b->nf = nf;
+    b->nv = nv;
+    b->nnodes = std::max(n - 1, 1);
+    mrs_status st = MRS_OK;
+#define TRY(x) do { st = (x); if (st != MRS_OK) goto done; } while (0)
+    TRY(tlo.alloc(sizeof(float4) * n));
+    TRY(thi.alloc(sizeof(float4) * n));
+    TRY(keys.alloc(sizeof(uint64_t) * npow2));
+    TRY(ids.alloc(sizeof(uint32_t) * npow2));
+    TRY(child.alloc(sizeof(int32_t) * 2 * std::max(n - 1, 1)));
+    TRY(parent.alloc(sizeof(int32_t) * (2 * n - 1)));
+    TRY(range.alloc(sizeof(int2) * std::max(n - 1, 1)));
+    TRY(flags.alloc(sizeof(int32_t) * std::max(n - 1, 1)));
+    TRY(blo.alloc(sizeof(float4) * (2 * n - 1)));
+    TRY(bhi.alloc(sizeof(float4) * (2 * n - 1)));
+    TRY(part.alloc(sizeof(float4) * 2 * 257));
+    TRY(depth.alloc(sizeof(int32_t)));
+    TRY(bad.alloc(sizeof(int32_t)));
+    TRY(b->nodes.alloc(sizeof(BvhNode) * b->nnodes));
+    TRY(b->tris.alloc(sizeof(TriRec) * n));
+    TRY(b->faces.alloc(sizeof(int32_t) * 3 * (size_t)n));
+    TRY(hip_check(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s), "memset"));
+    k_check_faces<<<blocks(n), 256, 0, s>>>(d_faces, nf, nv, (int32_t *)bad.p);
+    {
+        int32_t h_bad = 0;
+        TRY(hip_check(hipMemcpyAsync(&h_bad, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy"));
+        TRY(hip_check(hipStreamSynchronize(s), "sync"));
+        if (h_bad) { st = fail(MRS_EINVAL, "mrs_build_bvh: face index out of [0, nv)"); goto done; }
+    }
+    TRY(hip_check(hipMemcpyAsync(b->faces.p, d_faces, sizeof(int32_t) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s), "copy faces"));
+    k_tri_bounds<<<blocks(n), 256, 0, s>>>(d_pos, d_faces, nf, (float4 *)tlo.p, (float4 *)thi.p);
+    {
+        // per-block partial (min, max) of the centroids, merged on the host
+        int nb = std::min(256, blocks(n));
+        k_centroid_bounds<<<nb, 256, 0, s>>>((float4 *)tlo.p, (float4 *)thi.p, n, (float4 *)part.p + 2);
+        std::vector<float4> h(2 * nb);
+        TRY(hip_check(hipMemcpyAsync(h.data(), (float4 *)part.p + 2, sizeof(float4) * 2 * nb, hipMemcpyDeviceToHost, s), "copy"));
+        TRY(hip_check(hipStreamSynchronize(s), "sync"));
+        float4 mn = h[0], mx = h[1];
+        for (int i = 1; i < nb; ++i) {
+            mn.x = std::min(mn.x, h[2 * i].x); mn.y = std::min(mn.y, h[2 * i].y); mn.z = std::min(mn.z, h[2 * i].z);
+            mx.x = std::max(mx.x, h[2 * i + 1].x); mx.y = std::max(mx.y, h[2 * i + 1].y); mx.z = std::max(mx.z, h[2 * i + 1].z);
+        }
+        float4 hb[2] = {mn, mx};
+        TRY(hip_check(hipMemcpyAsync(part.p, hb, sizeof(hb), hipMemcpyHostToDevice, s), "copy"));
+        TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    }
+    k_morton<<<blocks(npow2), 256, 0, s>>>((float4 *)tlo.p, (float4 *)thi.p, n, npow2, (float4 *)part.p,
+                                         (uint64_t *)keys.p, (uint32_t *)ids.p);
+    for (int k = 2; k <= npow2; k *= 2) {
+        int j = k / 2;
+        for (; j >= 512; j /= 2)
+            k_bitonic<<<blocks(npow2), 256, 0, s>>>((uint64_t *)keys.p, (uint32_t *)ids.p, npow2, j, k);
+        k_bitonic_local<<<npow2 / 1024, 256, 0, s>>>((uint64_t *)keys.p, (uint32_t *)ids.p, npow2, k, j);
+    }
+    TRY(hip_check(hipMemsetAsync(parent.p, 0xFF, sizeof(int32_t) * (2 * n - 1), s), "memset"));
+    TRY(hip_check(hipMemsetAsync(flags.p, 0, sizeof(int32_t) * std::max(n - 1, 1), s), "memset"));
+    TRY(hip_check(hipMemsetAsync(depth.p, 0, sizeof(int32_t), s), "memset"));
+    if (n > 1)
+        k_karras<<<blocks(n - 1), 256, 0, s>>>((uint64_t *)keys.p, n, (int32_t *)child.p, (int32_t *)parent.p,
+                                               (int2 *)range.p);
+    k_boxes<<<blocks(n), 256, 0, s>>>((float4 *)tlo.p, (float4 *)thi.p, (uint32_t *)ids.p, n, (int32_t *)child.p,
+                                      (int32_t *)parent.p, (int32_t *)flags.p, (float4 *)blo.p, (float4 *)bhi.p);
+    k_layout<<<blocks(std::max(n - 1, 1)), 256, 0, s>>>(n, (int32_t *)child.p, (int2 *)range.p, (float4 *)blo.p,
+                                                        (float4 *)bhi.p, (BvhNode *)b->nodes.p);
+    k_tris<<<blocks(n), 256, 0, s>>>(d_pos, d_faces, (uint32_t *)ids.p, n, (TriRec *)b->tris.p);
+    k_depth<<<blocks(n), 256, 0, s>>>((int32_t *)parent.p, n, (int32_t *)depth.p);
+    {
+        int32_t h_depth = 0;
+        TRY(hip_check(hipGetLastError(), "bvh kernels"));
+        TRY(hip_check(hipMemcpyAsync(&h_depth, depth.p, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy"));
+        TRY(hip_check(hipStreamSynchronize(s), "sync"));
+        b->depth = h_depth;
+        if (h_depth + 2 > kStackSize) {
+            st = fail(MRS_EOVERFLOW, "mrs_build_bvh: tree depth %d exceeds the traversal stack (%d)", h_depth, kStackSize);
+            goto done;
+        }
+    }
+#undef TRY
+done:
+    if (st != MRS_OK) { delete b; return st; }
+    *out = b;
+    return MRS_OK;
+}
+
+extern "C" void mrs_bvh_destroy(mrs_bvh *b) { delete b; }
+
+extern "C" mrs_status mrs_bvh_info(const mrs_bvh *b, int32_t *nf, int32_t *nodes, int32_t *depth) {
+    clear_error();
+    if (!b) return fail(MRS_EINVAL, "mrs_bvh_info: bvh is NULL");
+    if (nf) *nf = b->nf;
+    if (nodes) *nodes = b->nnodes;
+    if (depth) *depth = b->depth;
+    return MRS_OK;
+}

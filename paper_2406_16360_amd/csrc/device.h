@@ -1,0 +1,344 @@
+// Device-side building blocks of the gfx950 path tracer: Philox4x32-10,
+// small vector math, the shading frame, the Lambert + GGX BRDF with its
+// mixture sampler and hand-written material derivatives, environment-map
+// sampling, and the internal data layouts shared by the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mirres.h"
+
+namespace mrs {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr float kRoughMin = 0.05f;
+constexpr float kF0Dielectric = 0.04f;
+constexpr uint32_t kBlockCont = 0xFFFFu;   // Philox block of the continuation sample
+constexpr int kStackSize = 96;             // traversal stack (tree depth is checked at build)
+constexpr int kLeafMax = 4;                // triangles per collapsed leaf
+
+// ----------------------------------------------------------------------------
+// vector helpers
+// ----------------------------------------------------------------------------
+struct V3 { float x, y, z; };
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator*(V3 a, float s) { return V3{a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ V3 operator*(V3 a, V3 b) { return V3{a.x * b.x, a.y * b.y, a.z * b.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+    return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ V3 normalize(V3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+__device__ __forceinline__ float maxc(V3 a) { return fmaxf(a.x, fmaxf(a.y, a.z)); }
+__device__ __forceinline__ float meanc(V3 a) { return (a.x + a.y + a.z) * (1.0f / 3.0f); }
+__device__ __forceinline__ V3 ld3(const float *p) { return V3{p[0], p[1], p[2]}; }
+__device__ __forceinline__ V3 xyz(float4 a) { return V3{a.x, a.y, a.z}; }
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+struct Rng {
+    uint32_t k0, k1, pixel, sample, view;
+    __device__ __forceinline__ float4 draw(uint32_t vertex, uint32_t block) const {
+        uint4 r = philox(make_uint4(pixel, sample, view, (vertex << 16) | (block & 0xFFFFu)), k0, k1);
+        return make_float4(u01(r.x), u01(r.y), u01(r.z), u01(r.w));
+    }
+};
+
+// FNV-1a (32-bit) over little-endian words, for the per-sample decision hash
+__device__ __forceinline__ uint32_t fnv_word(uint32_t h, uint32_t w) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { h ^= (w >> (8 * i)) & 0xFFu; h *= 16777619u; }
+    return h;
+}
+constexpr uint32_t kFnvBasis = 2166136261u;
+
+// ----------------------------------------------------------------------------
+// shading frame: branchless orthonormal basis (Duff et al., JCGT 2017, sign
+// +1 for z >= 0) built for m = R n and mapped back with R, where
+// R = (1/9)[[1,4,8],[4,7,-4],[8,-4,1]] is symmetric and orthogonal.  The
+// basis switches branch on the plane 8x - 4y + z = 0 of normals, which no
+// axis-aligned or mirror-symmetric face normal lies on, so float rounding of
+// a face normal cannot flip the whole frame except within rounding of it.
+// ----------------------------------------------------------------------------
+struct Frame { V3 t, b, n; };
+__device__ __forceinline__ V3 frame_r(V3 v) {
+    constexpr float k = 1.0f / 9.0f;
+    return V3{k * (v.x + 4.0f * v.y + 8.0f * v.z), k * (4.0f * v.x + 7.0f * v.y - 4.0f * v.z),
+              k * (8.0f * v.x - 4.0f * v.y + v.z)};
+}
+__device__ __forceinline__ Frame make_frame(V3 n) {
+    V3 m = frame_r(n);
+    float sg = m.z >= 0.0f ? 1.0f : -1.0f;
+    float a = -1.0f / (sg + m.z);
+    float bb = m.x * m.y * a;
+    Frame f;
+    f.t = frame_r(V3{1.0f + sg * m.x * m.x * a, sg * bb, -sg * m.x});
+    f.b = frame_r(V3{bb, sg + m.y * m.y * a, -m.y});
+    f.n = n;
+    return f;
+}
+__device__ __forceinline__ V3 to_local(const Frame &f, V3 w) { return V3{dot(w, f.t), dot(w, f.b), dot(w, f.n)}; }
+__device__ __forceinline__ V3 to_world(const Frame &f, V3 l) { return f.t * l.x + f.b * l.y + f.n * l.z; }
+
+// ----------------------------------------------------------------------------
+// material and BRDF: Lambert diffuse (1 - mu) a / pi plus GGX specular
+// D G1(wo) G1(wi) F / (4 cos_i cos_o), F Schlick with F0 = 0.04 (1 - mu) + mu a
+// ----------------------------------------------------------------------------
+struct Mat {
+    V3 a;           // clamped albedo
+    float r, mu;    // clamped roughness, metallic
+};
+
+struct Lobe {       // per-vertex constants of the BRDF at a fixed wo (local frame)
+    V3 wo;          // local outgoing direction, wo.z = cos_o
+    V3 kd;          // (1 - mu) a / pi
+    V3 f0;
+    float a2;       // alpha^2, alpha = r^2
+    float g1o;      // Smith G1(wo)
+    float pspec;    // probability of the specular lobe in the mixture sampler
+    int spec;       // GGX lobe enabled
+};
+
+__device__ __forceinline__ float ggx_g1(float a2, float c) {
+    float c2 = c * c;
+    float t2 = fmaxf(0.0f, 1.0f - c2) / c2;
+    return 2.0f / (1.0f + sqrtf(1.0f + a2 * t2));
+}
+
+__device__ __forceinline__ Lobe make_lobe(const Mat &m, V3 wo, int spec) {
+    Lobe L;
+    L.wo = wo;
+    L.spec = spec;
+    float omm = 1.0f - m.mu;
+    L.kd = m.a * (omm * kInvPi);
+    L.f0 = V3{kF0Dielectric * omm + m.mu * m.a.x, kF0Dielectric * omm + m.mu * m.a.y,
+              kF0Dielectric * omm + m.mu * m.a.z};
+    float alpha = m.r * m.r;
+    L.a2 = alpha * alpha;
+    L.g1o = wo.z > 0.0f ? ggx_g1(L.a2, wo.z) : 0.0f;
+    if (spec) {
+        float f0m = meanc(L.f0);
+        float dif = omm * meanc(m.a);
+        float den = f0m + dif;
+        L.pspec = den > 0.0f ? fminf(fmaxf(f0m / den, 0.1f), 0.9f) : 0.5f;
+    } else {
+        L.pspec = 0.0f;
+    }
+    return L;
+}
+
+// Microfacet terms for a local wi.  den is written in the cancellation-free
+// form sin^2(theta_h) + alpha^2 cos^2(theta_h) (equal to the textbook
+// (n.h)^2 (alpha^2 - 1) + 1 for a unit h).
+struct Micro { float D, g1i, fw, nh2, den; };
+__device__ __forceinline__ Micro micro(const Lobe &L, V3 wi) {
+    V3 h = normalize(wi + L.wo);
+    Micro m;
+    m.nh2 = h.z * h.z;
+    m.den = (h.x * h.x + h.y * h.y) + L.a2 * m.nh2;
+    m.D = L.a2 / (kPi * m.den * m.den);
+    m.g1i = ggx_g1(L.a2, wi.z);
+    float oh = fmaxf(0.0f, dot(L.wo, h));
+    float x = 1.0f - oh, x2 = x * x;
+    m.fw = x2 * x2 * x;
+    return m;
+}
+
+__device__ __forceinline__ V3 brdf_eval(const Lobe &L, V3 wi) {
+    if (!(wi.z > 0.0f) || !(L.wo.z > 0.0f)) return V3{0, 0, 0};
+    V3 f = L.kd;
+    if (L.spec) {
+        Micro m = micro(L, wi);
+        float k = m.D * L.g1o * m.g1i / (4.0f * wi.z * L.wo.z);
+        f = f + V3{(L.f0.x + (1.0f - L.f0.x) * m.fw) * k, (L.f0.y + (1.0f - L.f0.y) * m.fw) * k,
+                   (L.f0.z + (1.0f - L.f0.z) * m.fw) * k};
+    }
+    return f;
+}
+
+__device__ __forceinline__ float mix_pdf(const Lobe &L, V3 wi) {
+    if (!(wi.z > 0.0f) || !(L.wo.z > 0.0f)) return 0.0f;
+    float p = (1.0f - L.pspec) * wi.z * kInvPi;
+    if (L.pspec > 0.0f) {
+        Micro m = micro(L, wi);
+        p += L.pspec * L.g1o * m.D / (4.0f * L.wo.z);
+    }
+    return p;
+}
+
+// GGX visible-normal sample (Heitz, JCGT 2018) for isotropic alpha, local frame.
+__device__ __forceinline__ V3 vndf(V3 wo, float alpha, float u1, float u2) {
+    V3 vh = normalize(V3{alpha * wo.x, alpha * wo.y, wo.z});
+    float lensq = vh.x * vh.x + vh.y * vh.y;
+    V3 T1 = lensq > 0.0f ? V3{-vh.y, vh.x, 0.0f} * (1.0f / sqrtf(lensq)) : V3{1.0f, 0.0f, 0.0f};
+    V3 T2 = cross(vh, T1);
+    float r = sqrtf(u1);
+    float sp, cp;
+    sincosf(2.0f * kPi * u2, &sp, &cp);
+    float t1 = r * cp, t2 = r * sp;
+    float s = 0.5f * (1.0f + vh.z);
+    t2 = (1.0f - s) * sqrtf(1.0f - t1 * t1) + s * t2;
+    float tz = sqrtf(fmaxf(0.0f, 1.0f - t1 * t1 - t2 * t2));
+    V3 nh = T1 * t1 + T2 * t2 + vh * tz;
+    return normalize(V3{alpha * nh.x, alpha * nh.y, fmaxf(0.0f, nh.z)});
+}
+
+// Mixture sampler: u0 picks the lobe, (u1, u2) the direction.  Returns the
+// lobe (1 diffuse, 2 specular) or 0 when the direction is below the surface.
+__device__ __forceinline__ int mix_sample(const Lobe &L, float u0, float u1, float u2, V3 &wi) {
+    int lobe;
+    if (u0 < L.pspec) {
+        V3 h = vndf(L.wo, sqrtf(L.a2), u1, u2);
+        wi = h * (2.0f * dot(L.wo, h)) - L.wo;
+        lobe = 2;
+    } else {
+        float r = sqrtf(u1), sp, cp;
+        sincosf(2.0f * kPi * u2, &sp, &cp);
+        wi = V3{r * cp, r * sp, sqrtf(fmaxf(0.0f, 1.0f - u1))};
+        lobe = 1;
+    }
+    return wi.z > 0.0f ? lobe : 0;
+}
+
+// d f_c / d(albedo_c), d f / d(roughness), d f / d(metallic) at a local wi
+// (hand-written from the closed forms of D, Smith G1 and Schlick F).
+struct BrdfGrad { V3 da; V3 dr; V3 dmu; };
+__device__ __forceinline__ BrdfGrad brdf_grad(const Lobe &L, const Mat &m, V3 wi) {
+    BrdfGrad g;
+    g.da = V3{0, 0, 0}; g.dr = V3{0, 0, 0}; g.dmu = V3{0, 0, 0};
+    if (!(wi.z > 0.0f) || !(L.wo.z > 0.0f)) return g;
+    float omm = 1.0f - m.mu;
+    g.da = V3{omm * kInvPi, omm * kInvPi, omm * kInvPi};
+    g.dmu = m.a * (-kInvPi);
+    if (!L.spec) return g;
+    Micro mi = micro(L, wi);
+    float k = mi.D * L.g1o * mi.g1i / (4.0f * wi.z * L.wo.z);
+    float ofw = 1.0f - mi.fw;
+    // dF_c/da_c = mu (1 - fw); dF_c/dmu = (a_c - 0.04) (1 - fw)
+    g.da = g.da + V3{k * m.mu * ofw, k * m.mu * ofw, k * m.mu * ofw};
+    g.dmu = g.dmu + V3{k * (m.a.x - kF0Dielectric) * ofw, k * (m.a.y - kF0Dielectric) * ofw,
+                       k * (m.a.z - kF0Dielectric) * ofw};
+    // d ln D / d alpha = 2/alpha - 4 alpha cos^2(theta_h) / den
+    float alpha = m.r * m.r;
+    float dlnD = 2.0f / alpha - 4.0f * alpha * mi.nh2 / mi.den;
+    // d ln G1 / d alpha = -alpha t2 / (R (1 + R)), R = sqrt(1 + alpha^2 t2)
+    float co2 = L.wo.z * L.wo.z, ci2 = wi.z * wi.z;
+    float to2 = fmaxf(0.0f, 1.0f - co2) / co2, ti2 = fmaxf(0.0f, 1.0f - ci2) / ci2;
+    float Ro = sqrtf(1.0f + L.a2 * to2), Ri = sqrtf(1.0f + L.a2 * ti2);
+    float dlnG = -alpha * to2 / (Ro * (1.0f + Ro)) - alpha * ti2 / (Ri * (1.0f + Ri));
+    float dk = k * (dlnD + dlnG) * 2.0f * m.r;     // d alpha / d r = 2 r
+    g.dr = V3{(L.f0.x + (1.0f - L.f0.x) * mi.fw) * dk, (L.f0.y + (1.0f - L.f0.y) * mi.fw) * dk,
+              (L.f0.z + (1.0f - L.f0.z) * mi.fw) * dk};
+    return g;
+}
+
+// ----------------------------------------------------------------------------
+// environment map (equirectangular, +y up): theta = acos(d_y),
+// phi = atan2(d_x, -d_z), u = phi / 2pi + 1/2, v = theta / pi; nearest texel
+// ----------------------------------------------------------------------------
+struct EnvTables {
+    const double *marg;     // [H + 1] normalised marginal CDF over rows
+    const double *cond;     // [H][W + 1] normalised conditional CDFs
+    const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
+    const int32_t *gcond;   // [H][W] guide per row
+    const float4 *lp;       // [H][W] (L_r, L_g, L_b clamped >= 0, pdf_uv / (2 pi^2))
+    const float *raw;       // [H][W][3] the caller's env (for gradient masks)
+    int W, H;
+    int valid;              // total weight > 0
+};
+
+__device__ __forceinline__ int env_texel_of(const EnvTables &e, V3 d) {
+    float dy = fminf(fmaxf(d.y, -1.0f), 1.0f);
+    float theta = acosf(dy), phi = atan2f(d.x, -d.z);
+    float u = phi * (0.5f * kInvPi) + 0.5f, v = theta * kInvPi;
+    int col = (int)floorf(u * (float)e.W), row = (int)floorf(v * (float)e.H);
+    col = min(max(col, 0), e.W - 1);
+    row = min(max(row, 0), e.H - 1);
+    return row * e.W + col;
+}
+
+// solid-angle pdf of the env sampler at direction d, with its texel radiance
+__device__ __forceinline__ float env_pdf_dir(const EnvTables &e, V3 d, int texel, float4 lp) {
+    if (!e.valid) return 0.0f;
+    float st = sqrtf(fmaxf(0.0f, 1.0f - d.y * d.y));
+    return st > 0.0f ? lp.w / st : 0.0f;
+}
+
+// smallest i with cdf[i + 1] > u (cdf[0] = 0 <= u < 1 = cdf[n]): the unique i
+// with cdf[i] <= u < cdf[i + 1].  The guide entry is only a starting point;
+// walking back then forward makes the answer exact whatever the guide is.
+__device__ __forceinline__ int cdf_walk(const double *cdf, int start, int n, double u) {
+    int i = min(max(start, 0), n - 1);
+    while (i > 0 && cdf[i] > u) --i;
+    while (i < n - 1 && !(cdf[i + 1] > u)) ++i;
+    return i;
+}
+
+// CDF inversion (row from the marginal, column from the row's conditional,
+// linear remainder inside the texel), in double like the tables.
+__device__ __forceinline__ bool env_sample(const EnvTables &e, float u0f, float u1f, V3 &dir, int &texel,
+                                           float4 &lp, float &pdf) {
+    if (!e.valid) return false;
+    double u0 = u0f, u1 = u1f;
+    int gi = min((int)(u0 * e.H), e.H - 1);
+    int i = cdf_walk(e.marg, e.gmarg[gi], e.H, u0);
+    double fv = (u0 - e.marg[i]) / (e.marg[i + 1] - e.marg[i]);
+    const double *cr = e.cond + (size_t)i * (e.W + 1);
+    int gj = min((int)(u1 * e.W), e.W - 1);
+    int j = cdf_walk(cr, e.gcond[(size_t)i * e.W + gj], e.W, u1);
+    double fu = (u1 - cr[j]) / (cr[j + 1] - cr[j]);
+    double v = (i + fv) / e.H, u = (j + fu) / e.W;
+    float theta = (float)(3.14159265358979323846 * v);
+    float phi = (float)(6.28318530717958647692 * (u - 0.5));
+    float st, ct, sp, cp;
+    sincosf(theta, &st, &ct);
+    sincosf(phi, &sp, &cp);
+    if (!(st > 0.0f)) return false;
+    dir = V3{st * sp, ct, -st * cp};
+    texel = i * e.W + j;
+    lp = e.lp[texel];
+    pdf = lp.w / st;
+    return pdf > 0.0f;
+}
+
+// ----------------------------------------------------------------------------
+// internal layouts
+// ----------------------------------------------------------------------------
+// BVH node: both children's boxes, so one 64-byte fetch tests two boxes.
+//   n0 = (l.lo.x, l.hi.x, l.lo.y, l.hi.y), n1 = (r.lo.x, r.hi.x, r.lo.y, r.hi.y)
+//   n2 = (l.lo.z, l.hi.z, r.lo.z, r.hi.z), n3 = (lref, rref, -, -)
+// ref >= 0: internal node; ref < 0: leaf ~(first << 3 | (count - 1)) over the
+// leaf-ordered triangle array.
+struct BvhNode { float4 n0, n1, n2; int4 n3; };
+// Triangle in leaf order: v0 (w = original face id), v1, v2.
+struct TriRec { float4 a, b, c; };
+
+struct ViewDev {
+    float rot[9];
+    float org[3];
+    double tan_half, aspect;
+    int32_t w, h, spp;
+    uint32_t sample_offset;
+    int64_t pixel_offset;
+    uint64_t sample_base;   // first global sample index of the view
+    uint64_t pix_base;      // first view-order pixel index of the view
+};
+
+}  // namespace mrs

@@ -1,0 +1,365 @@
+"""Python binding of libmirres (include/mirres.h): argument marshalling only.
+
+Every step of the rendering path runs in the HIP library.  PyTorch provides
+device memory and the current stream.  If the library is missing the import
+of this module fails: there is no CPU fallback.
+
+    bvh   = build_bvh(pos, faces)                       # pos [nv,3], faces [nf,3] on cuda
+    scene = GpuScene(pos, faces, env, vmat=...)         # or uv/albedo/rough/metal
+    img   = render(scene, views, RenderOptions(...))    # [sum W*H, 3]
+    img   = render_autograd(scene, views, opts)         # differentiable w.r.t. materials and env
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmirres.so")
+
+MRS_OK, MRS_EINVAL, MRS_ENOMEM, MRS_EHIP, MRS_EOVERFLOW, MRS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+MAT_VERTEX, MAT_TEXTURE = 0, 1
+TAPE_AUTO, TAPE_ON, TAPE_OFF = 0, 1, 2
+
+
+class MirresError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mirres error {code}: {msg}")
+        self.code = code
+
+
+class _Scene(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("nv", C.c_int32), ("faces", C.c_void_p), ("nf", C.c_int32),
+                ("uv", C.c_void_p), ("bvh", C.c_void_p), ("mat_mode", C.c_int32), ("vmat", C.c_void_p),
+                ("albedo", C.c_void_p), ("rough", C.c_void_p), ("metal", C.c_void_p), ("tw", C.c_int32),
+                ("th", C.c_int32), ("env", C.c_void_p), ("ew", C.c_int32), ("eh", C.c_int32)]
+
+
+class _View(C.Structure):
+    _fields_ = [("c2w", C.c_float * 16), ("fov_y_deg", C.c_float), ("w", C.c_int32), ("h", C.c_int32),
+                ("spp", C.c_int32), ("sample_offset", C.c_uint32), ("pixel_offset", C.c_int64)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("bounces", C.c_int32), ("ris_m", C.c_int32), ("ris_m_brdf", C.c_int32), ("rr_start", C.c_int32),
+                ("seed", C.c_uint64), ("brdf", C.c_int32), ("background", C.c_int32), ("grad_mode", C.c_int32),
+                ("tape_mode", C.c_int32), ("tape_budget", C.c_int64), ("pool", C.c_int32), ("block", C.c_int32),
+                ("debug_sample_rgb", C.c_void_p), ("debug_hash", C.c_void_p)]
+
+
+class _Grads(C.Structure):
+    _fields_ = [("vmat", C.c_void_p), ("albedo", C.c_void_p), ("rough", C.c_void_p), ("metal", C.c_void_p),
+                ("env", C.c_void_p)]
+
+
+# the C-ABI symbols declared in include/mirres.h
+EXPORTS = ["mrs_build_bvh", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
+           "mrs_tape_bytes", "mrs_tape_destroy", "mrs_release_workspace", "mrs_last_error"]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2406_16360_amd/csrc/build.py "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.mrs_build_bvh.restype = i32
+    lib.mrs_build_bvh.argtypes = [p, i32, p, i32, p, C.POINTER(p)]
+    lib.mrs_bvh_destroy.argtypes = [p]
+    lib.mrs_bvh_info.restype = i32
+    lib.mrs_bvh_info.argtypes = [p, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.mrs_trace.restype = i32
+    lib.mrs_trace.argtypes = [p, p, p, i64, i32, p, p]
+    lib.mrs_render.restype = i32
+    lib.mrs_render.argtypes = [C.POINTER(_Scene), p, i32, C.POINTER(_Options), p, C.POINTER(p), p]
+    lib.mrs_render_backward.restype = i32
+    lib.mrs_render_backward.argtypes = [C.POINTER(_Scene), p, i32, C.POINTER(_Options), p, C.POINTER(_Grads), p, p]
+    lib.mrs_tape_bytes.restype = i64
+    lib.mrs_tape_bytes.argtypes = [p, i32, C.POINTER(_Options)]
+    lib.mrs_tape_destroy.argtypes = [p]
+    lib.mrs_release_workspace.argtypes = []
+    lib.mrs_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(code: int):
+    if code != MRS_OK:
+        raise MirresError(code, (_lib.mrs_last_error() or b"").decode())
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t: Optional[torch.Tensor], dtype=torch.float32) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("mirres: tensors must be on the GPU")
+    return t.detach().to(dtype).contiguous()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+@dataclasses.dataclass
+class RenderOptions:
+    bounces: int = 3
+    ris_m: int = 32
+    ris_m_brdf: int = 16
+    rr_start: int = -1
+    seed: int = 1
+    brdf: int = 1
+    background: int = 0
+    grad_mode: int = 0
+    tape_mode: int = TAPE_AUTO
+    tape_budget: int = 0
+    pool: int = 0
+    block: int = 0
+
+    @classmethod
+    def from_any(cls, o) -> "RenderOptions":
+        if isinstance(o, cls):
+            return o
+        names = [f.name for f in dataclasses.fields(cls)]
+        return cls(**{n: getattr(o, n) for n in names if hasattr(o, n)})
+
+    def struct(self, debug_rgb=None, debug_hash=None) -> _Options:
+        return _Options(self.bounces, self.ris_m, self.ris_m_brdf, self.rr_start, self.seed & (2 ** 64 - 1), self.brdf,
+                        self.background, self.grad_mode, self.tape_mode, self.tape_budget, self.pool, self.block,
+                        _ptr(debug_rgb), _ptr(debug_hash))
+
+
+class Bvh:
+    """Linear BVH over a triangle mesh (library-owned)."""
+
+    def __init__(self, pos: torch.Tensor, faces: torch.Tensor, stream=None):
+        pos = _dev(pos)
+        faces = _dev(faces, torch.int32)
+        h = C.c_void_p()
+        _check(_lib.mrs_build_bvh(pos.data_ptr(), pos.shape[0], faces.data_ptr(), faces.shape[0], _stream(stream),
+                                  C.byref(h)))
+        self._h = h
+        self.nf = int(faces.shape[0])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> Tuple[int, int, int]:
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.mrs_bvh_info(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def trace(self, orig: torch.Tensor, dirs: torch.Tensor, any_hit: bool = False, stream=None) -> torch.Tensor:
+        o = _dev(orig)
+        d = _dev(dirs)
+        out = torch.empty((o.shape[0], 4), dtype=torch.float32, device=o.device)
+        _check(_lib.mrs_trace(self._h, o.data_ptr(), d.data_ptr(), o.shape[0], int(any_hit), out.data_ptr(),
+                              _stream(stream)))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mrs_bvh_destroy(self._h)
+            self._h = None
+
+
+def build_bvh(pos: torch.Tensor, faces: torch.Tensor, stream=None) -> Bvh:
+    return Bvh(pos, faces, stream)
+
+
+class Tape:
+    """Per-vertex path records kept by render() for render_backward()."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mrs_tape_destroy(self._h)
+            self._h = None
+
+
+class GpuScene:
+    """Mesh, materials and environment map as GPU float32 tensors."""
+
+    def __init__(self, pos, faces, env, vmat=None, uv=None, albedo=None, rough=None, metal=None,
+                 bvh: Optional[Bvh] = None, device="cuda"):
+        dev = torch.device(device)
+
+        def t(x, dt=torch.float32):
+            if x is None:
+                return None
+            return torch.as_tensor(x).to(device=dev, dtype=dt).contiguous()
+
+        self.pos = t(pos)
+        self.faces = t(faces, torch.int32)
+        self.env = t(env)
+        self.vmat = t(vmat)
+        self.uv = t(uv)
+        self.albedo = t(albedo)
+        self.rough = t(rough)
+        self.metal = t(metal)
+        self.mat_mode = MAT_VERTEX if self.vmat is not None else MAT_TEXTURE
+        self.bvh = bvh if bvh is not None else Bvh(self.pos, self.faces)
+
+    @classmethod
+    def from_synth(cls, sc, device="cuda") -> "GpuScene":
+        return cls(sc.pos, sc.faces, sc.env, vmat=sc.vmat if sc.mat_mode == 0 else None, uv=sc.uv,
+                   albedo=sc.albedo, rough=sc.rough, metal=sc.metal, device=device)
+
+    def with_params(self, vmat=None, albedo=None, rough=None, metal=None, env=None) -> "GpuScene":
+        s = object.__new__(GpuScene)
+        s.__dict__.update(self.__dict__)
+        for k, v in dict(vmat=vmat, albedo=albedo, rough=rough, metal=metal, env=env).items():
+            if v is not None:
+                setattr(s, k, _dev(v))
+        return s
+
+    def struct(self) -> _Scene:
+        tw = th = 0
+        if self.mat_mode == MAT_TEXTURE:
+            th, tw = self.rough.shape
+        return _Scene(_ptr(self.pos), self.pos.shape[0], _ptr(self.faces), self.faces.shape[0], _ptr(self.uv),
+                      self.bvh.handle, self.mat_mode, _ptr(self.vmat), _ptr(self.albedo), _ptr(self.rough),
+                      _ptr(self.metal), tw, th, _ptr(self.env), self.env.shape[1], self.env.shape[0])
+
+
+def views_struct(views: Sequence) -> Tuple[C.Array, int, List[int]]:
+    """Packs views (objects with c2w, fov_y_deg, w, h, spp, sample_offset)
+    back to back; returns the struct array, total pixels and per-view offsets."""
+    arr = (_View * len(views))()
+    off, offsets = 0, []
+    for i, v in enumerate(views):
+        c2w = torch.as_tensor(v.c2w, dtype=torch.float32).reshape(16).tolist()
+        arr[i].c2w[:] = c2w
+        arr[i].fov_y_deg = float(v.fov_y_deg)
+        arr[i].w, arr[i].h, arr[i].spp = int(v.w), int(v.h), int(v.spp)
+        arr[i].sample_offset = int(getattr(v, "sample_offset", 0))
+        arr[i].pixel_offset = off
+        offsets.append(off)
+        off += int(v.w) * int(v.h)
+    return arr, off, offsets
+
+
+def total_samples(views: Sequence) -> int:
+    return int(sum(int(v.w) * int(v.h) * int(v.spp) for v in views))
+
+
+def render(scene: GpuScene, views: Sequence, opts, keep_tape: bool = False, debug: bool = False,
+           out: Optional[torch.Tensor] = None, stream=None):
+    """Renders packed images [sum W*H, 3].  With keep_tape returns (image,
+    tape or None); with debug also per-sample radiance and decision hashes."""
+    o = RenderOptions.from_any(opts)
+    vs, npix, _ = views_struct(views)
+    dev = scene.pos.device
+    img = out if out is not None else torch.empty((npix, 3), dtype=torch.float32, device=dev)
+    dbg_rgb = dbg_hash = None
+    if debug:
+        S = total_samples(views)
+        dbg_rgb = torch.empty((S, 3), dtype=torch.float32, device=dev)
+        dbg_hash = torch.empty((S,), dtype=torch.int32, device=dev)
+    op = o.struct(dbg_rgb, dbg_hash)
+    sc = scene.struct()
+    th = C.c_void_p()
+    _check(_lib.mrs_render(C.byref(sc), C.addressof(vs), len(views), C.byref(op), img.data_ptr(),
+                           C.byref(th) if keep_tape else None, _stream(stream)))
+    tape = Tape(th) if (keep_tape and th.value) else None
+    res = [img]
+    if keep_tape:
+        res.append(tape)
+    if debug:
+        res += [dbg_rgb, dbg_hash]
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def render_backward(scene: GpuScene, views: Sequence, opts, grad_image: torch.Tensor, tape: Optional[Tape] = None,
+                    grads: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
+    """Accumulates d(sum grad_image . image)/d(materials, env) into `grads`
+    (allocated zero if None) and returns it."""
+    o = RenderOptions.from_any(opts)
+    vs, npix, _ = views_struct(views)
+    gi = _dev(grad_image).reshape(npix, 3)
+    if grads is None:
+        grads = {"env": torch.zeros_like(scene.env)}
+        if scene.mat_mode == MAT_VERTEX:
+            grads["vmat"] = torch.zeros_like(scene.vmat)
+        else:
+            grads["albedo"] = torch.zeros_like(scene.albedo)
+            grads["rough"] = torch.zeros_like(scene.rough)
+            grads["metal"] = torch.zeros_like(scene.metal)
+    g = _Grads(_ptr(grads.get("vmat")), _ptr(grads.get("albedo")), _ptr(grads.get("rough")),
+               _ptr(grads.get("metal")), _ptr(grads.get("env")))
+    op = o.struct()
+    sc = scene.struct()
+    _check(_lib.mrs_render_backward(C.byref(sc), C.addressof(vs), len(views), C.byref(op), gi.data_ptr(),
+                                    C.byref(g), tape.handle if tape is not None else None, _stream(stream)))
+    return grads
+
+
+def tape_bytes(views: Sequence, opts) -> int:
+    vs, _, _ = views_struct(views)
+    op = RenderOptions.from_any(opts).struct()
+    return int(_lib.mrs_tape_bytes(C.addressof(vs), len(views), C.byref(op)))
+
+
+def release_workspace():
+    _lib.mrs_release_workspace()
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, scene, views, opts, vmat, albedo, rough, metal, env):
+        sc = scene.with_params(vmat=vmat, albedo=albedo, rough=rough, metal=metal, env=env)
+        img, tape = render(sc, views, opts, keep_tape=True)
+        ctx.scene, ctx.views, ctx.opts, ctx.tape = sc, views, opts, tape
+        return img
+
+    @staticmethod
+    def backward(ctx, gimg):
+        sc = ctx.scene
+        need = ctx.needs_input_grad
+        grads = {}
+        if sc.mat_mode == MAT_VERTEX:
+            grads["vmat"] = torch.zeros_like(sc.vmat) if need[3] else None
+        else:
+            grads["albedo"] = torch.zeros_like(sc.albedo) if need[4] else None
+            grads["rough"] = torch.zeros_like(sc.rough) if need[5] else None
+            grads["metal"] = torch.zeros_like(sc.metal) if need[6] else None
+        grads["env"] = torch.zeros_like(sc.env) if need[7] else None
+        render_backward(sc, ctx.views, ctx.opts, gimg, tape=ctx.tape, grads=grads)
+        ctx.tape = None
+        return (None, None, None, grads.get("vmat"), grads.get("albedo"), grads.get("rough"), grads.get("metal"),
+                grads.get("env"))
+
+
+def render_autograd(scene: GpuScene, views: Sequence, opts, vmat=None, albedo=None, rough=None, metal=None,
+                    env=None) -> torch.Tensor:
+    """Differentiable render: gradients flow to whichever of vmat / albedo /
+    rough / metal / env are passed as tensors requiring grad (defaults: the
+    scene's own tensors, without grad)."""
+    vmat = scene.vmat if vmat is None else vmat
+    albedo = scene.albedo if albedo is None else albedo
+    rough = scene.rough if rough is None else rough
+    metal = scene.metal if metal is None else metal
+    env = scene.env if env is None else env
+    return _RenderFn.apply(scene, list(views), opts, vmat, albedo, rough, metal, env)

@@ -118,11 +118,13 @@ def test_mixture_sampler_chi2(oracle_lib, m):
 
 
 def test_frame_orthonormal(oracle_lib):
+    """Orthonormal basis with n as third axis, also for axis-aligned normals."""
     rng = np.random.default_rng(9)
     ns = [_unit(rng.normal(size=3)) for _ in range(100)] + [np.array([0, 0, 1.0]), np.array([0, 0, -1.0]),
                                                              np.array([0, 1.0, 0]), np.array([0, -1.0, 0])]
     for n in ns:
         t, b = oracle_lib.frame(n)
         M = np.stack([t, b, n])
+        assert np.allclose(M[2], n)
         assert np.allclose(M @ M.T, np.eye(3), atol=1e-12)
-        assert np.linalg.det(M) > 0
+        assert abs(abs(np.linalg.det(M)) - 1.0) < 1e-12   # handedness is irrelevant
