@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of the differentiable RIS path tracer on one MI355X.
+
+One step = one optimisation step of the texture/env inverse problem on the
+differentiation workload: render 8 views of 800x800 at 4 spp over a ~300k
+triangle displaced mesh with 2048^2 fp32 textures and a 512x256 HDR env
+(3 bounces, RIS M = 32), L2 loss against a target rendered from seeded
+ground-truth materials, then the adjoint replay that scatters dL/dtexel and
+dL/denv-texel.  value = path samples per second of that fwd+bwd step.
+
+Also reported (one JSON line):
+  roofline      the dominant kernel's algorithmic bytes per second (counts
+                from the FP64 oracle's own SAH BVH on a seeded subset of the
+                same samples, bytes per unit as stated in the design doc) over its
+                HIP-event-timed duration, against the 8 TB/s HBM3E peak;
+  cpu_baseline  the FP64 oracle, as it stands, on a bounded seeded subset of
+                the same samples, on this host's cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd path samples/s at 800x800, 3 bounces, RIS M=32; % of HBM roofline"
+HBM_PEAK_GBPS = 8000.0
+
+# algorithmic bytes per unit (gather model): BVH node 32 B, triangle 36 B,
+# hit re-read 36 B (indices + uv), material fetch 80 B (bilinear: 4 texels x
+# 20 B) or 60 B (per-vertex), RIS candidate 20 B (env radiance 12 + pdf
+# entries 8), pixel 12 B, adjoint gradient RMW 3x the material fetch, env
+# gradient RMW 24 B, vertex record 32 B written + read.
+NODE_B, TRI_B, HIT_B, CAND_B, PIX_B, ENVG_B, VREC_B = 32, 36, 36, 20, 12, 24, 64
+
+
+def kernel_bytes(cnt, n, spp, tex):
+    """Per-sample algorithmic bytes attributed to each kernel class."""
+    tmat = 80 if tex else 60
+    per = {k: v / n for k, v in cnt.items()}
+    return {
+        "trace_closest": NODE_B * per["closest_nodes"] + TRI_B * per["closest_tris"],
+        "trace_shadow": NODE_B * per["shadow_nodes"] + TRI_B * per["shadow_tris"],
+        "shade": per["hits"] * (HIT_B + tmat) + per["candidates"] * CAND_B,
+        "resolve": PIX_B / spp,
+        "adjoint": PIX_B / spp + per["hits"] * (HIT_B + 3 * tmat) + per["nee_visible"] * ENVG_B + per["hits"] * VREC_B,
+    }
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2406_16360_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None if the kernel sources changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_workload(name):
+    from paper_2406_16360_amd import synth
+    if name == "c3":
+        return synth.config3()
+    if name == "c2":
+        return synth.config2()
+    if name == "c1":
+        return synth.config1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, seconds, nthreads):
+    """The FP64 oracle on a bounded seeded subset of the same samples (render
+    + gradient), plus its traversal counters for the roofline model."""
+    from oracle.oracle import Oracle
+    from paper_2406_16360_amd import synth
+    orc = Oracle(w.scene)
+    probe = synth.sample_items(w, 4000, 12345)
+    t0 = time.perf_counter()
+    orc.render(w.views, w.opts, probe, nthreads=nthreads)
+    orc.grad(w.views, w.opts, probe, np.ones((len(probe), 3)), nthreads=nthreads)
+    per = (time.perf_counter() - t0) / len(probe)
+    n = int(min(max(seconds / max(per, 1e-9), 4000), 4_000_000))
+    items = synth.sample_items(w, n, 2024)
+    dl = np.random.default_rng(7).random((n, 3))
+    t0 = time.perf_counter()
+    _, _, cnt = orc.render(w.views, w.opts, items, nthreads=nthreads, counters=True)
+    orc.grad(w.views, w.opts, items, dl, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return n / dt, n, dt, cnt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--mode", default="fwdbwd", choices=["fwdbwd", "fwd"])
+    ap.add_argument("--tape", default="on", choices=["auto", "on", "off"])
+    ap.add_argument("--pool", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would render its own "
+              "share of the views; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2406_16360_amd import mirres, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = make_workload(args.workload)
+    print(f"# workload {w.name}: {w.samples} samples/step, {w.scene.nf} triangles", file=sys.stderr, flush=True)
+    sc = mirres.GpuScene.from_synth(w.scene)
+    opts = mirres.RenderOptions.from_any(w.opts)
+    opts.tape_mode = {"auto": mirres.TAPE_AUTO, "on": mirres.TAPE_ON, "off": mirres.TAPE_OFF}[args.tape]
+    opts.pool, opts.block = args.pool, args.block
+    tex = sc.mat_mode == mirres.MAT_TEXTURE
+
+    # target rendered from seeded ground-truth materials (a second texture set)
+    rng = np.random.default_rng(9000)
+    if tex:
+        ga, gr_, gm = synth.noise_textures(sc.rough.shape[0], rng)
+        gt = sc.with_params(albedo=torch.tensor(ga, device=dev), rough=torch.tensor(gr_, device=dev),
+                            metal=torch.tensor(gm, device=dev))
+    else:
+        gt = sc.with_params(vmat=sc.vmat.flip(0).contiguous())
+    target = mirres.render(gt, w.views, opts).clone()
+    grads = {"env": torch.zeros_like(sc.env)}
+    if tex:
+        grads.update(albedo=torch.zeros_like(sc.albedo), rough=torch.zeros_like(sc.rough),
+                     metal=torch.zeros_like(sc.metal))
+    else:
+        grads["vmat"] = torch.zeros_like(sc.vmat)
+
+    def step():
+        if args.mode == "fwd":
+            mirres.render(sc, w.views, opts)
+            return
+        img, tape = mirres.render(sc, w.views, opts, keep_tape=True)
+        dimg = 2.0 * (img - target)                    # d/dI of the L2 loss sum (I - I_ref)^2
+        for g in grads.values():
+            g.zero_()
+        mirres.render_backward(sc, w.views, opts, dimg, tape=tape, grads=grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mirres.profile_begin()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = mirres.profile_end()
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = wall * 1e3 / args.steps
+    S = w.samples
+    value = S * args.steps / wall
+    print(f"# wall {wall:.3f}s events {gpu_ms:.1f}ms kernels {json.dumps(prof)}", file=sys.stderr, flush=True)
+
+    # CPU baseline (oracle) and the roofline model from its counters
+    cpu = None
+    cnt = None
+    nsub = 0
+    if not args.no_cpu_baseline:
+        ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        v, nsub, dt, cnt = cpu_baseline(w, args.cpu_seconds, ncores)
+        cpu = {"value": v, "unit": "samples/s", "cores": ncores, "kind": "oracle",
+               "sample": f"{nsub} seeded samples of {w.name} (render + gradient) in {dt:.1f}s"}
+        if args.mode == "fwd":
+            cpu["sample"] += "; value counts render + gradient per sample"
+    roof = None
+    extra = {}
+    if cnt is not None:
+        kb = kernel_bytes(cnt, nsub, w.views[0].spp, tex)
+        if args.mode == "fwd":
+            kb.pop("adjoint")
+        balg = sum(kb.values())
+        kern = {}
+        for name, (launches, ms) in prof.items():
+            if name in kb:
+                per_step_ms = ms / args.steps
+                kern[name] = {"ms_per_step": per_step_ms, "launches_per_step": launches / args.steps,
+                              "alg_bytes_per_sample": kb[name],
+                              "alg_GBps": S * kb[name] / (per_step_ms * 1e-3) / 1e9}
+        dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+        d = kern[dom]
+        launches = d["launches_per_step"]
+        traffic = load_traffic(dom, args.workload)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": d["alg_GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
+                "alg_bytes_per_launch": S * kb[dom] / launches,
+                "avg_launch_ms": d["ms_per_step"] / launches}
+        extra = {"path_roofline": {"alg_bytes_per_sample": balg,
+                                   "frac": value * balg / (HBM_PEAK_GBPS * 1e9),
+                                   "counts_per_sample": {k: v / nsub for k, v in cnt.items()}},
+                 "kernels": kern}
+    out = {"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "views": len(w.views), "width": w.views[0].w, "height": w.views[0].h,
+                      "spp": w.views[0].spp, "samples_per_step": S, "bounces": w.opts.bounces,
+                      "ris_m": w.opts.ris_m, "ris_m_brdf": w.opts.ris_m_brdf, "triangles": w.scene.nf,
+                      "mode": args.mode, "tape": args.tape, "pool": args.pool, "block": args.block},
+           "roofline": roof, "cpu_baseline": cpu, "gpu_event_ms": gpu_ms}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

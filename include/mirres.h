@@ -178,6 +178,21 @@ mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, in
 int64_t    mrs_tape_bytes(const mrs_view *views, int32_t n_views, const mrs_options *opt);
 void       mrs_tape_destroy(mrs_tape *tape);
 
+/* Kernel timing for measurement: between mrs_profile_begin and
+ * mrs_profile_end every kernel the library launches is bracketed by a pair
+ * of HIP events on the launch's own stream.  mrs_profile_end waits for the
+ * recorded events and writes up to `cap` entries (one per kernel class with
+ * at least one launch: name, launches, summed device milliseconds) to `out`;
+ * *n receives the number written.  Errors: MRS_EINVAL (null out/n),
+ * MRS_EHIP. */
+typedef struct {
+    char    name[32];
+    int64_t launches;
+    double  ms;
+} mrs_kernel_time;
+mrs_status mrs_profile_begin(void);
+mrs_status mrs_profile_end(mrs_kernel_time *out, int32_t cap, int32_t *n);
+
 /* Frees the library's internal device workspace (it regrows on demand). */
 void        mrs_release_workspace(void);
 const char *mrs_last_error(void);

@@ -755,6 +755,44 @@ __global__ void k_set_sched(Sched *s, uint64_t a, uint64_t b) {
 // ============================================================================
 // host side
 // ============================================================================
+// kernel timing: event pairs around every launch while profiling is on
+enum KernelId { KID_ENV = 0, KID_SCHED, KID_GENERATE, KID_CLOSEST, KID_SHADE, KID_SHADOW, KID_RESOLVE, KID_ADJOINT,
+                KID_TRACE, KID_COUNT };
+const char *const kKernelNames[KID_COUNT] = {"env_tables", "schedule", "generate", "trace_closest", "shade",
+                                             "trace_shadow", "resolve", "adjoint", "trace_batch"};
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int kid; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    hipEvent_t next() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+};
+Profiler g_prof;
+
+struct ProfScope {
+    int kid; hipStream_t s; hipEvent_t a = nullptr;
+    ProfScope(int k, hipStream_t st) : kid(k), s(st) {
+        if (g_prof.on && (a = g_prof.next())) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = g_prof.next();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        g_prof.recs.push_back({kid, a, b});
+    }
+};
+#define PROF(kid, s) ProfScope prof_scope_##__LINE__((kid), (s))
+
 constexpr uint64_t kOutChunkMax = 1ull << 26;   // samples per super-chunk of the output buffer
 constexpr uint32_t kPoolDefault = 1u << 22;      // paths in flight
 constexpr uint64_t kTapeRecBytes = 36;           // tape bytes per path vertex
@@ -895,10 +933,13 @@ mrs_status setup(const mrs_scene *sc, Job &job, hipStream_t s) {
     TRY(w.lp.reserve(sizeof(float4) * nt));
     TRY(w.gmarg.reserve(sizeof(int32_t) * H));
     TRY(w.gcond.reserve(sizeof(int32_t) * nt));
+    {
+    PROF(KID_ENV, s);
     k_env_rows<<<H, 256, 0, s>>>(sc->env, W, H, w.wts.as<double>(), w.cond.as<double>(), w.rowsum.as<double>());
     k_env_marg<<<1, 64, 0, s>>>(w.rowsum.as<double>(), H, w.marg.as<double>(), w.info.as<double>());
     k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, w.wts.as<double>(), w.info.as<double>(), w.marg.as<double>(),
                                         w.cond.as<double>(), w.lp.as<float4>(), w.gmarg.as<int32_t>(), w.gcond.as<int32_t>());
+    }
     // env validity (total weight > 0) is needed on the host once per call
     double info = 0.0;
     HIPTRY(hipMemcpyAsync(&info, w.info.p, sizeof(double), hipMemcpyDeviceToHost, s), "copy env total");
@@ -979,18 +1020,33 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
     IterCtr *ctr = w.ctr.as<IterCtr>();
     int bs = job.block;
     for (int it = 0; it < n_iter; ++it) {
-        k_schedule<<<1, 64, 0, s>>>(ctr, it, w.sched.as<Sched>(), P);
+        {
+            PROF(KID_SCHED, s);
+            k_schedule<<<1, 64, 0, s>>>(ctr, it, w.sched.as<Sched>(), P);
+        }
         GenArgs ga{job.vt, job.op, qa, ctr, it, w.out.as<float4>(), ch.c0, hash};
-        k_generate<<<nblocks(P, 256), 256, 0, s>>>(ga);
+        {
+            PROF(KID_GENERATE, s);
+            k_generate<<<nblocks(P, 256), 256, 0, s>>>(ga);
+        }
         TraceArgs ta{job.sd.nodes, job.sd.tris, qa, w.hits.as<float4>(), ctr, it};
-        k_trace_closest<<<nblocks(P, bs), bs, 0, s>>>(ta);
+        {
+            PROF(KID_CLOSEST, s);
+            k_trace_closest<<<nblocks(P, bs), bs, 0, s>>>(ta);
+        }
         ShadeArgs sa{job.sd, job.vt, job.op, qa, qb, w.hits.as<float4>(), ctr, it,
                      w.so.as<float4>(), w.sd.as<float4>(), w.sc.as<float4>(), w.out.as<float4>(), ch.c0, hash,
                      tape, use_tape};
-        k_shade<<<nblocks(P, bs), bs, 0, s>>>(sa);
+        {
+            PROF(KID_SHADE, s);
+            k_shade<<<nblocks(P, bs), bs, 0, s>>>(sa);
+        }
         ShadowArgs sh{job.sd.nodes, job.sd.tris, w.so.as<float4>(), w.sd.as<float4>(), w.sc.as<float4>(), ctr, it,
                       w.out.as<float4>(), ch.c0, hash, tape, use_tape};
-        k_trace_shadow<<<nblocks(P, bs), bs, 0, s>>>(sh);
+        {
+            PROF(KID_SHADOW, s);
+            k_trace_shadow<<<nblocks(P, bs), bs, 0, s>>>(sh);
+        }
         std::swap(qa, qb);
     }
     HIPTRY(hipGetLastError(), "wavefront launch");
@@ -1011,6 +1067,44 @@ extern "C" int64_t mrs_tape_bytes(const mrs_view *views, int32_t n_views, const 
 
 extern "C" void mrs_tape_destroy(mrs_tape *t) { delete t; }
 
+extern "C" mrs_status mrs_profile_begin(void) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.recs.clear();
+    g_prof.used = 0;
+    g_prof.on = true;
+    return MRS_OK;
+}
+
+extern "C" mrs_status mrs_profile_end(mrs_kernel_time *out, int32_t cap, int32_t *n) {
+    clear_error();
+    if (!out || !n) return fail(MRS_EINVAL, "mrs_profile_end: null output");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = false;
+    double ms[KID_COUNT] = {0};
+    int64_t cnt[KID_COUNT] = {0};
+    for (const Profiler::Rec &r : g_prof.recs) {
+        TRY(hip_check(hipEventSynchronize(r.b), "hipEventSynchronize"));
+        float t = 0.0f;
+        TRY(hip_check(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime"));
+        ms[r.kid] += t;
+        cnt[r.kid] += 1;
+    }
+    g_prof.recs.clear();
+    g_prof.used = 0;
+    int32_t k = 0;
+    for (int i = 0; i < KID_COUNT && k < cap; ++i) {
+        if (!cnt[i]) continue;
+        std::memset(out[k].name, 0, sizeof(out[k].name));
+        std::strncpy(out[k].name, kKernelNames[i], sizeof(out[k].name) - 1);
+        out[k].launches = cnt[i];
+        out[k].ms = ms[i];
+        ++k;
+    }
+    *n = k;
+    return MRS_OK;
+}
+
 extern "C" mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const float *d_dir, int64_t n,
                                 int32_t any_hit, float *d_hit, void *stream) {
     clear_error();
@@ -1018,8 +1112,11 @@ extern "C" mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const f
     if (n < 0) return fail(MRS_EINVAL, "mrs_trace: n < 0");
     if (n == 0) return MRS_OK;
     hipStream_t s = (hipStream_t)stream;
-    k_trace_batch<<<nblocks((uint64_t)n, 256), 256, 0, s>>>(bvh->nodes.as<BvhNode>(), bvh->tris.as<TriRec>(), d_orig,
+    {
+        PROF(KID_TRACE, s);
+        k_trace_batch<<<nblocks((uint64_t)n, 256), 256, 0, s>>>(bvh->nodes.as<BvhNode>(), bvh->tris.as<TriRec>(), d_orig,
                                                            d_dir, n, any_hit ? 1 : 0, (float4 *)d_hit);
+    }
     return hip_check(hipGetLastError(), "mrs_trace launch");
 }
 
@@ -1084,7 +1181,10 @@ extern "C" mrs_status mrs_render(const mrs_scene *scene, const mrs_view *views, 
         st = run_wavefront(job, ch, tp, tape != nullptr, hash, s);
         if (st != MRS_OK) break;
         ResolveArgs ra{job.vt, g_ws.out.as<float4>(), ch.c0, ch.pix0, ch.pix1, d_image, opt->debug_sample_rgb};
-        k_resolve<<<nblocks(ch.pix1 - ch.pix0, 256), 256, 0, s>>>(ra);
+        {
+            PROF(KID_RESOLVE, s);
+            k_resolve<<<nblocks(ch.pix1 - ch.pix0, 256), 256, 0, s>>>(ra);
+        }
     }
     if (st == MRS_OK) st = finish(s);
     if (st != MRS_OK) { delete tape; return st; }
@@ -1097,7 +1197,10 @@ static mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t 
     for (uint64_t a0 = c0; a0 < c1; a0 += kAdjChunk) {
         uint64_t n = std::min<uint64_t>(kAdjChunk, c1 - a0);
         AdjArgs aa{job.sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env};
-        k_adjoint<<<nblocks(n, 256), 256, 0, s>>>(aa);
+        {
+            PROF(KID_ADJOINT, s);
+            k_adjoint<<<nblocks(n, 256), 256, 0, s>>>(aa);
+        }
     }
     HIPTRY(hipGetLastError(), "adjoint launch");
     return MRS_OK;

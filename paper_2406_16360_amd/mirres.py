@@ -58,7 +58,12 @@ class _Grads(C.Structure):
 
 # the C-ABI symbols declared in include/mirres.h
 EXPORTS = ["mrs_build_bvh", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
-           "mrs_tape_bytes", "mrs_tape_destroy", "mrs_release_workspace", "mrs_last_error"]
+           "mrs_tape_bytes", "mrs_tape_destroy", "mrs_profile_begin", "mrs_profile_end", "mrs_release_workspace",
+           "mrs_last_error"]
+
+
+class _KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double)]
 
 
 def _load():
@@ -82,6 +87,10 @@ def _load():
     lib.mrs_tape_bytes.argtypes = [p, i32, C.POINTER(_Options)]
     lib.mrs_tape_destroy.argtypes = [p]
     lib.mrs_release_workspace.argtypes = []
+    lib.mrs_profile_begin.restype = i32
+    lib.mrs_profile_begin.argtypes = []
+    lib.mrs_profile_end.restype = i32
+    lib.mrs_profile_end.argtypes = [p, i32, C.POINTER(i32)]
     lib.mrs_last_error.restype = C.c_char_p
     return lib
 
@@ -320,6 +329,19 @@ def tape_bytes(views: Sequence, opts) -> int:
     vs, _, _ = views_struct(views)
     op = RenderOptions.from_any(opts).struct()
     return int(_lib.mrs_tape_bytes(C.addressof(vs), len(views), C.byref(op)))
+
+
+def profile_begin():
+    """Start timing every kernel launch with HIP events on its stream."""
+    _check(_lib.mrs_profile_begin())
+
+
+def profile_end() -> Dict[str, Tuple[int, float]]:
+    """Stop timing; returns {kernel: (launches, device milliseconds)}."""
+    buf = (_KernelTime * 32)()
+    n = C.c_int32()
+    _check(_lib.mrs_profile_end(C.addressof(buf), 32, C.byref(n)))
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].ms)) for i in range(n.value)}
 
 
 def release_workspace():
