@@ -174,6 +174,36 @@ mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, in
                                const mrs_options *opt, const float *d_grad_image,
                                const mrs_grads *grads, const mrs_tape *tape, void *stream);
 
+/* Plans: a render (and optionally its adjoint) for fixed views, options and
+ * bound device arrays, with every buffer the passes need allocated by the
+ * plan at creation (pool, output, env tables, tape or recompute chunk tape).
+ * Many views of uneven size and spp share one persistent wavefront pool that
+ * is refilled from a global sample counter.  With use_graph the launch
+ * sequence of each pass is captured once into a hipGraph (on a stream the
+ * plan owns) and every later call replays it on `stream`.
+ *   - The arrays bound at creation (scene arrays, d_image, d_grad_image,
+ *     grads, debug outputs in opt) must stay allocated at the same addresses
+ *     while the plan lives; their CONTENTS may change between calls (an
+ *     optimiser updating textures and env in place is the intended use).
+ *   - mrs_plan_backward accumulates into grads (the caller zeroes them) using
+ *     the tape of the latest mrs_plan_forward when the plan keeps one
+ *     (tape_mode / tape_budget as for mrs_render), else re-renders.
+ *   - Calls on one plan must not overlap: issue them on one stream or
+ *     synchronise in between.  Plans never share buffers with each other or
+ *     with the eager calls.
+ * Errors: MRS_EINVAL (as mrs_render; grads and d_grad_image must be both set
+ * or both NULL; backward on a plan without grads), MRS_ENOMEM, MRS_EHIP. */
+typedef struct mrs_plan mrs_plan;   /* opaque, library-owned */
+mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *views, int32_t n_views, const mrs_options *opt,
+                           float *d_image, const float *d_grad_image, const mrs_grads *grads, int32_t use_graph,
+                           mrs_plan **out);
+mrs_status mrs_plan_forward(mrs_plan *plan, void *stream);
+mrs_status mrs_plan_backward(mrs_plan *plan, void *stream);
+/* samples per pass, whether the plan keeps a tape, whether it replays graphs */
+mrs_status mrs_plan_info(const mrs_plan *plan, int64_t *samples, int32_t *keeps_tape, int32_t *graph);
+/* waits for the device, then frees the plan and its buffers */
+void       mrs_plan_destroy(mrs_plan *plan);
+
 /* Bytes a tape for these views/options would take (host arithmetic). */
 int64_t    mrs_tape_bytes(const mrs_view *views, int32_t n_views, const mrs_options *opt);
 void       mrs_tape_destroy(mrs_tape *tape);

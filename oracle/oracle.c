@@ -127,6 +127,11 @@ static uint32_t ev_vertex(uint32_t k, uint32_t prim, uint32_t sel, uint32_t code
     return fnv_word(fnv_word(fnv_word(fnv_word(FNV_BASIS, k), prim), sel), code);
 }
 static uint32_t ev_nee(uint32_t k, uint32_t vis) { return fnv_word(fnv_word(FNV_BASIS, k | 0x10000u), vis); }
+/*   BRDF candidate s of vertex k fnv(k | 0x20000, s, lobe, env texel of its direction)
+ * (the continuation code distinguishes lobes: 1 diffuse, 4 specular) */
+static uint32_t ev_cand(uint32_t k, uint32_t s, uint32_t lobe, uint32_t tex) {
+    return fnv_word(fnv_word(fnv_word(fnv_word(FNV_BASIS, k | 0x20000u), s), lobe), tex);
+}
 
 /* ------------------------------------------------------------------ */
 /* context                                                             */
@@ -821,11 +826,13 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
                     ok = env_sample(c, u[0], u[1], w, &qe, &tex);
                     if (ok) qb = mix_pdf(V->n, V->wo, w, m, spec);
                 } else {
-                    ok = mix_sample(V->n, tf, bf, V->wo, m, spec, u[0], u[1], u[2], w) != 0;
+                    int lb = mix_sample(V->n, tf, bf, V->wo, m, spec, u[0], u[1], u[2], w);
+                    ok = lb != 0;
                     if (ok) {
                         qb = mix_pdf(V->n, V->wo, w, m, spec);
                         qe = env_pdf_dir(c, w);
                         tex = env_texel_of(c, w);
+                        h ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
                     }
                 }
                 if (!ok) continue;
@@ -876,7 +883,7 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
             for (int ch = 0; ch < 3; ++ch) T[ch] /= qr;
             V->rr = 1.0 / qr;
         }
-        h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 1u);
+        h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, lobe == 2 ? 4u : 1u);
         for (int a = 0; a < 3; ++a) { o[a] = org[a]; d[a] = wi[a]; }
     }
     *hash = h;

@@ -1,0 +1,96 @@
+"""Autotuner for the persistent wavefront launch.
+
+Searches the path-pool size (paths in flight) and the workgroup size of the
+trace and shade kernels for a given scene, view set and options, timing
+graph replays of a plan's forward pass with HIP events (median of `reps`).
+Results are cached in a JSON file keyed by the device name and a signature
+of the workload (samples, views, bounces, candidates, triangles, material
+mode), so a repeated optimisation loop pays the search once.
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import mirres
+
+DEFAULT_POOLS = (1 << 20, 1 << 21, 1 << 22, 1 << 23)
+DEFAULT_BLOCKS = (64, 128, 256)
+
+
+def _cache_path() -> str:
+    base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(base, "paper_2406_16360_amd", "autotune.json")
+
+
+def workload_key(scene: mirres.GpuScene, views: Sequence, opts) -> str:
+    o = mirres.RenderOptions.from_any(opts)
+    S = mirres.total_samples(views)
+    dev = torch.cuda.get_device_name(scene.pos.device)
+    return (f"{dev}|S={S}|views={len(views)}|B={o.bounces}|M={o.ris_m}|Mb={o.ris_m_brdf}|rr={o.rr_start}"
+            f"|nf={scene.faces.shape[0]}|mat={scene.mat_mode}")
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time_forward(plan: mirres.Plan, reps: int) -> float:
+    plan.forward()                      # capture + first replay
+    torch.cuda.synchronize()
+    times = []
+    stream = torch.cuda.current_stream()
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.forward()
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return statistics.median(times)
+
+
+def autotune(scene: mirres.GpuScene, views: Sequence, opts, pools: Sequence[int] = DEFAULT_POOLS,
+             blocks: Sequence[int] = DEFAULT_BLOCKS, reps: int = 3, use_graph: bool = True,
+             cache: Optional[str] = "default", verbose: bool = False) -> Dict:
+    """Returns {"pool": P, "block": b, "ms": t, "table": [...]} for the fastest
+    forward pass; the caller copies pool/block into its RenderOptions."""
+    key = workload_key(scene, views, opts)
+    path = _cache_path() if cache == "default" else cache
+    if path:
+        hit = _load(path).get(key)
+        if hit:
+            return hit
+    S = mirres.total_samples(views)
+    base = mirres.RenderOptions.from_any(opts)
+    table = []
+    for pool in pools:
+        if pool > 2 * S and pool != min(pools):
+            continue
+        for block in blocks:
+            o = mirres.RenderOptions(**{**base.__dict__, "pool": int(pool), "block": int(block)})
+            plan = mirres.Plan(scene, views, o, use_graph=use_graph)
+            ms = _time_forward(plan, reps)
+            del plan
+            table.append({"pool": int(pool), "block": int(block), "ms": ms})
+            if verbose:
+                print(f"autotune pool={pool} block={block}: {ms:.3f} ms", flush=True)
+    best = min(table, key=lambda r: r["ms"])
+    res = {"pool": best["pool"], "block": best["block"], "ms": best["ms"], "table": table}
+    if path:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        data = _load(path)
+        data[key] = res
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1)
+        os.replace(tmp, path)
+    return res

@@ -261,7 +261,7 @@ struct EnvTables {
     const float4 *lp;       // [H][W] (L_r, L_g, L_b clamped >= 0, pdf_uv / (2 pi^2))
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
-    int valid;              // total weight > 0
+    const double *total;    // device: total sampling weight (no valid sample when 0)
 };
 
 __device__ __forceinline__ int env_texel_of(const EnvTables &e, V3 d) {
@@ -276,7 +276,7 @@ __device__ __forceinline__ int env_texel_of(const EnvTables &e, V3 d) {
 
 // solid-angle pdf of the env sampler at direction d, with its texel radiance
 __device__ __forceinline__ float env_pdf_dir(const EnvTables &e, V3 d, int texel, float4 lp) {
-    if (!e.valid) return 0.0f;
+    if (!(*e.total > 0.0)) return 0.0f;
     float st = sqrtf(fmaxf(0.0f, 1.0f - d.y * d.y));
     return st > 0.0f ? lp.w / st : 0.0f;
 }
@@ -295,7 +295,7 @@ __device__ __forceinline__ int cdf_walk(const double *cdf, int start, int n, dou
 // linear remainder inside the texel), in double like the tables.
 __device__ __forceinline__ bool env_sample(const EnvTables &e, float u0f, float u1f, V3 &dir, int &texel,
                                            float4 &lp, float &pdf) {
-    if (!e.valid) return false;
+    if (!(*e.total > 0.0)) return false;
     double u0 = u0f, u1 = u1f;
     int gi = min((int)(u0 * e.H), e.H - 1);
     int i = cdf_walk(e.marg, e.gmarg[gi], e.H, u0);

@@ -1,23 +1,7 @@
-// Wavefront path tracer with RIS direct lighting and its adjoint, for gfx950.
-//
-// Forward (per super-chunk of samples, one persistent pool of P paths):
-//   iterate: schedule (refill the pool from a global sample counter) ->
-//            generate (camera rays for the new paths) ->
-//            closest hit (SoA ray queue -> hit queue) ->
-//            shade (surface interaction, material fetch, M-candidate RIS with a
-//                   streaming weighted reservoir, shadow-ray emission,
-//                   BRDF-mixture continuation, Russian roulette, wave-level
-//                   ballot/prefix-sum compaction into the next queue) ->
-//            shadow (any hit; unoccluded NEE added to the sample's radiance)
-//   then resolve the per-sample radiance into per-pixel means.
-// Backward: one thread per sample replays the path from the per-vertex tape
-// (written by the forward pass, or regenerated chunk by chunk), sweeps the
-// vertices in reverse and scatters material and env-texel gradients with
-// global float atomics.
-//
-// Paper: Sec. 3 Eqs. pbr_render / incident, Sec. 4.1 Eq. restir with the
-// reservoir rule of Appendix A, Sec. 4.2 Eqs. mc_indir / sec_bouce, and
-// Appendix A "Visibility estimation".
+// Host side of libmirres: argument validation, buffer management, the
+// launch sequence of the wavefront path tracer and of its adjoint, the
+// eager C-ABI entry points and the plan API (buffers owned per plan, launch
+// sequence captured once in a hipGraph and replayed).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +15,7 @@
 
 #include "device.h"
 #include "runtime.h"
-#include "trace.h"
+#include "wavefront.h"
 
 // ============================================================================
 // error state
@@ -60,706 +44,18 @@ extern "C" const char *mrs_last_error(void) { return mrs::g_err.c_str(); }
 namespace mrs {
 namespace {
 
-// ============================================================================
-// device-side argument bundles
-// ============================================================================
-struct IterCtr {
-    uint32_t n_in;       // continuing paths entering the iteration
-    uint32_t n_new;      // camera paths generated in the iteration
-    uint32_t n_live;     // n_in + n_new
-    uint32_t n_shadow;   // shadow rays emitted by the iteration's shade
-    uint64_t gen_base;   // first sample index generated in the iteration
-};
-struct Sched { uint64_t next, end; };
-
-struct SceneDev {
-    const int32_t *faces;
-    const float *uv, *vmat, *albedo, *rough, *metal;
-    int mat_mode, tw, th;
-    const BvhNode *nodes;
-    const TriRec *tris;
-    EnvTables env;
-};
-
-struct Opts {
-    int B, M, Mb, rr_start, spec, background, grad_mode;
-    uint32_t k0, k1;
-};
-
-struct Queue { float4 *o, *d, *t; };   // o.w = sample id, d.w = vertex k, t = throughput
-
-struct Tape {
-    float4 *hit;   // [B][S]: (b1, b2, leaf, env texel)
-    float4 *y;     // [B][S]: (y, W when unoccluded else 0)
-    float *rr;     // [B][S]: continuation factor, 0 = path ended
-    uint64_t base; // sample index of entry 0
-    uint64_t S;    // samples per vertex slice
-};
-
-struct ViewTable {
-    const ViewDev *v;
-    int n;
-};
+#define TRY(x) do { mrs_status st_ = (x); if (st_ != MRS_OK) return st_; } while (0)
+#define HIPTRY(x, what) TRY(hip_check((x), what))
 
 // ============================================================================
-// small helpers
+// kernel timing: event pairs around every launch while profiling is on (not
+// while a launch sequence is being captured into a graph)
 // ============================================================================
-__device__ __forceinline__ int find_view(const ViewTable &vt, uint64_t g) {
-    int lo = 0, hi = vt.n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (vt.v[mid].sample_base <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-struct SampleId { int view; uint32_t pixel, sample; };
-__device__ __forceinline__ SampleId decode(const ViewTable &vt, uint64_t g) {
-    SampleId s;
-    s.view = find_view(vt, g);
-    const ViewDev &v = vt.v[s.view];
-    uint64_t local = g - v.sample_base;
-    s.pixel = (uint32_t)(local / (uint64_t)v.spp);
-    s.sample = v.sample_offset + (uint32_t)(local % (uint64_t)v.spp);
-    return s;
-}
-
-// pinhole camera ray in double, rounded once to float
-__device__ __forceinline__ void camera_ray(const ViewDev &v, uint32_t pixel, float u0, float u1, V3 &o, V3 &d) {
-    double x = (double)(pixel % (uint32_t)v.w), y = (double)(pixel / (uint32_t)v.w);
-    double nx = 2.0 * (x + (double)u0) / v.w - 1.0;
-    double ny = 1.0 - 2.0 * (y + (double)u1) / v.h;
-    double dc[3] = {nx * v.tan_half * v.aspect, ny * v.tan_half, -1.0};
-    double w[3];
-    for (int r = 0; r < 3; ++r)
-        w[r] = (double)v.rot[3 * r] * dc[0] + (double)v.rot[3 * r + 1] * dc[1] + (double)v.rot[3 * r + 2] * dc[2];
-    double l = 1.0 / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-    d = V3{(float)(w[0] * l), (float)(w[1] * l), (float)(w[2] * l)};
-    o = V3{v.org[0], v.org[1], v.org[2]};
-}
-
-struct Interp { int idx[4]; float w[4]; int n; };
-struct MatRaw { V3 a; float r, mu; };
-
-__device__ __forceinline__ int wrapi(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
-
-// affine interpolation: equal inputs give that value exactly, so a material
-// sitting on a clamp boundary stays on it (the clamp's derivative mask then
-// agrees with any other evaluation order)
-__device__ __forceinline__ float bary(float x0, float x1, float x2, float b1, float b2) {
-    return x0 + b1 * (x1 - x0) + b2 * (x2 - x0);
-}
-__device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f * (b - a); }
-__device__ __forceinline__ float bilerp(float x00, float x10, float x01, float x11, float fx, float fy) {
-    return lerpf(lerpf(x00, x10, fx), lerpf(x01, x11, fx), fy);
-}
-
-// material at a hit: per-vertex attributes by barycentrics, or bilinear
-// textures (texel centres at (i + 1/2) / W, wrap) at the interpolated uv.
-// ip receives the indices and the linear weights used by the adjoint.
-__device__ __forceinline__ MatRaw fetch_material(const SceneDev &s, int prim, float b1, float b2, Interp &ip) {
-    int v0 = s.faces[3 * prim], v1 = s.faces[3 * prim + 1], v2 = s.faces[3 * prim + 2];
-    MatRaw m;
-    if (s.mat_mode == MRS_MAT_VERTEX) {
-        ip.n = 3;
-        ip.idx[0] = v0; ip.idx[1] = v1; ip.idx[2] = v2; ip.idx[3] = v0;
-        ip.w[0] = 1.0f - b1 - b2; ip.w[1] = b1; ip.w[2] = b2; ip.w[3] = 0.0f;
-        const float *p0 = s.vmat + 5 * (size_t)v0, *p1 = s.vmat + 5 * (size_t)v1, *p2 = s.vmat + 5 * (size_t)v2;
-        m.a = V3{bary(p0[0], p1[0], p2[0], b1, b2), bary(p0[1], p1[1], p2[1], b1, b2), bary(p0[2], p1[2], p2[2], b1, b2)};
-        m.r = bary(p0[3], p1[3], p2[3], b1, b2);
-        m.mu = bary(p0[4], p1[4], p2[4], b1, b2);
-        return m;
-    }
-    float u = bary(s.uv[2 * v0], s.uv[2 * v1], s.uv[2 * v2], b1, b2);
-    float v = bary(s.uv[2 * v0 + 1], s.uv[2 * v1 + 1], s.uv[2 * v2 + 1], b1, b2);
-    float x = u * (float)s.tw - 0.5f, y = v * (float)s.th - 0.5f;
-    float x0 = floorf(x), y0 = floorf(y);
-    float fx = x - x0, fy = y - y0;
-    int i0 = wrapi((int)x0, s.tw), i1 = wrapi((int)x0 + 1, s.tw);
-    int j0 = wrapi((int)y0, s.th), j1 = wrapi((int)y0 + 1, s.th);
-    ip.n = 4;
-    ip.idx[0] = j0 * s.tw + i0; ip.w[0] = (1.0f - fx) * (1.0f - fy);
-    ip.idx[1] = j0 * s.tw + i1; ip.w[1] = fx * (1.0f - fy);
-    ip.idx[2] = j1 * s.tw + i0; ip.w[2] = (1.0f - fx) * fy;
-    ip.idx[3] = j1 * s.tw + i1; ip.w[3] = fx * fy;
-    const float *a0 = s.albedo + 3 * (size_t)ip.idx[0], *a1 = s.albedo + 3 * (size_t)ip.idx[1];
-    const float *a2 = s.albedo + 3 * (size_t)ip.idx[2], *a3 = s.albedo + 3 * (size_t)ip.idx[3];
-    m.a = V3{bilerp(a0[0], a1[0], a2[0], a3[0], fx, fy), bilerp(a0[1], a1[1], a2[1], a3[1], fx, fy),
-             bilerp(a0[2], a1[2], a2[2], a3[2], fx, fy)};
-    m.r = bilerp(s.rough[ip.idx[0]], s.rough[ip.idx[1]], s.rough[ip.idx[2]], s.rough[ip.idx[3]], fx, fy);
-    m.mu = bilerp(s.metal[ip.idx[0]], s.metal[ip.idx[1]], s.metal[ip.idx[2]], s.metal[ip.idx[3]], fx, fy);
-    return m;
-}
-
-__device__ __forceinline__ Mat clamp_material(const MatRaw &r) {
-    Mat m;
-    m.a = V3{fminf(fmaxf(r.a.x, 0.0f), 1.0f), fminf(fmaxf(r.a.y, 0.0f), 1.0f), fminf(fmaxf(r.a.z, 0.0f), 1.0f)};
-    m.r = fminf(fmaxf(r.r, kRoughMin), 1.0f);
-    m.mu = fminf(fmaxf(r.mu, 0.0f), 1.0f);
-    return m;
-}
-
-struct Surf { V3 p, n; Frame F; int prim; };
-__device__ __forceinline__ Surf surface(const SceneDev &s, int leaf, float b1, float b2, V3 d) {
-    TriRec tr = s.tris[leaf];
-    V3 a = xyz(tr.a), b = xyz(tr.b), c = xyz(tr.c);
-    Surf S;
-    S.prim = __float_as_int(tr.a.w);
-    float b0 = 1.0f - b1 - b2;
-    S.p = a * b0 + b * b1 + c * b2;
-    V3 ng = normalize(cross(b - a, c - a));
-    if (dot(ng, d) > 0.0f) ng = ng * -1.0f;
-    S.n = ng;
-    S.F = make_frame(ng);
-    return S;
-}
-
-__device__ __forceinline__ V3 spawn(V3 p, V3 n) {
-    float pn = fmaxf(fabsf(p.x), fmaxf(fabsf(p.y), fabsf(p.z)));
-    return p + n * (1e-4f * fmaxf(1.0f, pn));
-}
-
-// ballot / prefix-sum append: one atomic per wave
-__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
-    uint64_t mask = __ballot(pred);
-    if (mask == 0) return 0;
-    int lane = __lane_id();
-    int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    uint64_t below = lane == 0 ? 0ull : (mask & ((~0ull) >> (64 - lane)));
-    return base + (uint32_t)__popcll(below);
-}
-
-// decision-hash events (XOR-combined per sample)
-__device__ __forceinline__ uint32_t ev_vertex(uint32_t k, uint32_t prim, uint32_t sel, uint32_t cont) {
-    return fnv_word(fnv_word(fnv_word(fnv_word(kFnvBasis, k), prim), sel), cont);
-}
-__device__ __forceinline__ uint32_t ev_miss(uint32_t k) { return fnv_word(fnv_word(kFnvBasis, k), 0xFFFFFFFFu); }
-__device__ __forceinline__ uint32_t ev_nee(uint32_t k, uint32_t vis) { return fnv_word(fnv_word(kFnvBasis, k | 0x10000u), vis); }
-
-// ============================================================================
-// environment tables (rebuilt every call: the env map is a trainable input)
-// ============================================================================
-// Row i: texel weights w_ij = mean_c max(0, L) * sin(pi (i + 1/2) / H), prefix
-// sums in double, conditional CDF normalised by the row sum.
-__global__ void k_env_rows(const float *__restrict__ env, int W, int H, double *__restrict__ wts,
-                           double *__restrict__ cond, double *__restrict__ rowsum) {
-    __shared__ double part[256];
-    int i = blockIdx.x;
-    double st = sin(3.14159265358979323846 * (i + 0.5) / H);
-    double carry = 0.0;
-    double *cr = cond + (size_t)i * (W + 1);
-    if (threadIdx.x == 0) cr[0] = 0.0;
-    for (int base = 0; base < W; base += 256) {
-        int j = base + threadIdx.x;
-        double w = 0.0;
-        if (j < W) {
-            const float *L = env + ((size_t)i * W + j) * 3;
-            double m = (double)fmaxf(L[0], 0.0f) + (double)fmaxf(L[1], 0.0f) + (double)fmaxf(L[2], 0.0f);
-            w = (m / 3.0) * st;
-            wts[(size_t)i * W + j] = w;
-        }
-        part[threadIdx.x] = w;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {      // inclusive Hillis-Steele scan
-            double v = threadIdx.x >= off ? part[threadIdx.x - off] : 0.0;
-            __syncthreads();
-            part[threadIdx.x] += v;
-            __syncthreads();
-        }
-        if (j < W) cr[j + 1] = carry + part[threadIdx.x];
-        double tot = part[255];
-        __syncthreads();
-        carry += tot;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x + 1; j <= W; j += 256) cr[j] = carry > 0.0 ? cr[j] / carry : cr[j];
-    __syncthreads();
-    if (threadIdx.x == 0) { cr[W] = 1.0; rowsum[i] = carry; }
-}
-
-__global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__restrict__ marg, double *__restrict__ info) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double acc = 0.0;
-    marg[0] = 0.0;
-    for (int i = 0; i < H; ++i) { acc += rowsum[i]; marg[i + 1] = acc; }
-    for (int i = 1; i <= H; ++i) marg[i] = acc > 0.0 ? marg[i] / acc : marg[i];
-    marg[H] = 1.0;
-    info[0] = acc;
-}
-
-// radiance + pdf table and the guide tables of both CDFs
-__global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
-                             const double *__restrict__ info, const double *__restrict__ marg,
-                             const double *__restrict__ cond, float4 *__restrict__ lp, int32_t *__restrict__ gmarg,
-                             int32_t *__restrict__ gcond) {
-    int i = blockIdx.x;
-    double total = info[0];
-    double scale = total > 0.0 ? (double)W * (double)H / (2.0 * 3.14159265358979323846 * 3.14159265358979323846 * total) : 0.0;
-    if (i < H) {
-        const double *cr = cond + (size_t)i * (W + 1);
-        for (int j = threadIdx.x; j < W; j += blockDim.x) {
-            const float *L = env + ((size_t)i * W + j) * 3;
-            lp[(size_t)i * W + j] = make_float4(fmaxf(L[0], 0.0f), fmaxf(L[1], 0.0f), fmaxf(L[2], 0.0f),
-                                                (float)(wts[(size_t)i * W + j] * scale));
-            double t = (double)j / W;
-            int lo = 0, hi = W - 1;   // smallest c with cr[c + 1] > t
-            while (lo < hi) { int mid = (lo + hi) >> 1; if (cr[mid + 1] > t) hi = mid; else lo = mid + 1; }
-            gcond[(size_t)i * W + j] = lo;
-        }
-    } else {
-        for (int t0 = threadIdx.x; t0 < H; t0 += blockDim.x) {
-            double t = (double)t0 / H;
-            int lo = 0, hi = H - 1;
-            while (lo < hi) { int mid = (lo + hi) >> 1; if (marg[mid + 1] > t) hi = mid; else lo = mid + 1; }
-            gmarg[t0] = lo;
-        }
-    }
-}
-
-// ============================================================================
-// wavefront kernels
-// ============================================================================
-__global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
-__global__ void k_schedule(IterCtr *__restrict__ ctr, int it, Sched *__restrict__ sched, uint32_t P) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t n_in = ctr[it].n_in;
-    uint64_t rem = sched->end - sched->next;
-    uint32_t n_new = (uint32_t)std::min<uint64_t>(rem, (uint64_t)(P - n_in));
-    ctr[it].n_new = n_new;
-    ctr[it].n_live = n_in + n_new;
-    ctr[it].gen_base = sched->next;
-    sched->next += n_new;
-}
-
-struct GenArgs {
-    ViewTable vt; Opts op; Queue q; IterCtr *ctr; int it;
-    float4 *out; uint64_t out_base; uint32_t *hash;
-};
-
-__global__ void k_generate(GenArgs a) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const IterCtr c = a.ctr[a.it];
-    if (i >= c.n_new) return;
-    uint64_t g = c.gen_base + i;
-    SampleId sid = decode(a.vt, g);
-    Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
-    float4 u = rng.draw(0, 0);
-    V3 o, d;
-    camera_ray(a.vt.v[sid.view], sid.pixel, u.x, u.y, o, d);
-    uint32_t slot = c.n_in + i;
-    a.q.o[slot] = make_float4(o.x, o.y, o.z, __uint_as_float((uint32_t)g));
-    a.q.d[slot] = make_float4(d.x, d.y, d.z, __int_as_float(1));
-    a.q.t[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
-    a.out[g - a.out_base] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (a.hash) a.hash[g - a.out_base] = 0u;
-}
-
-struct TraceArgs {
-    const BvhNode *nodes; const TriRec *tris;
-    Queue q; float4 *hits; IterCtr *ctr; int it;
-};
-
-__global__ void k_trace_closest(TraceArgs a) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.ctr[a.it].n_live) return;
-    float4 o = a.q.o[i], d = a.q.d[i];
-    Hit h = trace_closest(a.nodes, a.tris, xyz(o), xyz(d));
-    a.hits[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf));
-}
-
-struct ShadeArgs {
-    SceneDev s; ViewTable vt; Opts op;
-    Queue q, qn; float4 *hits; IterCtr *ctr; int it;
-    float4 *so, *sd, *sc;          // shadow queue: origin (w = sample), dir (w = k), contribution
-    float4 *out; uint64_t out_base; uint32_t *hash;
-    Tape tape; int use_tape;
-};
-
-__global__ void k_shade(ShadeArgs a) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t n = a.ctr[a.it].n_live;
-    const bool active = i < n;
-    bool emit = false, cont = false;
-    float4 e_o, e_d, e_c, c_o, c_d, c_t;
-    if (active) {
-        float4 po = a.q.o[i], pd = a.q.d[i], pt = a.q.t[i], hr = a.hits[i];
-        uint32_t g = __float_as_uint(po.w);
-        int k = __float_as_int(pd.w);
-        V3 d = xyz(pd), T = xyz(pt);
-        int leaf = __float_as_int(hr.w);
-        uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
-        uint32_t hev;
-        if (leaf < 0) {
-            int tex = -1;
-            if (k == 1 && a.op.background == MRS_BG_ENV) {
-                tex = env_texel_of(a.s.env, d);
-                float4 L = a.s.env.lp[tex];
-                a.out[g - a.out_base] = make_float4(L.x, L.y, L.z, 0.0f);
-            }
-            hev = ev_miss((uint32_t)k);
-            if (a.use_tape) {
-                a.tape.hit[ti] = make_float4(0.0f, 0.0f, __int_as_float(-1), __int_as_float(tex));
-                a.tape.y[ti] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                a.tape.rr[ti] = 0.0f;
-            }
-        } else {
-            SampleId sid = decode(a.vt, g);
-            Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
-            float b1 = hr.y, b2 = hr.z;
-            Surf S = surface(a.s, leaf, b1, b2, d);
-            Interp ip;
-            Mat m = clamp_material(fetch_material(a.s, S.prim, b1, b2, ip));
-            V3 wo = to_local(S.F, d * -1.0f);
-            Lobe L = make_lobe(m, wo, a.op.spec);
-            V3 org = spawn(S.p, S.n);
-            const int Me = a.op.M - a.op.Mb, Mb = a.op.Mb;
-            // ---- RIS over Me env + Mb BRDF candidates, streaming WRS ----
-            float wsum = 0.0f, phat_y = 0.0f, cos_y = 0.0f;
-            V3 y = V3{0, 0, 0}, fy = V3{0, 0, 0}, Ly = V3{0, 0, 0};
-            int sel = -1, ytex = -1;
-            if (wo.z > 0.0f) {
-                for (int s = 0; s < a.op.M; ++s) {
-                    float4 u = rng.draw((uint32_t)k, (uint32_t)s);
-                    V3 dir, wl;
-                    int tex;
-                    float4 lp;
-                    float qe, qb;
-                    if (s < Me) {
-                        if (!env_sample(a.s.env, u.x, u.y, dir, tex, lp, qe)) continue;
-                        wl = to_local(S.F, dir);
-                        qb = mix_pdf(L, wl);
-                    } else {
-                        if (!mix_sample(L, u.x, u.y, u.z, wl)) continue;
-                        dir = to_world(S.F, wl);
-                        qb = mix_pdf(L, wl);
-                        tex = env_texel_of(a.s.env, dir);
-                        lp = a.s.env.lp[tex];
-                        qe = env_pdf_dir(a.s.env, dir, tex, lp);
-                    }
-                    if (!(wl.z > 0.0f)) continue;
-                    V3 f = brdf_eval(L, wl);
-                    float phat = (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
-                    float den = (float)Me * qe + (float)Mb * qb;
-                    if (!(phat > 0.0f) || !(den > 0.0f)) continue;
-                    float w = phat / den;
-                    wsum += w;
-                    if (u.w < w / wsum) {
-                        sel = s; y = dir; fy = f; Ly = V3{lp.x, lp.y, lp.z}; phat_y = phat; ytex = tex; cos_y = wl.z;
-                    }
-                }
-            }
-            float Wy = 0.0f;
-            if (sel >= 0) {
-                Wy = wsum / phat_y;
-                emit = true;
-                V3 cc = T * Ly * fy * (cos_y * Wy);
-                e_o = make_float4(org.x, org.y, org.z, __uint_as_float(g));
-                e_d = make_float4(y.x, y.y, y.z, __int_as_float(k));
-                e_c = make_float4(cc.x, cc.y, cc.z, 0.0f);
-            }
-            // ---- continuation (BRDF mixture), Russian roulette ----
-            uint32_t code = 0;
-            float rrf = 0.0f;
-            if (k < a.op.B) {
-                code = 2;
-                float4 u = rng.draw((uint32_t)k, kBlockCont);
-                V3 wl;
-                int lobe = wo.z > 0.0f ? mix_sample(L, u.x, u.y, u.z, wl) : 0;
-                float q = lobe ? mix_pdf(L, wl) : 0.0f;
-                if (lobe && q > 0.0f) {
-                    V3 f = brdf_eval(L, wl);
-                    V3 Tn = T * f * (wl.z / q);
-                    bool alive = true;
-                    rrf = 1.0f;
-                    if (a.op.rr_start >= 0 && k >= a.op.rr_start) {
-                        float qr = fminf(0.95f, maxc(Tn));
-                        if (!(qr > 0.0f) || !(u.w < qr)) { alive = false; code = 3; rrf = 0.0f; }
-                        else { Tn = Tn * (1.0f / qr); rrf = 1.0f / qr; }
-                    }
-                    if (alive) {
-                        code = 1;
-                        cont = true;
-                        V3 wn = to_world(S.F, wl);
-                        c_o = make_float4(org.x, org.y, org.z, __uint_as_float(g));
-                        c_d = make_float4(wn.x, wn.y, wn.z, __int_as_float(k + 1));
-                        c_t = make_float4(Tn.x, Tn.y, Tn.z, 0.0f);
-                    }
-                }
-            }
-            hev = ev_vertex((uint32_t)k, (uint32_t)S.prim, (uint32_t)sel, code);
-            if (a.use_tape) {
-                a.tape.hit[ti] = make_float4(b1, b2, __int_as_float(leaf), __int_as_float(ytex));
-                a.tape.y[ti] = make_float4(y.x, y.y, y.z, Wy);
-                a.tape.rr[ti] = cont ? rrf : 0.0f;
-            }
-        }
-        if (a.hash) a.hash[g - a.out_base] ^= hev;
-    }
-    // compaction: wave-aggregated appends (all lanes reach this point)
-    uint32_t si = wave_append(&a.ctr[a.it].n_shadow, emit);
-    if (emit) { a.so[si] = e_o; a.sd[si] = e_d; a.sc[si] = e_c; }
-    uint32_t ci = wave_append(&a.ctr[a.it + 1].n_in, cont);
-    if (cont) { a.qn.o[ci] = c_o; a.qn.d[ci] = c_d; a.qn.t[ci] = c_t; }
-}
-
-struct ShadowArgs {
-    const BvhNode *nodes; const TriRec *tris;
-    float4 *so, *sd, *sc; IterCtr *ctr; int it;
-    float4 *out; uint64_t out_base; uint32_t *hash;
-    Tape tape; int use_tape;
-};
-
-__global__ void k_trace_shadow(ShadowArgs a) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.ctr[a.it].n_shadow) return;
-    float4 o = a.so[i], d = a.sd[i];
-    uint32_t g = __float_as_uint(o.w);
-    int k = __float_as_int(d.w);
-    bool occl = trace_any(a.nodes, a.tris, xyz(o), xyz(d));
-    if (!occl) {
-        float4 c = a.sc[i];
-        float4 &acc = a.out[g - a.out_base];
-        acc = make_float4(acc.x + c.x, acc.y + c.y, acc.z + c.z, 0.0f);
-    } else if (a.use_tape) {
-        a.tape.y[(uint64_t)(k - 1) * a.tape.S + (g - a.tape.base)].w = 0.0f;
-    }
-    if (a.hash) a.hash[g - a.out_base] ^= ev_nee((uint32_t)k, occl ? 0u : 1u);
-}
-
-struct ResolveArgs {
-    ViewTable vt; const float4 *out; uint64_t out_base;
-    uint64_t pix0, pix1;      // global (view-order) pixel range of the chunk
-    float *image; float *dbg_rgb;
-};
-
-__device__ __forceinline__ int find_view_pix(const ViewTable &vt, uint64_t P) {
-    int lo = 0, hi = vt.n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (vt.v[mid].pix_base <= P) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// pixel = mean of its spp samples, summed in sample order (deterministic)
-__global__ void k_resolve(ResolveArgs a) {
-    uint64_t P = a.pix0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (P >= a.pix1) return;
-    const ViewDev &v = a.vt.v[find_view_pix(a.vt, P)];
-    uint64_t p = P - v.pix_base;
-    uint64_t g0 = v.sample_base + p * (uint64_t)v.spp - a.out_base;
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    for (int s = 0; s < v.spp; ++s) {
-        float4 c = a.out[g0 + s];
-        sx += c.x; sy += c.y; sz += c.z;
-        if (a.dbg_rgb) {
-            float *dst = a.dbg_rgb + 3 * (g0 + a.out_base + s);
-            dst[0] = c.x; dst[1] = c.y; dst[2] = c.z;
-        }
-    }
-    float inv = 1.0f / (float)v.spp;
-    float *img = a.image + 3 * (uint64_t)(v.pixel_offset + (int64_t)p);
-    img[0] = sx * inv; img[1] = sy * inv; img[2] = sz * inv;
-}
-
-// ============================================================================
-// adjoint path replay
-// ============================================================================
-struct AdjArgs {
-    SceneDev s; ViewTable vt; Opts op; Tape tape;
-    uint64_t g0, n;
-    const float *dimg;
-    float *gvmat, *galb, *grough, *gmetal, *genv;
-};
-
-__device__ __forceinline__ void scatter_material(const AdjArgs &a, const Interp &ip, const MatRaw &raw,
-                                                 V3 ga, float gr, float gmu) {
-    // clamp masks: the derivative passes on the closed interval
-    float ma[3] = {(raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f,
-                   (raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f,
-                   (raw.a.z >= 0.0f && raw.a.z <= 1.0f) ? ga.z : 0.0f};
-    float mr = (raw.r >= kRoughMin && raw.r <= 1.0f) ? gr : 0.0f;
-    float mm = (raw.mu >= 0.0f && raw.mu <= 1.0f) ? gmu : 0.0f;
-    if (a.s.mat_mode == MRS_MAT_VERTEX) {
-        if (!a.gvmat) return;
-        for (int q = 0; q < 3; ++q) {
-            float w = ip.w[q];
-            float *dst = a.gvmat + 5 * (size_t)ip.idx[q];
-            if (ma[0] != 0.0f) atomicAdd(dst + 0, w * ma[0]);
-            if (ma[1] != 0.0f) atomicAdd(dst + 1, w * ma[1]);
-            if (ma[2] != 0.0f) atomicAdd(dst + 2, w * ma[2]);
-            if (mr != 0.0f) atomicAdd(dst + 3, w * mr);
-            if (mm != 0.0f) atomicAdd(dst + 4, w * mm);
-        }
-        return;
-    }
-    for (int q = 0; q < 4; ++q) {
-        float w = ip.w[q];
-        if (w == 0.0f) continue;
-        size_t t = (size_t)ip.idx[q];
-        if (a.galb) {
-            if (ma[0] != 0.0f) atomicAdd(a.galb + 3 * t + 0, w * ma[0]);
-            if (ma[1] != 0.0f) atomicAdd(a.galb + 3 * t + 1, w * ma[1]);
-            if (ma[2] != 0.0f) atomicAdd(a.galb + 3 * t + 2, w * ma[2]);
-        }
-        if (a.grough && mr != 0.0f) atomicAdd(a.grough + t, w * mr);
-        if (a.gmetal && mm != 0.0f) atomicAdd(a.gmetal + t, w * mm);
-    }
-}
-
-__device__ __forceinline__ void scatter_env(const AdjArgs &a, int tex, V3 g) {
-    if (!a.genv || tex < 0) return;
-    const float *raw = a.s.env.raw + 3 * (size_t)tex;
-    if (raw[0] >= 0.0f && g.x != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 0, g.x);
-    if (raw[1] >= 0.0f && g.y != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 1, g.y);
-    if (raw[2] >= 0.0f && g.z != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 2, g.z);
-}
-
-// Detached-sampling gradient of one sample: with directions, selections and
-// all pdf / reservoir weights held fixed, C = sum_k T_k (.) D_k and
-// T_{k+1} = T_k (.) beta_k, so dC/dm_k = T_k (.) (dD_k/dm_k + dbeta_k/dm_k (.) Li_{k+1})
-// with Li_k = D_k + beta_k (.) Li_{k+1} accumulated from the last vertex back.
-__global__ void k_adjoint(AdjArgs a) {
-    uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
-    uint64_t g = a.g0 + j;
-    SampleId sid = decode(a.vt, g);
-    const ViewDev &vw = a.vt.v[sid.view];
-    Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
-    const float *gi = a.dimg + 3 * (uint64_t)(vw.pixel_offset + (int64_t)sid.pixel);
-    float inv_spp = 1.0f / (float)vw.spp;
-    V3 gp = V3{gi[0] * inv_spp, gi[1] * inv_spp, gi[2] * inv_spp};
-    if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return;
-    float4 u = rng.draw(0, 0);
-    V3 o, d;
-    camera_ray(vw, sid.pixel, u.x, u.y, o, d);
-    const int B = a.op.B;
-    V3 Dk[MRS_MAX_BOUNCES], Bk[MRS_MAX_BOUNCES], Lk[MRS_MAX_BOUNCES], dk[MRS_MAX_BOUNCES];
-    int nv = 0;
-    // pass 1: per-vertex direct term D_k and continuation weight beta_k
-    for (int k = 1; k <= B; ++k) {
-        uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
-        float4 th = a.tape.hit[ti];
-        int leaf = __float_as_int(th.z);
-        if (leaf < 0) {
-            if (k == 1) scatter_env(a, __float_as_int(th.w), gp);
-            break;
-        }
-        dk[k - 1] = d;
-        Surf S = surface(a.s, leaf, th.x, th.y, d);
-        Interp ip;
-        Mat m = clamp_material(fetch_material(a.s, S.prim, th.x, th.y, ip));
-        Lobe L = make_lobe(m, to_local(S.F, d * -1.0f), a.op.spec);
-        float4 ty = a.tape.y[ti];
-        V3 D = V3{0, 0, 0};
-        if (ty.w > 0.0f) {
-            V3 yl = to_local(S.F, xyz(ty));
-            V3 f = brdf_eval(L, yl);
-            float4 lp = a.s.env.lp[__float_as_int(th.w)];
-            D = V3{lp.x, lp.y, lp.z} * f * (yl.z * ty.w);
-        }
-        Dk[k - 1] = D;
-        Bk[k - 1] = V3{0, 0, 0};
-        nv = k;
-        float rr = a.tape.rr[ti];
-        if (!(rr > 0.0f) || k == B) break;
-        float4 uc = rng.draw((uint32_t)k, kBlockCont);
-        V3 wl;
-        mix_sample(L, uc.x, uc.y, uc.z, wl);
-        float q = mix_pdf(L, wl);
-        if (!(q > 0.0f)) break;
-        Bk[k - 1] = brdf_eval(L, wl) * (wl.z / q * rr);
-        d = to_world(S.F, wl);
-    }
-    // suffix radiance Li_{k+1}
-    V3 Li = V3{0, 0, 0};
-    for (int k = nv; k >= 1; --k) {
-        Lk[k - 1] = Li;
-        Li = Dk[k - 1] + Bk[k - 1] * Li;
-    }
-    // pass 2: local derivatives, scattered through interpolation weights
-    V3 T = V3{1, 1, 1};
-    for (int k = 1; k <= nv; ++k) {
-        if (a.op.grad_mode == MRS_GRAD_PRIMARY && k > 1) break;
-        uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
-        float4 th = a.tape.hit[ti];
-        int leaf = __float_as_int(th.z);
-        V3 dd = dk[k - 1];
-        Surf S = surface(a.s, leaf, th.x, th.y, dd);
-        Interp ip;
-        MatRaw raw = fetch_material(a.s, S.prim, th.x, th.y, ip);
-        Mat m = clamp_material(raw);
-        Lobe L = make_lobe(m, to_local(S.F, dd * -1.0f), a.op.spec);
-        V3 ga = V3{0, 0, 0};
-        float gr = 0.0f, gmu = 0.0f;
-        V3 w = gp * T;   // dL/dC weighted by throughput
-        float4 ty = a.tape.y[ti];
-        if (ty.w > 0.0f) {
-            V3 yl = to_local(S.F, xyz(ty));
-            int tex = __float_as_int(th.w);
-            float4 lp = a.s.env.lp[tex];
-            V3 Lv = V3{lp.x, lp.y, lp.z};
-            float cw = yl.z * ty.w;
-            BrdfGrad bg = brdf_grad(L, m, yl);
-            V3 wl = w * Lv * cw;
-            ga = ga + wl * bg.da;
-            gr += dot(wl, bg.dr);
-            gmu += dot(wl, bg.dmu);
-            V3 f = brdf_eval(L, yl);
-            scatter_env(a, tex, w * f * cw);
-        }
-        if (k < nv) {
-            float rr = a.tape.rr[ti];
-            float4 uc = rng.draw((uint32_t)k, kBlockCont);
-            V3 wl;
-            mix_sample(L, uc.x, uc.y, uc.z, wl);
-            float q = mix_pdf(L, wl);
-            if (q > 0.0f) {
-                BrdfGrad bg = brdf_grad(L, m, wl);
-                V3 wb = w * Lk[k - 1] * (wl.z / q * rr);
-                ga = ga + wb * bg.da;
-                gr += dot(wb, bg.dr);
-                gmu += dot(wb, bg.dmu);
-            }
-        }
-        scatter_material(a, ip, raw, ga, gr, gmu);
-        T = T * Bk[k - 1];
-    }
-}
-
-__global__ void k_trace_batch(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
-                              const float *__restrict__ orig, const float *__restrict__ dir, int64_t n, int any,
-                              float4 *__restrict__ out) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    V3 o = ld3(orig + 3 * i), d = ld3(dir + 3 * i);
-    if (any) {
-        bool h = trace_any(nodes, tris, o, d);
-        out[i] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(h ? 0 : -1));
-    } else {
-        Hit h = trace_closest(nodes, tris, o, d);
-        out[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf >= 0 ? h.prim : -1));
-    }
-}
-
-__global__ void k_set_sched(Sched *s, uint64_t a, uint64_t b) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) { s->next = a; s->end = b; }
-}
-
-// ============================================================================
-// host side
-// ============================================================================
-// kernel timing: event pairs around every launch while profiling is on
 enum KernelId { KID_ENV = 0, KID_SCHED, KID_GENERATE, KID_CLOSEST, KID_SHADE, KID_SHADOW, KID_RESOLVE, KID_ADJOINT,
-                KID_TRACE, KID_COUNT };
+                KID_TRACE, KID_PLAN_FWD, KID_PLAN_BWD, KID_COUNT };
 const char *const kKernelNames[KID_COUNT] = {"env_tables", "schedule", "generate", "trace_closest", "shade",
-                                             "trace_shadow", "resolve", "adjoint", "trace_batch"};
+                                             "trace_shadow", "resolve", "adjoint", "trace_batch",
+                                             "plan_forward_graph", "plan_backward_graph"};
 struct Profiler {
     std::mutex mu;
     bool on = false;
@@ -777,11 +73,12 @@ struct Profiler {
     }
 };
 Profiler g_prof;
+thread_local bool t_capturing = false;
 
 struct ProfScope {
     int kid; hipStream_t s; hipEvent_t a = nullptr;
     ProfScope(int k, hipStream_t st) : kid(k), s(st) {
-        if (g_prof.on && (a = g_prof.next())) (void)hipEventRecord(a, s);
+        if (g_prof.on && !t_capturing && (a = g_prof.next())) (void)hipEventRecord(a, s);
     }
     ~ProfScope() {
         if (!a) return;
@@ -791,8 +88,11 @@ struct ProfScope {
         g_prof.recs.push_back({kid, a, b});
     }
 };
-#define PROF(kid, s) ProfScope prof_scope_##__LINE__((kid), (s))
+#define PROF(kid, s) ProfScope prof_scope_((kid), (s))
 
+// ============================================================================
+// jobs and buffers
+// ============================================================================
 constexpr uint64_t kOutChunkMax = 1ull << 26;   // samples per super-chunk of the output buffer
 constexpr uint32_t kPoolDefault = 1u << 22;      // paths in flight
 constexpr uint64_t kTapeRecBytes = 36;           // tape bytes per path vertex
@@ -800,16 +100,28 @@ constexpr uint64_t kAdjChunk = 1ull << 24;        // samples per adjoint launch
 
 struct Chunk { uint64_t c0, c1, pix0, pix1; };
 
+// Device buffers one launch sequence works in: the library's shared
+// workspace for eager calls, or a plan's own set.
+struct Res {
+    DevBuf wts, cond, marg, rowsum, info, lp, gmarg, gcond;    // environment tables
+    DevBuf views;                                              // ViewDev table
+    DevBuf qa_o, qa_d, qa_t, qb_o, qb_d, qb_t, hits, so, sd, sc; // path pool queues
+    DevBuf ctr, sched, out;                                    // iteration counters, scheduler, sample radiance
+    DevBuf ct_hit, ct_y, ct_rr;                                // chunk tape (recompute mode)
+    void release_all() {
+        for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &views, &qa_o, &qa_d, &qa_t, &qb_o,
+                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr})
+            b->release();
+    }
+};
+
 struct Workspace {
     std::mutex mu;
-    DevBuf wts, cond, marg, rowsum, info, lp, gmarg, gcond;
-    DevBuf views;
-    DevBuf qa_o, qa_d, qa_t, qb_o, qb_d, qb_t, hits, so, sd, sc;
-    DevBuf ctr, sched, out;
-    DevBuf ct_hit, ct_y, ct_rr;   // chunk tape (recompute mode)
+    Res res;
     ViewDev *staging = nullptr;   // pinned host copy of the view table
     size_t staging_n = 0;
-    hipEvent_t done = nullptr;    // end of the previous call
+    std::vector<ViewDev> uploaded;  // view table currently on the device
+    hipEvent_t done = nullptr;    // end of the previous eager call
     hipStream_t last = nullptr;
     bool has_last = false;
 };
@@ -818,7 +130,6 @@ Workspace g_ws;
 struct Job {
     std::vector<ViewDev> vd;
     uint64_t S = 0, pixels = 0;
-    EnvTables env{};
     SceneDev sd{};
     Opts op{};
     ViewTable vt{};
@@ -903,74 +214,6 @@ uint64_t signature(const Job &job) {
     return h;
 }
 
-#define TRY(x) do { mrs_status st_ = (x); if (st_ != MRS_OK) return st_; } while (0)
-#define HIPTRY(x, what) TRY(hip_check((x), what))
-
-mrs_status begin(hipStream_t s) {
-    Workspace &w = g_ws;
-    if (!w.done) HIPTRY(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "hipEventCreate");
-    if (w.has_last && w.last != s) HIPTRY(hipStreamWaitEvent(s, w.done, 0), "hipStreamWaitEvent");
-    return MRS_OK;
-}
-mrs_status finish(hipStream_t s) {
-    Workspace &w = g_ws;
-    HIPTRY(hipGetLastError(), "kernel launch");
-    HIPTRY(hipEventRecord(w.done, s), "hipEventRecord");
-    w.last = s;
-    w.has_last = true;
-    return MRS_OK;
-}
-
-mrs_status setup(const mrs_scene *sc, Job &job, hipStream_t s) {
-    Workspace &w = g_ws;
-    int W = sc->ew, H = sc->eh;
-    size_t nt = (size_t)W * H;
-    TRY(w.wts.reserve(sizeof(double) * nt));
-    TRY(w.cond.reserve(sizeof(double) * (size_t)H * (W + 1)));
-    TRY(w.marg.reserve(sizeof(double) * (H + 1)));
-    TRY(w.rowsum.reserve(sizeof(double) * H));
-    TRY(w.info.reserve(sizeof(double) * 2));
-    TRY(w.lp.reserve(sizeof(float4) * nt));
-    TRY(w.gmarg.reserve(sizeof(int32_t) * H));
-    TRY(w.gcond.reserve(sizeof(int32_t) * nt));
-    {
-    PROF(KID_ENV, s);
-    k_env_rows<<<H, 256, 0, s>>>(sc->env, W, H, w.wts.as<double>(), w.cond.as<double>(), w.rowsum.as<double>());
-    k_env_marg<<<1, 64, 0, s>>>(w.rowsum.as<double>(), H, w.marg.as<double>(), w.info.as<double>());
-    k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, w.wts.as<double>(), w.info.as<double>(), w.marg.as<double>(),
-                                        w.cond.as<double>(), w.lp.as<float4>(), w.gmarg.as<int32_t>(), w.gcond.as<int32_t>());
-    }
-    // env validity (total weight > 0) is needed on the host once per call
-    double info = 0.0;
-    HIPTRY(hipMemcpyAsync(&info, w.info.p, sizeof(double), hipMemcpyDeviceToHost, s), "copy env total");
-    HIPTRY(hipStreamSynchronize(s), "sync env total");
-    job.env.marg = w.marg.as<double>(); job.env.cond = w.cond.as<double>();
-    job.env.gmarg = w.gmarg.as<int32_t>(); job.env.gcond = w.gcond.as<int32_t>();
-    job.env.lp = w.lp.as<float4>(); job.env.raw = sc->env;
-    job.env.W = W; job.env.H = H; job.env.valid = info > 0.0;
-    // views: pinned staging, reused once the previous call has finished
-    size_t nv = job.vd.size();
-    if (w.staging_n < nv) {
-        if (w.staging) HIPTRY(hipHostFree(w.staging), "hipHostFree");
-        w.staging = nullptr;
-        w.staging_n = 0;
-        HIPTRY(hipHostMalloc((void **)&w.staging, sizeof(ViewDev) * nv, hipHostMallocDefault), "hipHostMalloc");
-        w.staging_n = nv;
-    }
-    std::memcpy(w.staging, job.vd.data(), sizeof(ViewDev) * nv);
-    TRY(w.views.reserve(sizeof(ViewDev) * nv));
-    HIPTRY(hipMemcpyAsync(w.views.p, w.staging, sizeof(ViewDev) * nv, hipMemcpyHostToDevice, s), "copy views");
-    job.vt.v = w.views.as<ViewDev>();
-    job.vt.n = (int)nv;
-    job.sd.faces = sc->bvh->faces.as<int32_t>(); job.sd.uv = sc->uv; job.sd.vmat = sc->vmat;
-    job.sd.albedo = sc->albedo; job.sd.rough = sc->rough; job.sd.metal = sc->metal;
-    job.sd.mat_mode = sc->mat_mode; job.sd.tw = sc->tw; job.sd.th = sc->th;
-    job.sd.nodes = sc->bvh->nodes.as<BvhNode>();
-    job.sd.tris = sc->bvh->tris.as<TriRec>();
-    job.sd.env = job.env;
-    return MRS_OK;
-}
-
 // pixel-aligned sample ranges of at most `cap` samples (a pixel is never split)
 std::vector<Chunk> make_chunks(const Job &job, uint64_t cap) {
     std::vector<Chunk> out;
@@ -993,58 +236,108 @@ std::vector<Chunk> make_chunks(const Job &job, uint64_t cap) {
     return out;
 }
 
-mrs_status ensure_pool(uint32_t P, uint64_t out_samples, int n_iter) {
-    Workspace &w = g_ws;
+uint64_t max_chunk(const std::vector<Chunk> &cs) {
+    uint64_t m = 0;
+    for (const Chunk &c : cs) m = std::max(m, c.c1 - c.c0);
+    return m;
+}
+
+int iterations(const Job &job, uint64_t n, uint32_t P) { return (int)((n * job.op.B + P - 1) / P) + job.op.B + 1; }
+
+// scene pointers the kernels read (the BVH's validated face copy for shading)
+void bind_scene(const mrs_scene *sc, Job &job) {
+    job.sd.faces = sc->bvh->faces.as<int32_t>(); job.sd.uv = sc->uv; job.sd.vmat = sc->vmat;
+    job.sd.albedo = sc->albedo; job.sd.rough = sc->rough; job.sd.metal = sc->metal;
+    job.sd.mat_mode = sc->mat_mode; job.sd.tw = sc->tw; job.sd.th = sc->th;
+    job.sd.nodes = sc->bvh->nodes.as<BvhNode>();
+    job.sd.tris = sc->bvh->tris.as<TriRec>();
+}
+
+mrs_status reserve_env(const mrs_scene *sc, Res &r) {
+    size_t W = sc->ew, H = sc->eh, nt = W * H;
+    TRY(r.wts.reserve(sizeof(double) * nt));
+    TRY(r.cond.reserve(sizeof(double) * H * (W + 1)));
+    TRY(r.marg.reserve(sizeof(double) * (H + 1)));
+    TRY(r.rowsum.reserve(sizeof(double) * H));
+    TRY(r.info.reserve(sizeof(double) * 2));
+    TRY(r.lp.reserve(sizeof(float4) * nt));
+    TRY(r.gmarg.reserve(sizeof(int32_t) * H));
+    TRY(r.gcond.reserve(sizeof(int32_t) * nt));
+    return MRS_OK;
+}
+
+mrs_status reserve_pool(Res &r, uint32_t P, uint64_t out_samples, int n_iter) {
     size_t q = sizeof(float4) * (size_t)P;
-    for (DevBuf *b : {&w.qa_o, &w.qa_d, &w.qa_t, &w.qb_o, &w.qb_d, &w.qb_t, &w.hits, &w.so, &w.sd, &w.sc}) TRY(b->reserve(q));
-    TRY(w.ctr.reserve(sizeof(IterCtr) * (size_t)(n_iter + 1)));
-    TRY(w.sched.reserve(sizeof(Sched)));
-    TRY(w.out.reserve(sizeof(float4) * (size_t)out_samples));
+    for (DevBuf *b : {&r.qa_o, &r.qa_d, &r.qa_t, &r.qb_o, &r.qb_d, &r.qb_t, &r.hits, &r.so, &r.sd, &r.sc}) TRY(b->reserve(q));
+    TRY(r.ctr.reserve(sizeof(IterCtr) * (size_t)(n_iter + 1)));
+    TRY(r.sched.reserve(sizeof(Sched)));
+    TRY(r.out.reserve(sizeof(float4) * (size_t)out_samples));
+    return MRS_OK;
+}
+
+// env tables: kernels only (the validity flag stays on the device), so the
+// sequence can be captured in a graph
+mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
+    TRY(reserve_env(sc, r));
+    int W = sc->ew, H = sc->eh;
+    {
+        PROF(KID_ENV, s);
+        k_env_rows<<<H, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.cond.as<double>(), r.rowsum.as<double>());
+        k_env_marg<<<1, 64, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
+        k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.info.as<double>(), r.marg.as<double>(),
+                                            r.cond.as<double>(), r.lp.as<float4>(), r.gmarg.as<int32_t>(),
+                                            r.gcond.as<int32_t>());
+    }
+    EnvTables &e = job.sd.env;
+    e.marg = r.marg.as<double>(); e.cond = r.cond.as<double>();
+    e.gmarg = r.gmarg.as<int32_t>(); e.gcond = r.gcond.as<int32_t>();
+    e.lp = r.lp.as<float4>(); e.raw = sc->env; e.total = r.info.as<double>();
+    e.W = W; e.H = H;
     return MRS_OK;
 }
 
 // One super-chunk through the persistent pool.  The number of iterations is
 // an upper bound (every full iteration retires P path vertices); iterations
-// past the end find empty queues and exit at once.
-mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tape, uint32_t *hash, hipStream_t s) {
-    Workspace &w = g_ws;
+// past the end find empty queues and exit at once.  No allocation happens
+// when the buffers were reserved beforehand (graph capture relies on it).
+mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tape, uint32_t *hash, Res &r,
+                         hipStream_t s) {
     uint64_t n = ch.c1 - ch.c0;
     uint32_t P = (uint32_t)std::min<uint64_t>(job.pool, n);
-    int n_iter = (int)((n * job.op.B + P - 1) / P) + job.op.B + 1;
-    TRY(ensure_pool(P, n, n_iter));
-    k_fill_u32<<<nblocks((sizeof(IterCtr) / 4) * (n_iter + 1), 256), 256, 0, s>>>(w.ctr.as<uint32_t>(),
-                                                                              (sizeof(IterCtr) / 4) * (n_iter + 1), 0u);
-    k_set_sched<<<1, 64, 0, s>>>(w.sched.as<Sched>(), ch.c0, ch.c1);
-    Queue qa{w.qa_o.as<float4>(), w.qa_d.as<float4>(), w.qa_t.as<float4>()};
-    Queue qb{w.qb_o.as<float4>(), w.qb_d.as<float4>(), w.qb_t.as<float4>()};
-    IterCtr *ctr = w.ctr.as<IterCtr>();
+    int n_iter = iterations(job, n, P);
+    TRY(reserve_pool(r, P, n, n_iter));
+    size_t nctr = (sizeof(IterCtr) / 4) * (size_t)(n_iter + 1);
+    k_fill_u32<<<nblocks(nctr, 256), 256, 0, s>>>(r.ctr.as<uint32_t>(), nctr, 0u);
+    k_set_sched<<<1, 64, 0, s>>>(r.sched.as<Sched>(), ch.c0, ch.c1);
+    Queue qa{r.qa_o.as<float4>(), r.qa_d.as<float4>(), r.qa_t.as<float4>()};
+    Queue qb{r.qb_o.as<float4>(), r.qb_d.as<float4>(), r.qb_t.as<float4>()};
+    IterCtr *ctr = r.ctr.as<IterCtr>();
     int bs = job.block;
     for (int it = 0; it < n_iter; ++it) {
         {
             PROF(KID_SCHED, s);
-            k_schedule<<<1, 64, 0, s>>>(ctr, it, w.sched.as<Sched>(), P);
+            k_schedule<<<1, 64, 0, s>>>(ctr, it, r.sched.as<Sched>(), P);
         }
-        GenArgs ga{job.vt, job.op, qa, ctr, it, w.out.as<float4>(), ch.c0, hash};
         {
             PROF(KID_GENERATE, s);
+            GenArgs ga{job.vt, job.op, qa, ctr, it, r.out.as<float4>(), ch.c0, hash};
             k_generate<<<nblocks(P, 256), 256, 0, s>>>(ga);
         }
-        TraceArgs ta{job.sd.nodes, job.sd.tris, qa, w.hits.as<float4>(), ctr, it};
         {
             PROF(KID_CLOSEST, s);
+            TraceArgs ta{job.sd.nodes, job.sd.tris, qa, r.hits.as<float4>(), ctr, it};
             k_trace_closest<<<nblocks(P, bs), bs, 0, s>>>(ta);
         }
-        ShadeArgs sa{job.sd, job.vt, job.op, qa, qb, w.hits.as<float4>(), ctr, it,
-                     w.so.as<float4>(), w.sd.as<float4>(), w.sc.as<float4>(), w.out.as<float4>(), ch.c0, hash,
-                     tape, use_tape};
         {
             PROF(KID_SHADE, s);
+            ShadeArgs sa{job.sd, job.vt, job.op, qa, qb, r.hits.as<float4>(), ctr, it, r.so.as<float4>(),
+                         r.sd.as<float4>(), r.sc.as<float4>(), r.out.as<float4>(), ch.c0, hash, tape, use_tape};
             k_shade<<<nblocks(P, bs), bs, 0, s>>>(sa);
         }
-        ShadowArgs sh{job.sd.nodes, job.sd.tris, w.so.as<float4>(), w.sd.as<float4>(), w.sc.as<float4>(), ctr, it,
-                      w.out.as<float4>(), ch.c0, hash, tape, use_tape};
         {
             PROF(KID_SHADOW, s);
+            ShadowArgs sh{job.sd.nodes, job.sd.tris, r.so.as<float4>(), r.sd.as<float4>(), r.sc.as<float4>(), ctr, it,
+                          r.out.as<float4>(), ch.c0, hash, tape, use_tape};
             k_trace_shadow<<<nblocks(P, bs), bs, 0, s>>>(sh);
         }
         std::swap(qa, qb);
@@ -1053,19 +346,215 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
     return MRS_OK;
 }
 
+void resolve(const Job &job, const Chunk &ch, const Res &r, float *image, float *dbg_rgb, hipStream_t s) {
+    PROF(KID_RESOLVE, s);
+    ResolveArgs ra{job.vt, r.out.as<float4>(), ch.c0, ch.pix0, ch.pix1, image, dbg_rgb};
+    k_resolve<<<nblocks(ch.pix1 - ch.pix0, 256), 256, 0, s>>>(ra);
+}
+
+mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, const float *dimg, const mrs_grads *gr,
+                   hipStream_t s) {
+    for (uint64_t a0 = c0; a0 < c1; a0 += kAdjChunk) {
+        uint64_t n = std::min<uint64_t>(kAdjChunk, c1 - a0);
+        PROF(KID_ADJOINT, s);
+        AdjArgs aa{job.sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env};
+        k_adjoint<<<nblocks(n, 256), 256, 0, s>>>(aa);
+    }
+    HIPTRY(hipGetLastError(), "adjoint launch");
+    return MRS_OK;
+}
+
+mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B) {
+    size_t n = (size_t)S * B;
+    TRY(t->hit.alloc(sizeof(float4) * n));
+    TRY(t->y.alloc(sizeof(float4) * n));
+    TRY(t->rr.alloc(sizeof(float) * n));
+    return MRS_OK;
+}
+
+// tape policy: keep the per-vertex records when asked and affordable
+mrs_status decide_tape(const Job &job, const mrs_options *opt, bool wanted, mrs_tape **out) {
+    *out = nullptr;
+    if (!wanted || opt->tape_mode == MRS_TAPE_OFF) return MRS_OK;
+    uint64_t bytes = job.S * job.op.B * kTapeRecBytes;
+    uint64_t budget = (uint64_t)opt->tape_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIPTRY(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+        budget = fr / 2;
+    }
+    if (opt->tape_mode != MRS_TAPE_ON && bytes > budget) return MRS_OK;
+    mrs_tape *t = new mrs_tape();
+    mrs_status st = tape_alloc(t, job.S, job.op.B);
+    if (st != MRS_OK) {
+        delete t;
+        if (opt->tape_mode == MRS_TAPE_ON) return st;
+        clear_error();   // AUTO falls back to recompute
+        return MRS_OK;
+    }
+    t->samples = job.S; t->bounces = job.op.B; t->seed = opt->seed; t->signature = signature(job);
+    *out = t;
+    return MRS_OK;
+}
+
+Tape tape_view(const mrs_tape *t) {
+    return Tape{t->hit.as<float4>(), t->y.as<float4>(), t->rr.as<float>(), 0, t->samples};
+}
+
+// forward launch sequence (eager or under capture)
+mrs_status enqueue_forward(const Job &job, const std::vector<Chunk> &chunks, const mrs_scene *sc, Res &r,
+                           const mrs_tape *tape, float *image, float *dbg_rgb, uint32_t *dbg_hash, hipStream_t s) {
+    Job j = job;
+    TRY(env_tables(sc, j, r, s));
+    Tape tp = tape ? tape_view(tape) : Tape{};
+    for (const Chunk &ch : chunks) {
+        // the hash buffer is indexed from the chunk start like the output
+        TRY(run_wavefront(j, ch, tp, tape != nullptr, dbg_hash ? dbg_hash + ch.c0 : nullptr, r, s));
+        resolve(j, ch, r, image, dbg_rgb, s);
+    }
+    return MRS_OK;
+}
+
+// backward launch sequence: replay the tape, or re-render chunk by chunk into
+// a bounded tape and replay that
+mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, const mrs_scene *sc, Res &r,
+                            const mrs_tape *tape, const float *dimg, const mrs_grads *grads, hipStream_t s) {
+    Job j = job;
+    TRY(env_tables(sc, j, r, s));
+    if (tape) return adjoint(j, tape_view(tape), 0, j.S, dimg, grads, s);
+    uint64_t cap = max_chunk(chunks);
+    size_t n = (size_t)cap * j.op.B;
+    TRY(r.ct_hit.reserve(sizeof(float4) * n));
+    TRY(r.ct_y.reserve(sizeof(float4) * n));
+    TRY(r.ct_rr.reserve(sizeof(float) * n));
+    for (const Chunk &ch : chunks) {
+        Tape tp{r.ct_hit.as<float4>(), r.ct_y.as<float4>(), r.ct_rr.as<float>(), ch.c0, cap};
+        TRY(run_wavefront(j, ch, tp, 1, nullptr, r, s));
+        TRY(adjoint(j, tp, ch.c0, ch.c1, dimg, grads, s));
+    }
+    return MRS_OK;
+}
+
+// eager calls share one workspace; a call on another stream first waits for
+// the previous call to finish with it
+mrs_status begin(hipStream_t s) {
+    Workspace &w = g_ws;
+    if (!w.done) HIPTRY(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "hipEventCreate");
+    if (w.has_last && w.last != s) HIPTRY(hipStreamWaitEvent(s, w.done, 0), "hipStreamWaitEvent");
+    return MRS_OK;
+}
+mrs_status finish(hipStream_t s) {
+    Workspace &w = g_ws;
+    HIPTRY(hipGetLastError(), "kernel launch");
+    HIPTRY(hipEventRecord(w.done, s), "hipEventRecord");
+    w.last = s;
+    w.has_last = true;
+    return MRS_OK;
+}
+
+// view table through pinned staging, reused once the previous call is done;
+// skipped when the device already holds the same table (repeated calls over
+// the same views, as in an optimisation loop)
+mrs_status upload_views_eager(Job &job, hipStream_t s) {
+    Workspace &w = g_ws;
+    size_t nv = job.vd.size();
+    job.vt.v = w.res.views.as<ViewDev>();
+    job.vt.n = (int)nv;
+    if (w.res.views.p && w.uploaded.size() == nv &&
+        std::memcmp(w.uploaded.data(), job.vd.data(), sizeof(ViewDev) * nv) == 0)
+        return MRS_OK;
+    w.uploaded.clear();
+    if (w.done) HIPTRY(hipEventSynchronize(w.done), "hipEventSynchronize");
+    if (w.staging_n < nv) {
+        if (w.staging) HIPTRY(hipHostFree(w.staging), "hipHostFree");
+        w.staging = nullptr;
+        w.staging_n = 0;
+        HIPTRY(hipHostMalloc((void **)&w.staging, sizeof(ViewDev) * nv, hipHostMallocDefault), "hipHostMalloc");
+        w.staging_n = nv;
+    }
+    std::memcpy(w.staging, job.vd.data(), sizeof(ViewDev) * nv);
+    TRY(w.res.views.reserve(sizeof(ViewDev) * nv));
+    HIPTRY(hipMemcpyAsync(w.res.views.p, w.staging, sizeof(ViewDev) * nv, hipMemcpyHostToDevice, s), "copy views");
+    job.vt.v = w.res.views.as<ViewDev>();
+    w.uploaded = job.vd;
+    return MRS_OK;
+}
+
 }  // namespace
 }  // namespace mrs
 
 using namespace mrs;
 
+// ============================================================================
+// eager entry points
+// ============================================================================
+extern "C" mrs_status mrs_render(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
+                                 const mrs_options *opt, float *d_image, mrs_tape **tape_out, void *stream) {
+    clear_error();
+    if (tape_out) *tape_out = nullptr;
+    if (!d_image) return fail(MRS_EINVAL, "mrs_render: image is NULL");
+    Job job;
+    TRY(validate(scene, views, n_views, opt, job));
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    hipStream_t s = (hipStream_t)stream;
+    TRY(begin(s));
+    TRY(upload_views_eager(job, s));
+    bind_scene(scene, job);
+    mrs_tape *tape = nullptr;
+    TRY(decide_tape(job, opt, tape_out != nullptr, &tape));
+    mrs_status st = enqueue_forward(job, make_chunks(job, kOutChunkMax), scene, g_ws.res, tape, d_image,
+                                    opt->debug_sample_rgb, opt->debug_hash, s);
+    if (st == MRS_OK) st = finish(s);
+    if (st != MRS_OK) { delete tape; return st; }
+    if (tape_out) *tape_out = tape;
+    return MRS_OK;
+}
+
+extern "C" mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
+                                          const mrs_options *opt, const float *d_grad_image, const mrs_grads *grads,
+                                          const mrs_tape *tape, void *stream) {
+    clear_error();
+    if (!d_grad_image) return fail(MRS_EINVAL, "mrs_render_backward: grad image is NULL");
+    if (!grads) return fail(MRS_EINVAL, "mrs_render_backward: grads is NULL");
+    Job job;
+    TRY(validate(scene, views, n_views, opt, job));
+    if (tape && (tape->samples != job.S || tape->bounces != job.op.B || tape->seed != opt->seed ||
+                 tape->signature != signature(job)))
+        return fail(MRS_EINVAL, "mrs_render_backward: tape was recorded for different views or options");
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    hipStream_t s = (hipStream_t)stream;
+    TRY(begin(s));
+    TRY(upload_views_eager(job, s));
+    bind_scene(scene, job);
+    std::vector<Chunk> chunks = make_chunks(job, std::min<uint64_t>(kOutChunkMax, job.S));
+    TRY(enqueue_backward(job, chunks, scene, g_ws.res, tape, d_grad_image, grads, s));
+    return finish(s);
+}
+
 extern "C" int64_t mrs_tape_bytes(const mrs_view *views, int32_t n_views, const mrs_options *opt) {
     if (!views || !opt || n_views < 1) return -1;
     uint64_t S = 0;
-    for (int i = 0; i < n_views; ++i) S += (uint64_t)std::max(0, views[i].w) * std::max(0, views[i].h) * std::max(0, views[i].spp);
+    for (int i = 0; i < n_views; ++i)
+        S += (uint64_t)std::max(0, views[i].w) * std::max(0, views[i].h) * std::max(0, views[i].spp);
     return (int64_t)(S * (uint64_t)std::max(0, opt->bounces) * kTapeRecBytes);
 }
 
 extern "C" void mrs_tape_destroy(mrs_tape *t) { delete t; }
+
+extern "C" mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const float *d_dir, int64_t n,
+                                int32_t any_hit, float *d_hit, void *stream) {
+    clear_error();
+    if (!bvh || !d_orig || !d_dir || !d_hit) return fail(MRS_EINVAL, "mrs_trace: null argument");
+    if (n < 0) return fail(MRS_EINVAL, "mrs_trace: n < 0");
+    if (n == 0) return MRS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    {
+        PROF(KID_TRACE, s);
+        k_trace_batch<<<nblocks((uint64_t)n, 256), 256, 0, s>>>(bvh->nodes.as<BvhNode>(), bvh->tris.as<TriRec>(),
+                                                               d_orig, d_dir, n, any_hit ? 1 : 0, (float4 *)d_hit);
+    }
+    return hip_check(hipGetLastError(), "mrs_trace launch");
+}
 
 extern "C" mrs_status mrs_profile_begin(void) {
     clear_error();
@@ -1084,9 +573,9 @@ extern "C" mrs_status mrs_profile_end(mrs_kernel_time *out, int32_t cap, int32_t
     double ms[KID_COUNT] = {0};
     int64_t cnt[KID_COUNT] = {0};
     for (const Profiler::Rec &r : g_prof.recs) {
-        TRY(hip_check(hipEventSynchronize(r.b), "hipEventSynchronize"));
+        HIPTRY(hipEventSynchronize(r.b), "hipEventSynchronize");
         float t = 0.0f;
-        TRY(hip_check(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime"));
+        HIPTRY(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
         ms[r.kid] += t;
         cnt[r.kid] += 1;
     }
@@ -1105,140 +594,155 @@ extern "C" mrs_status mrs_profile_end(mrs_kernel_time *out, int32_t cap, int32_t
     return MRS_OK;
 }
 
-extern "C" mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const float *d_dir, int64_t n,
-                                int32_t any_hit, float *d_hit, void *stream) {
-    clear_error();
-    if (!bvh || !d_orig || !d_dir || !d_hit) return fail(MRS_EINVAL, "mrs_trace: null argument");
-    if (n < 0) return fail(MRS_EINVAL, "mrs_trace: n < 0");
-    if (n == 0) return MRS_OK;
-    hipStream_t s = (hipStream_t)stream;
-    {
-        PROF(KID_TRACE, s);
-        k_trace_batch<<<nblocks((uint64_t)n, 256), 256, 0, s>>>(bvh->nodes.as<BvhNode>(), bvh->tris.as<TriRec>(), d_orig,
-                                                           d_dir, n, any_hit ? 1 : 0, (float4 *)d_hit);
-    }
-    return hip_check(hipGetLastError(), "mrs_trace launch");
-}
-
 extern "C" void mrs_release_workspace(void) {
     std::lock_guard<std::mutex> lk(g_ws.mu);
-    Workspace &w = g_ws;
-    if (w.done) (void)hipEventSynchronize(w.done);
-    for (DevBuf *b : {&w.wts, &w.cond, &w.marg, &w.rowsum, &w.info, &w.lp, &w.gmarg, &w.gcond, &w.views, &w.qa_o,
-                      &w.qa_d, &w.qa_t, &w.qb_o, &w.qb_d, &w.qb_t, &w.hits, &w.so, &w.sd, &w.sc, &w.ctr, &w.sched,
-                      &w.out, &w.ct_hit, &w.ct_y, &w.ct_rr})
-        b->release();
+    if (g_ws.done) (void)hipEventSynchronize(g_ws.done);
+    g_ws.res.release_all();
+    g_ws.uploaded.clear();
 }
 
-static mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B) {
-    size_t n = (size_t)S * B;
-    TRY(t->hit.alloc(sizeof(float4) * n));
-    TRY(t->y.alloc(sizeof(float4) * n));
-    TRY(t->rr.alloc(sizeof(float) * n));
-    return MRS_OK;
-}
-
-extern "C" mrs_status mrs_render(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
-                                 const mrs_options *opt, float *d_image, mrs_tape **tape_out, void *stream) {
-    clear_error();
-    if (tape_out) *tape_out = nullptr;
-    if (!d_image) return fail(MRS_EINVAL, "mrs_render: image is NULL");
+// ============================================================================
+// plans: buffers owned per plan, launch sequences captured once and replayed
+// ============================================================================
+struct mrs_plan {
     Job job;
-    TRY(validate(scene, views, n_views, opt, job));
-    std::lock_guard<std::mutex> lk(g_ws.mu);
-    hipStream_t s = (hipStream_t)stream;
-    TRY(begin(s));
-    TRY(setup(scene, job, s));
-    // tape policy: keep per-vertex records for the adjoint when asked and affordable
-    mrs_tape *tape = nullptr;
-    if (tape_out && opt->tape_mode != MRS_TAPE_OFF) {
-        uint64_t bytes = job.S * job.op.B * kTapeRecBytes;
-        uint64_t budget = (uint64_t)opt->tape_budget;
-        if (budget == 0) {
-            size_t fr = 0, tot = 0;
-            HIPTRY(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-            budget = fr / 2;
-        }
-        if (opt->tape_mode == MRS_TAPE_ON || bytes <= budget) {
-            tape = new mrs_tape();
-            mrs_status st = tape_alloc(tape, job.S, job.op.B);
-            if (st != MRS_OK) {
-                delete tape;
-                tape = nullptr;
-                if (opt->tape_mode == MRS_TAPE_ON) return st;
-                clear_error();   // AUTO falls back to recompute
-            } else {
-                tape->samples = job.S; tape->bounces = job.op.B; tape->seed = opt->seed; tape->signature = signature(job);
-            }
-        }
+    Res res;
+    mrs_scene scene{};
+    std::vector<Chunk> fwd_chunks, bwd_chunks;
+    float *image = nullptr, *dbg_rgb = nullptr;
+    uint32_t *dbg_hash = nullptr;
+    const float *dimg = nullptr;
+    mrs_grads grads{};
+    bool has_grads = false;
+    mrs_tape *tape = nullptr;   // owned; kept when the budget allows
+    bool use_graph = false;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    ~mrs_plan() {
+        for (hipGraphExec_t &e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
+        delete tape;
     }
-    Tape tp{};
-    if (tape) { tp.hit = tape->hit.as<float4>(); tp.y = tape->y.as<float4>(); tp.rr = tape->rr.as<float>(); tp.base = 0; tp.S = job.S; }
-    mrs_status st = MRS_OK;
-    for (const Chunk &ch : make_chunks(job, kOutChunkMax)) {
-        uint32_t *hash = opt->debug_hash ? opt->debug_hash + ch.c0 : nullptr;
-        // the hash buffer is indexed from the chunk start like the output
-        st = run_wavefront(job, ch, tp, tape != nullptr, hash, s);
-        if (st != MRS_OK) break;
-        ResolveArgs ra{job.vt, g_ws.out.as<float4>(), ch.c0, ch.pix0, ch.pix1, d_image, opt->debug_sample_rgb};
-        {
-            PROF(KID_RESOLVE, s);
-            k_resolve<<<nblocks(ch.pix1 - ch.pix0, 256), 256, 0, s>>>(ra);
-        }
-    }
-    if (st == MRS_OK) st = finish(s);
-    if (st != MRS_OK) { delete tape; return st; }
-    if (tape_out) *tape_out = tape;
+};
+
+namespace {
+
+mrs_status plan_enqueue(mrs_plan *p, int pass, hipStream_t s) {
+    if (pass == 0)
+        return enqueue_forward(p->job, p->fwd_chunks, &p->scene, p->res, p->tape, p->image, p->dbg_rgb, p->dbg_hash, s);
+    return enqueue_backward(p->job, p->bwd_chunks, &p->scene, p->res, p->tape, p->dimg, &p->grads, s);
+}
+
+// capture the pass on the plan's own stream; all buffers exist already, so
+// the sequence is kernel launches only
+mrs_status plan_capture(mrs_plan *p, int pass) {
+    if (!p->cap) HIPTRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking), "hipStreamCreate");
+    HIPTRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    t_capturing = true;
+    mrs_status st = plan_enqueue(p, pass, p->cap);
+    t_capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (st != MRS_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    HIPTRY(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->exec[pass], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPTRY(e, "hipGraphInstantiate");
     return MRS_OK;
 }
 
-static mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, const float *dimg,
-                          const mrs_grads *gr, hipStream_t s) {
-    for (uint64_t a0 = c0; a0 < c1; a0 += kAdjChunk) {
-        uint64_t n = std::min<uint64_t>(kAdjChunk, c1 - a0);
-        AdjArgs aa{job.sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env};
-        {
-            PROF(KID_ADJOINT, s);
-            k_adjoint<<<nblocks(n, 256), 256, 0, s>>>(aa);
-        }
+mrs_status plan_run(mrs_plan *p, int pass, hipStream_t s) {
+    if (!p->use_graph) {
+        TRY(plan_enqueue(p, pass, s));
+        HIPTRY(hipGetLastError(), "plan launch");
+        return MRS_OK;
     }
-    HIPTRY(hipGetLastError(), "adjoint launch");
+    if (!p->exec[pass]) TRY(plan_capture(p, pass));
+    PROF(pass == 0 ? KID_PLAN_FWD : KID_PLAN_BWD, s);
+    HIPTRY(hipGraphLaunch(p->exec[pass], s), "hipGraphLaunch");
     return MRS_OK;
 }
 
-extern "C" mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
-                                          const mrs_options *opt, const float *d_grad_image, const mrs_grads *grads,
-                                          const mrs_tape *tape, void *stream) {
+}  // namespace
+
+extern "C" mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
+                                      const mrs_options *opt, float *d_image, const float *d_grad_image,
+                                      const mrs_grads *grads, int32_t use_graph, mrs_plan **out) {
     clear_error();
-    if (!d_grad_image) return fail(MRS_EINVAL, "mrs_render_backward: grad image is NULL");
-    if (!grads) return fail(MRS_EINVAL, "mrs_render_backward: grads is NULL");
-    Job job;
-    TRY(validate(scene, views, n_views, opt, job));
-    if (tape && (tape->samples != job.S || tape->bounces != job.op.B || tape->seed != opt->seed ||
-                 tape->signature != signature(job)))
-        return fail(MRS_EINVAL, "mrs_render_backward: tape was recorded for different views or options");
-    std::lock_guard<std::mutex> lk(g_ws.mu);
-    hipStream_t s = (hipStream_t)stream;
-    TRY(begin(s));
-    TRY(setup(scene, job, s));
-    if (tape) {
-        Tape tp{tape->hit.as<float4>(), tape->y.as<float4>(), tape->rr.as<float>(), 0, job.S};
-        TRY(adjoint(job, tp, 0, job.S, d_grad_image, grads, s));
-    } else {
-        // recompute: re-render chunk by chunk into a bounded tape, then replay it
-        std::vector<Chunk> chunks = make_chunks(job, std::min<uint64_t>(kOutChunkMax, job.S));
-        uint64_t cap = 0;
-        for (const Chunk &ch : chunks) cap = std::max(cap, ch.c1 - ch.c0);
-        Workspace &w = g_ws;
-        size_t n = (size_t)cap * job.op.B;
-        TRY(w.ct_hit.reserve(sizeof(float4) * n));
-        TRY(w.ct_y.reserve(sizeof(float4) * n));
-        TRY(w.ct_rr.reserve(sizeof(float) * n));
-        for (const Chunk &ch : chunks) {
-            Tape tp{w.ct_hit.as<float4>(), w.ct_y.as<float4>(), w.ct_rr.as<float>(), ch.c0, cap};
-            TRY(run_wavefront(job, ch, tp, 1, nullptr, s));
-            TRY(adjoint(job, tp, ch.c0, ch.c1, d_grad_image, grads, s));
+    if (!out) return fail(MRS_EINVAL, "mrs_plan_create: out is NULL");
+    *out = nullptr;
+    if (!d_image) return fail(MRS_EINVAL, "mrs_plan_create: image is NULL");
+    if ((grads == nullptr) != (d_grad_image == nullptr))
+        return fail(MRS_EINVAL, "mrs_plan_create: grads and grad image must both be given or both be NULL");
+    mrs_plan *p = new mrs_plan();
+    mrs_status st = validate(scene, views, n_views, opt, p->job);
+    if (st != MRS_OK) { delete p; return st; }
+    p->scene = *scene;
+    p->image = d_image;
+    p->dbg_rgb = opt->debug_sample_rgb;
+    p->dbg_hash = opt->debug_hash;
+    p->dimg = d_grad_image;
+    if (grads) { p->grads = *grads; p->has_grads = true; }
+    p->use_graph = use_graph != 0;
+    Job &job = p->job;
+    bind_scene(scene, job);
+    p->fwd_chunks = make_chunks(job, kOutChunkMax);
+    p->bwd_chunks = make_chunks(job, std::min<uint64_t>(kOutChunkMax, job.S));
+#define PTRY(x) do { st = (x); if (st != MRS_OK) { delete p; return st; } } while (0)
+    // every buffer the passes use is allocated now (captures must not allocate)
+    PTRY(hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize"));
+    PTRY(p->res.views.alloc(sizeof(ViewDev) * job.vd.size()));
+    PTRY(hip_check(hipMemcpy(p->res.views.p, job.vd.data(), sizeof(ViewDev) * job.vd.size(), hipMemcpyHostToDevice),
+                   "copy views"));
+    job.vt.v = p->res.views.as<ViewDev>();
+    job.vt.n = (int)job.vd.size();
+    PTRY(reserve_env(scene, p->res));
+    uint64_t outmax = std::max(max_chunk(p->fwd_chunks), max_chunk(p->bwd_chunks));
+    uint32_t P = (uint32_t)std::min<uint64_t>(job.pool, outmax);
+    int n_iter = 0;
+    for (const std::vector<Chunk> *cs : {&p->fwd_chunks, &p->bwd_chunks})
+        for (const Chunk &c : *cs)
+            n_iter = std::max(n_iter, iterations(job, c.c1 - c.c0, (uint32_t)std::min<uint64_t>(job.pool, c.c1 - c.c0)));
+    PTRY(reserve_pool(p->res, P, outmax, n_iter));
+    if (p->has_grads) {
+        PTRY(decide_tape(job, opt, true, &p->tape));
+        if (!p->tape) {
+            size_t n = (size_t)max_chunk(p->bwd_chunks) * job.op.B;
+            PTRY(p->res.ct_hit.alloc(sizeof(float4) * n));
+            PTRY(p->res.ct_y.alloc(sizeof(float4) * n));
+            PTRY(p->res.ct_rr.alloc(sizeof(float) * n));
         }
     }
-    return finish(s);
+#undef PTRY
+    *out = p;
+    return MRS_OK;
+}
+
+extern "C" mrs_status mrs_plan_forward(mrs_plan *plan, void *stream) {
+    clear_error();
+    if (!plan) return fail(MRS_EINVAL, "mrs_plan_forward: plan is NULL");
+    return plan_run(plan, 0, (hipStream_t)stream);
+}
+
+extern "C" mrs_status mrs_plan_backward(mrs_plan *plan, void *stream) {
+    clear_error();
+    if (!plan) return fail(MRS_EINVAL, "mrs_plan_backward: plan is NULL");
+    if (!plan->has_grads) return fail(MRS_EINVAL, "mrs_plan_backward: plan was created without gradient buffers");
+    return plan_run(plan, 1, (hipStream_t)stream);
+}
+
+extern "C" mrs_status mrs_plan_info(const mrs_plan *plan, int64_t *samples, int32_t *keeps_tape, int32_t *graph) {
+    clear_error();
+    if (!plan) return fail(MRS_EINVAL, "mrs_plan_info: plan is NULL");
+    if (samples) *samples = (int64_t)plan->job.S;
+    if (keeps_tape) *keeps_tape = plan->tape != nullptr;
+    if (graph) *graph = plan->use_graph;
+    return MRS_OK;
+}
+
+extern "C" void mrs_plan_destroy(mrs_plan *plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    delete plan;
 }

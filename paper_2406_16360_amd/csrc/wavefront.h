@@ -1,0 +1,734 @@
+// Kernels of the wavefront path tracer and of the adjoint path replay
+// (device code plus the argument bundles the host fills).  Included by
+// render.hip only.
+//
+// Forward (per super-chunk of samples, one persistent pool of P paths):
+//   iterate: schedule (refill the pool from a global sample counter) ->
+//            generate (camera rays for the new paths) ->
+//            closest hit (SoA ray queue -> hit queue) ->
+//            shade (surface interaction, material fetch, M-candidate RIS with a
+//                   streaming weighted reservoir, shadow-ray emission,
+//                   BRDF-mixture continuation, Russian roulette, wave-level
+//                   ballot/prefix-sum compaction into the next queue) ->
+//            shadow (any hit; unoccluded NEE added to the sample's radiance)
+//   then resolve the per-sample radiance into per-pixel means.
+// Backward: one thread per sample replays the path from the per-vertex tape
+// (written by the forward pass, or regenerated chunk by chunk), sweeps the
+// vertices in reverse and scatters material and env-texel gradients with
+// global float atomics.
+//
+// Paper: Sec. 3 Eqs. pbr_render / incident, Sec. 4.1 Eq. restir with the
+// reservoir rule of Appendix A, Sec. 4.2 Eqs. mc_indir / sec_bouce, and
+// Appendix A "Visibility estimation".
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "device.h"
+#include "trace.h"
+
+namespace mrs {
+namespace {
+
+// ============================================================================
+// device-side argument bundles
+// ============================================================================
+struct IterCtr {
+    uint32_t n_in;       // continuing paths entering the iteration
+    uint32_t n_new;      // camera paths generated in the iteration
+    uint32_t n_live;     // n_in + n_new
+    uint32_t n_shadow;   // shadow rays emitted by the iteration's shade
+    uint64_t gen_base;   // first sample index generated in the iteration
+};
+struct Sched { uint64_t next, end; };
+
+struct SceneDev {
+    const int32_t *faces;
+    const float *uv, *vmat, *albedo, *rough, *metal;
+    int mat_mode, tw, th;
+    const BvhNode *nodes;
+    const TriRec *tris;
+    EnvTables env;
+};
+
+struct Opts {
+    int B, M, Mb, rr_start, spec, background, grad_mode;
+    uint32_t k0, k1;
+};
+
+struct Queue { float4 *o, *d, *t; };   // o.w = sample id, d.w = vertex k, t = throughput
+
+struct Tape {
+    float4 *hit;   // [B][S]: (b1, b2, leaf, env texel)
+    float4 *y;     // [B][S]: (y, W when unoccluded else 0)
+    float *rr;     // [B][S]: continuation factor, 0 = path ended
+    uint64_t base; // sample index of entry 0
+    uint64_t S;    // samples per vertex slice
+};
+
+struct ViewTable {
+    const ViewDev *v;
+    int n;
+};
+
+// ============================================================================
+// small helpers
+// ============================================================================
+__device__ __forceinline__ int find_view(const ViewTable &vt, uint64_t g) {
+    int lo = 0, hi = vt.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (vt.v[mid].sample_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct SampleId { int view; uint32_t pixel, sample; };
+__device__ __forceinline__ SampleId decode(const ViewTable &vt, uint64_t g) {
+    SampleId s;
+    s.view = find_view(vt, g);
+    const ViewDev &v = vt.v[s.view];
+    uint64_t local = g - v.sample_base;
+    s.pixel = (uint32_t)(local / (uint64_t)v.spp);
+    s.sample = v.sample_offset + (uint32_t)(local % (uint64_t)v.spp);
+    return s;
+}
+
+// pinhole camera ray in double, rounded once to float
+__device__ __forceinline__ void camera_ray(const ViewDev &v, uint32_t pixel, float u0, float u1, V3 &o, V3 &d) {
+    double x = (double)(pixel % (uint32_t)v.w), y = (double)(pixel / (uint32_t)v.w);
+    double nx = 2.0 * (x + (double)u0) / v.w - 1.0;
+    double ny = 1.0 - 2.0 * (y + (double)u1) / v.h;
+    double dc[3] = {nx * v.tan_half * v.aspect, ny * v.tan_half, -1.0};
+    double w[3];
+    for (int r = 0; r < 3; ++r)
+        w[r] = (double)v.rot[3 * r] * dc[0] + (double)v.rot[3 * r + 1] * dc[1] + (double)v.rot[3 * r + 2] * dc[2];
+    double l = 1.0 / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    d = V3{(float)(w[0] * l), (float)(w[1] * l), (float)(w[2] * l)};
+    o = V3{v.org[0], v.org[1], v.org[2]};
+}
+
+struct Interp { int idx[4]; float w[4]; int n; };
+struct MatRaw { V3 a; float r, mu; };
+
+__device__ __forceinline__ int wrapi(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+
+// affine interpolation: equal inputs give that value exactly, so a material
+// sitting on a clamp boundary stays on it (the clamp's derivative mask then
+// agrees with any other evaluation order)
+__device__ __forceinline__ float bary(float x0, float x1, float x2, float b1, float b2) {
+    return x0 + b1 * (x1 - x0) + b2 * (x2 - x0);
+}
+__device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f * (b - a); }
+__device__ __forceinline__ float bilerp(float x00, float x10, float x01, float x11, float fx, float fy) {
+    return lerpf(lerpf(x00, x10, fx), lerpf(x01, x11, fx), fy);
+}
+
+// material at a hit: per-vertex attributes by barycentrics, or bilinear
+// textures (texel centres at (i + 1/2) / W, wrap) at the interpolated uv.
+// ip receives the indices and the linear weights used by the adjoint.
+__device__ __forceinline__ MatRaw fetch_material(const SceneDev &s, int prim, float b1, float b2, Interp &ip) {
+    int v0 = s.faces[3 * prim], v1 = s.faces[3 * prim + 1], v2 = s.faces[3 * prim + 2];
+    MatRaw m;
+    if (s.mat_mode == MRS_MAT_VERTEX) {
+        ip.n = 3;
+        ip.idx[0] = v0; ip.idx[1] = v1; ip.idx[2] = v2; ip.idx[3] = v0;
+        ip.w[0] = 1.0f - b1 - b2; ip.w[1] = b1; ip.w[2] = b2; ip.w[3] = 0.0f;
+        const float *p0 = s.vmat + 5 * (size_t)v0, *p1 = s.vmat + 5 * (size_t)v1, *p2 = s.vmat + 5 * (size_t)v2;
+        m.a = V3{bary(p0[0], p1[0], p2[0], b1, b2), bary(p0[1], p1[1], p2[1], b1, b2), bary(p0[2], p1[2], p2[2], b1, b2)};
+        m.r = bary(p0[3], p1[3], p2[3], b1, b2);
+        m.mu = bary(p0[4], p1[4], p2[4], b1, b2);
+        return m;
+    }
+    float u = bary(s.uv[2 * v0], s.uv[2 * v1], s.uv[2 * v2], b1, b2);
+    float v = bary(s.uv[2 * v0 + 1], s.uv[2 * v1 + 1], s.uv[2 * v2 + 1], b1, b2);
+    float x = u * (float)s.tw - 0.5f, y = v * (float)s.th - 0.5f;
+    float x0 = floorf(x), y0 = floorf(y);
+    float fx = x - x0, fy = y - y0;
+    int i0 = wrapi((int)x0, s.tw), i1 = wrapi((int)x0 + 1, s.tw);
+    int j0 = wrapi((int)y0, s.th), j1 = wrapi((int)y0 + 1, s.th);
+    ip.n = 4;
+    ip.idx[0] = j0 * s.tw + i0; ip.w[0] = (1.0f - fx) * (1.0f - fy);
+    ip.idx[1] = j0 * s.tw + i1; ip.w[1] = fx * (1.0f - fy);
+    ip.idx[2] = j1 * s.tw + i0; ip.w[2] = (1.0f - fx) * fy;
+    ip.idx[3] = j1 * s.tw + i1; ip.w[3] = fx * fy;
+    const float *a0 = s.albedo + 3 * (size_t)ip.idx[0], *a1 = s.albedo + 3 * (size_t)ip.idx[1];
+    const float *a2 = s.albedo + 3 * (size_t)ip.idx[2], *a3 = s.albedo + 3 * (size_t)ip.idx[3];
+    m.a = V3{bilerp(a0[0], a1[0], a2[0], a3[0], fx, fy), bilerp(a0[1], a1[1], a2[1], a3[1], fx, fy),
+             bilerp(a0[2], a1[2], a2[2], a3[2], fx, fy)};
+    m.r = bilerp(s.rough[ip.idx[0]], s.rough[ip.idx[1]], s.rough[ip.idx[2]], s.rough[ip.idx[3]], fx, fy);
+    m.mu = bilerp(s.metal[ip.idx[0]], s.metal[ip.idx[1]], s.metal[ip.idx[2]], s.metal[ip.idx[3]], fx, fy);
+    return m;
+}
+
+__device__ __forceinline__ Mat clamp_material(const MatRaw &r) {
+    Mat m;
+    m.a = V3{fminf(fmaxf(r.a.x, 0.0f), 1.0f), fminf(fmaxf(r.a.y, 0.0f), 1.0f), fminf(fmaxf(r.a.z, 0.0f), 1.0f)};
+    m.r = fminf(fmaxf(r.r, kRoughMin), 1.0f);
+    m.mu = fminf(fmaxf(r.mu, 0.0f), 1.0f);
+    return m;
+}
+
+struct Surf { V3 p, n; Frame F; int prim; };
+__device__ __forceinline__ Surf surface(const SceneDev &s, int leaf, float b1, float b2, V3 d) {
+    TriRec tr = s.tris[leaf];
+    V3 a = xyz(tr.a), b = xyz(tr.b), c = xyz(tr.c);
+    Surf S;
+    S.prim = __float_as_int(tr.a.w);
+    float b0 = 1.0f - b1 - b2;
+    S.p = a * b0 + b * b1 + c * b2;
+    V3 ng = normalize(cross(b - a, c - a));
+    if (dot(ng, d) > 0.0f) ng = ng * -1.0f;
+    S.n = ng;
+    S.F = make_frame(ng);
+    return S;
+}
+
+__device__ __forceinline__ V3 spawn(V3 p, V3 n) {
+    float pn = fmaxf(fabsf(p.x), fmaxf(fabsf(p.y), fabsf(p.z)));
+    return p + n * (1e-4f * fmaxf(1.0f, pn));
+}
+
+// ballot / prefix-sum append: one atomic per wave
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return 0;
+    int lane = __lane_id();
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    uint64_t below = lane == 0 ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+    return base + (uint32_t)__popcll(below);
+}
+
+// decision-hash events (XOR-combined per sample)
+__device__ __forceinline__ uint32_t ev_vertex(uint32_t k, uint32_t prim, uint32_t sel, uint32_t cont) {
+    return fnv_word(fnv_word(fnv_word(fnv_word(kFnvBasis, k), prim), sel), cont);
+}
+__device__ __forceinline__ uint32_t ev_miss(uint32_t k) { return fnv_word(fnv_word(kFnvBasis, k), 0xFFFFFFFFu); }
+__device__ __forceinline__ uint32_t ev_nee(uint32_t k, uint32_t vis) { return fnv_word(fnv_word(kFnvBasis, k | 0x10000u), vis); }
+__device__ __forceinline__ uint32_t ev_cand(uint32_t k, uint32_t s, uint32_t lobe, uint32_t tex) {
+    return fnv_word(fnv_word(fnv_word(fnv_word(kFnvBasis, k | 0x20000u), s), lobe), tex);
+}
+
+// ============================================================================
+// environment tables (rebuilt every call: the env map is a trainable input)
+// ============================================================================
+// Row i: texel weights w_ij = mean_c max(0, L) * sin(pi (i + 1/2) / H), prefix
+// sums in double, conditional CDF normalised by the row sum.
+__global__ void k_env_rows(const float *__restrict__ env, int W, int H, double *__restrict__ wts,
+                           double *__restrict__ cond, double *__restrict__ rowsum) {
+    __shared__ double part[256];
+    int i = blockIdx.x;
+    double st = sin(3.14159265358979323846 * (i + 0.5) / H);
+    double carry = 0.0;
+    double *cr = cond + (size_t)i * (W + 1);
+    if (threadIdx.x == 0) cr[0] = 0.0;
+    for (int base = 0; base < W; base += 256) {
+        int j = base + threadIdx.x;
+        double w = 0.0;
+        if (j < W) {
+            const float *L = env + ((size_t)i * W + j) * 3;
+            double m = (double)fmaxf(L[0], 0.0f) + (double)fmaxf(L[1], 0.0f) + (double)fmaxf(L[2], 0.0f);
+            w = (m / 3.0) * st;
+            wts[(size_t)i * W + j] = w;
+        }
+        part[threadIdx.x] = w;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {      // inclusive Hillis-Steele scan
+            double v = threadIdx.x >= off ? part[threadIdx.x - off] : 0.0;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (j < W) cr[j + 1] = carry + part[threadIdx.x];
+        double tot = part[255];
+        __syncthreads();
+        carry += tot;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x + 1; j <= W; j += 256) cr[j] = carry > 0.0 ? cr[j] / carry : cr[j];
+    __syncthreads();
+    if (threadIdx.x == 0) { cr[W] = 1.0; rowsum[i] = carry; }
+}
+
+__global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__restrict__ marg, double *__restrict__ info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    marg[0] = 0.0;
+    for (int i = 0; i < H; ++i) { acc += rowsum[i]; marg[i + 1] = acc; }
+    for (int i = 1; i <= H; ++i) marg[i] = acc > 0.0 ? marg[i] / acc : marg[i];
+    marg[H] = 1.0;
+    info[0] = acc;
+}
+
+// radiance + pdf table and the guide tables of both CDFs
+__global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
+                             const double *__restrict__ info, const double *__restrict__ marg,
+                             const double *__restrict__ cond, float4 *__restrict__ lp, int32_t *__restrict__ gmarg,
+                             int32_t *__restrict__ gcond) {
+    int i = blockIdx.x;
+    double total = info[0];
+    double scale = total > 0.0 ? (double)W * (double)H / (2.0 * 3.14159265358979323846 * 3.14159265358979323846 * total) : 0.0;
+    if (i < H) {
+        const double *cr = cond + (size_t)i * (W + 1);
+        for (int j = threadIdx.x; j < W; j += blockDim.x) {
+            const float *L = env + ((size_t)i * W + j) * 3;
+            lp[(size_t)i * W + j] = make_float4(fmaxf(L[0], 0.0f), fmaxf(L[1], 0.0f), fmaxf(L[2], 0.0f),
+                                                (float)(wts[(size_t)i * W + j] * scale));
+            double t = (double)j / W;
+            int lo = 0, hi = W - 1;   // smallest c with cr[c + 1] > t
+            while (lo < hi) { int mid = (lo + hi) >> 1; if (cr[mid + 1] > t) hi = mid; else lo = mid + 1; }
+            gcond[(size_t)i * W + j] = lo;
+        }
+    } else {
+        for (int t0 = threadIdx.x; t0 < H; t0 += blockDim.x) {
+            double t = (double)t0 / H;
+            int lo = 0, hi = H - 1;
+            while (lo < hi) { int mid = (lo + hi) >> 1; if (marg[mid + 1] > t) hi = mid; else lo = mid + 1; }
+            gmarg[t0] = lo;
+        }
+    }
+}
+
+// ============================================================================
+// wavefront kernels
+// ============================================================================
+__global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_schedule(IterCtr *__restrict__ ctr, int it, Sched *__restrict__ sched, uint32_t P) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t n_in = ctr[it].n_in;
+    uint64_t rem = sched->end - sched->next;
+    uint32_t n_new = (uint32_t)std::min<uint64_t>(rem, (uint64_t)(P - n_in));
+    ctr[it].n_new = n_new;
+    ctr[it].n_live = n_in + n_new;
+    ctr[it].gen_base = sched->next;
+    sched->next += n_new;
+}
+
+struct GenArgs {
+    ViewTable vt; Opts op; Queue q; IterCtr *ctr; int it;
+    float4 *out; uint64_t out_base; uint32_t *hash;
+};
+
+__global__ void k_generate(GenArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const IterCtr c = a.ctr[a.it];
+    if (i >= c.n_new) return;
+    uint64_t g = c.gen_base + i;
+    SampleId sid = decode(a.vt, g);
+    Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
+    float4 u = rng.draw(0, 0);
+    V3 o, d;
+    camera_ray(a.vt.v[sid.view], sid.pixel, u.x, u.y, o, d);
+    uint32_t slot = c.n_in + i;
+    a.q.o[slot] = make_float4(o.x, o.y, o.z, __uint_as_float((uint32_t)g));
+    a.q.d[slot] = make_float4(d.x, d.y, d.z, __int_as_float(1));
+    a.q.t[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    a.out[g - a.out_base] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (a.hash) a.hash[g - a.out_base] = 0u;
+}
+
+struct TraceArgs {
+    const BvhNode *nodes; const TriRec *tris;
+    Queue q; float4 *hits; IterCtr *ctr; int it;
+};
+
+__global__ void k_trace_closest(TraceArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.ctr[a.it].n_live) return;
+    float4 o = a.q.o[i], d = a.q.d[i];
+    Hit h = trace_closest(a.nodes, a.tris, xyz(o), xyz(d));
+    a.hits[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf));
+}
+
+struct ShadeArgs {
+    SceneDev s; ViewTable vt; Opts op;
+    Queue q, qn; float4 *hits; IterCtr *ctr; int it;
+    float4 *so, *sd, *sc;          // shadow queue: origin (w = sample), dir (w = k), contribution
+    float4 *out; uint64_t out_base; uint32_t *hash;
+    Tape tape; int use_tape;
+};
+
+__global__ void k_shade(ShadeArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = a.ctr[a.it].n_live;
+    const bool active = i < n;
+    bool emit = false, cont = false;
+    float4 e_o, e_d, e_c, c_o, c_d, c_t;
+    if (active) {
+        float4 po = a.q.o[i], pd = a.q.d[i], pt = a.q.t[i], hr = a.hits[i];
+        uint32_t g = __float_as_uint(po.w);
+        int k = __float_as_int(pd.w);
+        V3 d = xyz(pd), T = xyz(pt);
+        int leaf = __float_as_int(hr.w);
+        uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
+        uint32_t hev;
+        if (leaf < 0) {
+            int tex = -1;
+            if (k == 1 && a.op.background == MRS_BG_ENV) {
+                tex = env_texel_of(a.s.env, d);
+                float4 L = a.s.env.lp[tex];
+                a.out[g - a.out_base] = make_float4(L.x, L.y, L.z, 0.0f);
+            }
+            hev = ev_miss((uint32_t)k);
+            if (a.use_tape) {
+                a.tape.hit[ti] = make_float4(0.0f, 0.0f, __int_as_float(-1), __int_as_float(tex));
+                a.tape.y[ti] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                a.tape.rr[ti] = 0.0f;
+            }
+        } else {
+            SampleId sid = decode(a.vt, g);
+            Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
+            float b1 = hr.y, b2 = hr.z;
+            Surf S = surface(a.s, leaf, b1, b2, d);
+            Interp ip;
+            Mat m = clamp_material(fetch_material(a.s, S.prim, b1, b2, ip));
+            V3 wo = to_local(S.F, d * -1.0f);
+            Lobe L = make_lobe(m, wo, a.op.spec);
+            V3 org = spawn(S.p, S.n);
+            const int Me = a.op.M - a.op.Mb, Mb = a.op.Mb;
+            // ---- RIS over Me env + Mb BRDF candidates, streaming WRS ----
+            uint32_t hcand = 0;   // hash events of the BRDF candidates
+            float wsum = 0.0f, phat_y = 0.0f, cos_y = 0.0f;
+            V3 y = V3{0, 0, 0}, fy = V3{0, 0, 0}, Ly = V3{0, 0, 0};
+            int sel = -1, ytex = -1;
+            if (wo.z > 0.0f) {
+                for (int s = 0; s < a.op.M; ++s) {
+                    float4 u = rng.draw((uint32_t)k, (uint32_t)s);
+                    V3 dir, wl;
+                    int tex;
+                    float4 lp;
+                    float qe, qb;
+                    if (s < Me) {
+                        if (!env_sample(a.s.env, u.x, u.y, dir, tex, lp, qe)) continue;
+                        wl = to_local(S.F, dir);
+                        qb = mix_pdf(L, wl);
+                    } else {
+                        int lb = mix_sample(L, u.x, u.y, u.z, wl);
+                        if (!lb) continue;
+                        dir = to_world(S.F, wl);
+                        qb = mix_pdf(L, wl);
+                        tex = env_texel_of(a.s.env, dir);
+                        if (a.hash) hcand ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
+                        lp = a.s.env.lp[tex];
+                        qe = env_pdf_dir(a.s.env, dir, tex, lp);
+                    }
+                    if (!(wl.z > 0.0f)) continue;
+                    V3 f = brdf_eval(L, wl);
+                    float phat = (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
+                    float den = (float)Me * qe + (float)Mb * qb;
+                    if (!(phat > 0.0f) || !(den > 0.0f)) continue;
+                    float w = phat / den;
+                    wsum += w;
+                    if (u.w < w / wsum) {
+                        sel = s; y = dir; fy = f; Ly = V3{lp.x, lp.y, lp.z}; phat_y = phat; ytex = tex; cos_y = wl.z;
+                    }
+                }
+            }
+            float Wy = 0.0f;
+            if (sel >= 0) {
+                Wy = wsum / phat_y;
+                emit = true;
+                V3 cc = T * Ly * fy * (cos_y * Wy);
+                e_o = make_float4(org.x, org.y, org.z, __uint_as_float(g));
+                e_d = make_float4(y.x, y.y, y.z, __int_as_float(k));
+                e_c = make_float4(cc.x, cc.y, cc.z, 0.0f);
+            }
+            // ---- continuation (BRDF mixture), Russian roulette ----
+            uint32_t code = 0;
+            float rrf = 0.0f;
+            if (k < a.op.B) {
+                code = 2;
+                float4 u = rng.draw((uint32_t)k, kBlockCont);
+                V3 wl;
+                int lobe = wo.z > 0.0f ? mix_sample(L, u.x, u.y, u.z, wl) : 0;
+                float q = lobe ? mix_pdf(L, wl) : 0.0f;
+                if (lobe && q > 0.0f) {
+                    V3 f = brdf_eval(L, wl);
+                    V3 Tn = T * f * (wl.z / q);
+                    bool alive = true;
+                    rrf = 1.0f;
+                    if (a.op.rr_start >= 0 && k >= a.op.rr_start) {
+                        float qr = fminf(0.95f, maxc(Tn));
+                        if (!(qr > 0.0f) || !(u.w < qr)) { alive = false; code = 3; rrf = 0.0f; }
+                        else { Tn = Tn * (1.0f / qr); rrf = 1.0f / qr; }
+                    }
+                    if (alive) {
+                        code = lobe == 2 ? 4 : 1;
+                        cont = true;
+                        V3 wn = to_world(S.F, wl);
+                        c_o = make_float4(org.x, org.y, org.z, __uint_as_float(g));
+                        c_d = make_float4(wn.x, wn.y, wn.z, __int_as_float(k + 1));
+                        c_t = make_float4(Tn.x, Tn.y, Tn.z, 0.0f);
+                    }
+                }
+            }
+            hev = ev_vertex((uint32_t)k, (uint32_t)S.prim, (uint32_t)sel, code) ^ hcand;
+            if (a.use_tape) {
+                a.tape.hit[ti] = make_float4(b1, b2, __int_as_float(leaf), __int_as_float(ytex));
+                a.tape.y[ti] = make_float4(y.x, y.y, y.z, Wy);
+                a.tape.rr[ti] = cont ? rrf : 0.0f;
+            }
+        }
+        if (a.hash) a.hash[g - a.out_base] ^= hev;
+    }
+    // compaction: wave-aggregated appends (all lanes reach this point)
+    uint32_t si = wave_append(&a.ctr[a.it].n_shadow, emit);
+    if (emit) { a.so[si] = e_o; a.sd[si] = e_d; a.sc[si] = e_c; }
+    uint32_t ci = wave_append(&a.ctr[a.it + 1].n_in, cont);
+    if (cont) { a.qn.o[ci] = c_o; a.qn.d[ci] = c_d; a.qn.t[ci] = c_t; }
+}
+
+struct ShadowArgs {
+    const BvhNode *nodes; const TriRec *tris;
+    float4 *so, *sd, *sc; IterCtr *ctr; int it;
+    float4 *out; uint64_t out_base; uint32_t *hash;
+    Tape tape; int use_tape;
+};
+
+__global__ void k_trace_shadow(ShadowArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.ctr[a.it].n_shadow) return;
+    float4 o = a.so[i], d = a.sd[i];
+    uint32_t g = __float_as_uint(o.w);
+    int k = __float_as_int(d.w);
+    bool occl = trace_any(a.nodes, a.tris, xyz(o), xyz(d));
+    if (!occl) {
+        float4 c = a.sc[i];
+        float4 &acc = a.out[g - a.out_base];
+        acc = make_float4(acc.x + c.x, acc.y + c.y, acc.z + c.z, 0.0f);
+    } else if (a.use_tape) {
+        a.tape.y[(uint64_t)(k - 1) * a.tape.S + (g - a.tape.base)].w = 0.0f;
+    }
+    if (a.hash) a.hash[g - a.out_base] ^= ev_nee((uint32_t)k, occl ? 0u : 1u);
+}
+
+struct ResolveArgs {
+    ViewTable vt; const float4 *out; uint64_t out_base;
+    uint64_t pix0, pix1;      // global (view-order) pixel range of the chunk
+    float *image; float *dbg_rgb;
+};
+
+__device__ __forceinline__ int find_view_pix(const ViewTable &vt, uint64_t P) {
+    int lo = 0, hi = vt.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (vt.v[mid].pix_base <= P) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// pixel = mean of its spp samples, summed in sample order (deterministic)
+__global__ void k_resolve(ResolveArgs a) {
+    uint64_t P = a.pix0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (P >= a.pix1) return;
+    const ViewDev &v = a.vt.v[find_view_pix(a.vt, P)];
+    uint64_t p = P - v.pix_base;
+    uint64_t g0 = v.sample_base + p * (uint64_t)v.spp - a.out_base;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    for (int s = 0; s < v.spp; ++s) {
+        float4 c = a.out[g0 + s];
+        sx += c.x; sy += c.y; sz += c.z;
+        if (a.dbg_rgb) {
+            float *dst = a.dbg_rgb + 3 * (g0 + a.out_base + s);
+            dst[0] = c.x; dst[1] = c.y; dst[2] = c.z;
+        }
+    }
+    float inv = 1.0f / (float)v.spp;
+    float *img = a.image + 3 * (uint64_t)(v.pixel_offset + (int64_t)p);
+    img[0] = sx * inv; img[1] = sy * inv; img[2] = sz * inv;
+}
+
+// ============================================================================
+// adjoint path replay
+// ============================================================================
+struct AdjArgs {
+    SceneDev s; ViewTable vt; Opts op; Tape tape;
+    uint64_t g0, n;
+    const float *dimg;
+    float *gvmat, *galb, *grough, *gmetal, *genv;
+};
+
+__device__ __forceinline__ void scatter_material(const AdjArgs &a, const Interp &ip, const MatRaw &raw,
+                                                 V3 ga, float gr, float gmu) {
+    // clamp masks: the derivative passes on the closed interval
+    float ma[3] = {(raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f,
+                   (raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f,
+                   (raw.a.z >= 0.0f && raw.a.z <= 1.0f) ? ga.z : 0.0f};
+    float mr = (raw.r >= kRoughMin && raw.r <= 1.0f) ? gr : 0.0f;
+    float mm = (raw.mu >= 0.0f && raw.mu <= 1.0f) ? gmu : 0.0f;
+    if (a.s.mat_mode == MRS_MAT_VERTEX) {
+        if (!a.gvmat) return;
+        for (int q = 0; q < 3; ++q) {
+            float w = ip.w[q];
+            float *dst = a.gvmat + 5 * (size_t)ip.idx[q];
+            if (ma[0] != 0.0f) atomicAdd(dst + 0, w * ma[0]);
+            if (ma[1] != 0.0f) atomicAdd(dst + 1, w * ma[1]);
+            if (ma[2] != 0.0f) atomicAdd(dst + 2, w * ma[2]);
+            if (mr != 0.0f) atomicAdd(dst + 3, w * mr);
+            if (mm != 0.0f) atomicAdd(dst + 4, w * mm);
+        }
+        return;
+    }
+    for (int q = 0; q < 4; ++q) {
+        float w = ip.w[q];
+        if (w == 0.0f) continue;
+        size_t t = (size_t)ip.idx[q];
+        if (a.galb) {
+            if (ma[0] != 0.0f) atomicAdd(a.galb + 3 * t + 0, w * ma[0]);
+            if (ma[1] != 0.0f) atomicAdd(a.galb + 3 * t + 1, w * ma[1]);
+            if (ma[2] != 0.0f) atomicAdd(a.galb + 3 * t + 2, w * ma[2]);
+        }
+        if (a.grough && mr != 0.0f) atomicAdd(a.grough + t, w * mr);
+        if (a.gmetal && mm != 0.0f) atomicAdd(a.gmetal + t, w * mm);
+    }
+}
+
+__device__ __forceinline__ void scatter_env(const AdjArgs &a, int tex, V3 g) {
+    if (!a.genv || tex < 0) return;
+    const float *raw = a.s.env.raw + 3 * (size_t)tex;
+    if (raw[0] >= 0.0f && g.x != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 0, g.x);
+    if (raw[1] >= 0.0f && g.y != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 1, g.y);
+    if (raw[2] >= 0.0f && g.z != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 2, g.z);
+}
+
+// Detached-sampling gradient of one sample: with directions, selections and
+// all pdf / reservoir weights held fixed, C = sum_k T_k (.) D_k and
+// T_{k+1} = T_k (.) beta_k, so dC/dm_k = T_k (.) (dD_k/dm_k + dbeta_k/dm_k (.) Li_{k+1})
+// with Li_k = D_k + beta_k (.) Li_{k+1} accumulated from the last vertex back.
+__global__ void k_adjoint(AdjArgs a) {
+    uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    uint64_t g = a.g0 + j;
+    SampleId sid = decode(a.vt, g);
+    const ViewDev &vw = a.vt.v[sid.view];
+    Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
+    const float *gi = a.dimg + 3 * (uint64_t)(vw.pixel_offset + (int64_t)sid.pixel);
+    float inv_spp = 1.0f / (float)vw.spp;
+    V3 gp = V3{gi[0] * inv_spp, gi[1] * inv_spp, gi[2] * inv_spp};
+    if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return;
+    float4 u = rng.draw(0, 0);
+    V3 o, d;
+    camera_ray(vw, sid.pixel, u.x, u.y, o, d);
+    const int B = a.op.B;
+    V3 Dk[MRS_MAX_BOUNCES], Bk[MRS_MAX_BOUNCES], Lk[MRS_MAX_BOUNCES], dk[MRS_MAX_BOUNCES];
+    int nv = 0;
+    // pass 1: per-vertex direct term D_k and continuation weight beta_k
+    for (int k = 1; k <= B; ++k) {
+        uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
+        float4 th = a.tape.hit[ti];
+        int leaf = __float_as_int(th.z);
+        if (leaf < 0) {
+            if (k == 1) scatter_env(a, __float_as_int(th.w), gp);
+            break;
+        }
+        dk[k - 1] = d;
+        Surf S = surface(a.s, leaf, th.x, th.y, d);
+        Interp ip;
+        Mat m = clamp_material(fetch_material(a.s, S.prim, th.x, th.y, ip));
+        Lobe L = make_lobe(m, to_local(S.F, d * -1.0f), a.op.spec);
+        float4 ty = a.tape.y[ti];
+        V3 D = V3{0, 0, 0};
+        if (ty.w > 0.0f) {
+            V3 yl = to_local(S.F, xyz(ty));
+            V3 f = brdf_eval(L, yl);
+            float4 lp = a.s.env.lp[__float_as_int(th.w)];
+            D = V3{lp.x, lp.y, lp.z} * f * (yl.z * ty.w);
+        }
+        Dk[k - 1] = D;
+        Bk[k - 1] = V3{0, 0, 0};
+        nv = k;
+        float rr = a.tape.rr[ti];
+        if (!(rr > 0.0f) || k == B) break;
+        float4 uc = rng.draw((uint32_t)k, kBlockCont);
+        V3 wl;
+        mix_sample(L, uc.x, uc.y, uc.z, wl);
+        float q = mix_pdf(L, wl);
+        if (!(q > 0.0f)) break;
+        Bk[k - 1] = brdf_eval(L, wl) * (wl.z / q * rr);
+        d = to_world(S.F, wl);
+    }
+    // suffix radiance Li_{k+1}
+    V3 Li = V3{0, 0, 0};
+    for (int k = nv; k >= 1; --k) {
+        Lk[k - 1] = Li;
+        Li = Dk[k - 1] + Bk[k - 1] * Li;
+    }
+    // pass 2: local derivatives, scattered through interpolation weights
+    V3 T = V3{1, 1, 1};
+    for (int k = 1; k <= nv; ++k) {
+        if (a.op.grad_mode == MRS_GRAD_PRIMARY && k > 1) break;
+        uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
+        float4 th = a.tape.hit[ti];
+        int leaf = __float_as_int(th.z);
+        V3 dd = dk[k - 1];
+        Surf S = surface(a.s, leaf, th.x, th.y, dd);
+        Interp ip;
+        MatRaw raw = fetch_material(a.s, S.prim, th.x, th.y, ip);
+        Mat m = clamp_material(raw);
+        Lobe L = make_lobe(m, to_local(S.F, dd * -1.0f), a.op.spec);
+        V3 ga = V3{0, 0, 0};
+        float gr = 0.0f, gmu = 0.0f;
+        V3 w = gp * T;   // dL/dC weighted by throughput
+        float4 ty = a.tape.y[ti];
+        if (ty.w > 0.0f) {
+            V3 yl = to_local(S.F, xyz(ty));
+            int tex = __float_as_int(th.w);
+            float4 lp = a.s.env.lp[tex];
+            V3 Lv = V3{lp.x, lp.y, lp.z};
+            float cw = yl.z * ty.w;
+            BrdfGrad bg = brdf_grad(L, m, yl);
+            V3 wl = w * Lv * cw;
+            ga = ga + wl * bg.da;
+            gr += dot(wl, bg.dr);
+            gmu += dot(wl, bg.dmu);
+            V3 f = brdf_eval(L, yl);
+            scatter_env(a, tex, w * f * cw);
+        }
+        if (k < nv) {
+            float rr = a.tape.rr[ti];
+            float4 uc = rng.draw((uint32_t)k, kBlockCont);
+            V3 wl;
+            mix_sample(L, uc.x, uc.y, uc.z, wl);
+            float q = mix_pdf(L, wl);
+            if (q > 0.0f) {
+                BrdfGrad bg = brdf_grad(L, m, wl);
+                V3 wb = w * Lk[k - 1] * (wl.z / q * rr);
+                ga = ga + wb * bg.da;
+                gr += dot(wb, bg.dr);
+                gmu += dot(wb, bg.dmu);
+            }
+        }
+        scatter_material(a, ip, raw, ga, gr, gmu);
+        T = T * Bk[k - 1];
+    }
+}
+
+__global__ void k_trace_batch(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+                              const float *__restrict__ orig, const float *__restrict__ dir, int64_t n, int any,
+                              float4 *__restrict__ out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    V3 o = ld3(orig + 3 * i), d = ld3(dir + 3 * i);
+    if (any) {
+        bool h = trace_any(nodes, tris, o, d);
+        out[i] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(h ? 0 : -1));
+    } else {
+        Hit h = trace_closest(nodes, tris, o, d);
+        out[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf >= 0 ? h.prim : -1));
+    }
+}
+
+__global__ void k_set_sched(Sched *s, uint64_t a, uint64_t b) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) { s->next = a; s->end = b; }
+}
+
+}  // namespace
+}  // namespace mrs

@@ -58,6 +58,7 @@ class _Grads(C.Structure):
 
 # the C-ABI symbols declared in include/mirres.h
 EXPORTS = ["mrs_build_bvh", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
+           "mrs_plan_create", "mrs_plan_forward", "mrs_plan_backward", "mrs_plan_info", "mrs_plan_destroy",
            "mrs_tape_bytes", "mrs_tape_destroy", "mrs_profile_begin", "mrs_profile_end", "mrs_release_workspace",
            "mrs_last_error"]
 
@@ -91,6 +92,16 @@ def _load():
     lib.mrs_profile_begin.argtypes = []
     lib.mrs_profile_end.restype = i32
     lib.mrs_profile_end.argtypes = [p, i32, C.POINTER(i32)]
+    lib.mrs_plan_create.restype = i32
+    lib.mrs_plan_create.argtypes = [C.POINTER(_Scene), p, i32, C.POINTER(_Options), p, p, C.POINTER(_Grads), i32,
+                                    C.POINTER(p)]
+    lib.mrs_plan_forward.restype = i32
+    lib.mrs_plan_forward.argtypes = [p, p]
+    lib.mrs_plan_backward.restype = i32
+    lib.mrs_plan_backward.argtypes = [p, p]
+    lib.mrs_plan_info.restype = i32
+    lib.mrs_plan_info.argtypes = [p, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
+    lib.mrs_plan_destroy.argtypes = [p]
     lib.mrs_last_error.restype = C.c_char_p
     return lib
 
@@ -329,6 +340,72 @@ def tape_bytes(views: Sequence, opts) -> int:
     vs, _, _ = views_struct(views)
     op = RenderOptions.from_any(opts).struct()
     return int(_lib.mrs_tape_bytes(C.addressof(vs), len(views), C.byref(op)))
+
+
+class Plan:
+    """A planned render (+ adjoint) over fixed views and bound tensors.
+
+    All views share one persistent path pool; with use_graph each pass is
+    captured once into a hipGraph and replayed.  The scene tensors, the image,
+    the grad image and the gradient buffers are bound at creation: update
+    their contents in place between passes (never rebind them)."""
+
+    def __init__(self, scene: GpuScene, views: Sequence, opts, with_grad: bool = False, use_graph: bool = True,
+                 debug: bool = False):
+        self.scene, self.views = scene, list(views)
+        self.opts = RenderOptions.from_any(opts)
+        vs, npix, self.offsets = views_struct(self.views)
+        dev = scene.pos.device
+        self.image = torch.zeros((npix, 3), dtype=torch.float32, device=dev)
+        self.dbg_rgb = self.dbg_hash = None
+        if debug:
+            S = total_samples(self.views)
+            self.dbg_rgb = torch.zeros((S, 3), dtype=torch.float32, device=dev)
+            self.dbg_hash = torch.zeros((S,), dtype=torch.int32, device=dev)
+        self.grad_image = None
+        self.grads: Dict[str, torch.Tensor] = {}
+        g = None
+        if with_grad:
+            self.grad_image = torch.zeros_like(self.image)
+            self.grads["env"] = torch.zeros_like(scene.env)
+            if scene.mat_mode == MAT_VERTEX:
+                self.grads["vmat"] = torch.zeros_like(scene.vmat)
+            else:
+                self.grads.update(albedo=torch.zeros_like(scene.albedo), rough=torch.zeros_like(scene.rough),
+                                  metal=torch.zeros_like(scene.metal))
+            g = _Grads(_ptr(self.grads.get("vmat")), _ptr(self.grads.get("albedo")), _ptr(self.grads.get("rough")),
+                       _ptr(self.grads.get("metal")), _ptr(self.grads.get("env")))
+        op = self.opts.struct(self.dbg_rgb, self.dbg_hash)
+        sc = scene.struct()
+        h = C.c_void_p()
+        _check(_lib.mrs_plan_create(C.byref(sc), C.addressof(vs), len(self.views), C.byref(op),
+                                    self.image.data_ptr(), _ptr(self.grad_image), C.byref(g) if g else None,
+                                    int(use_graph), C.byref(h)))
+        self._h = h
+
+    def forward(self, stream=None) -> torch.Tensor:
+        _check(_lib.mrs_plan_forward(self._h, _stream(stream)))
+        return self.image
+
+    def backward(self, stream=None) -> Dict[str, torch.Tensor]:
+        """Accumulates d(sum grad_image . image) into self.grads (zero them
+        first for a fresh gradient)."""
+        _check(_lib.mrs_plan_backward(self._h, _stream(stream)))
+        return self.grads
+
+    def zero_grad(self):
+        for t in self.grads.values():
+            t.zero_()
+
+    def info(self) -> Tuple[int, bool, bool]:
+        s, t, g = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(_lib.mrs_plan_info(self._h, C.byref(s), C.byref(t), C.byref(g)))
+        return s.value, bool(t.value), bool(g.value)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mrs_plan_destroy(self._h)
+            self._h = None
 
 
 def profile_begin():
