@@ -108,12 +108,94 @@ def cpu_baseline(w, seconds, nthreads):
     return n / dt, n, dt, cnt
 
 
+def roofline_from(prof, kb, S, steps, workload):
+    """Dominant kernel's algorithmic GB/s from HIP-event kernel times."""
+    kern = {}
+    for name, (launches, ms) in prof.items():
+        if name in kb:
+            per_step_ms = ms / steps
+            kern[name] = {"ms_per_step": per_step_ms, "launches_per_step": launches / steps,
+                          "alg_bytes_per_sample": kb[name],
+                          "alg_GBps": S * kb[name] / (per_step_ms * 1e-3) / 1e9}
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    d = kern[dom]
+    launches = d["launches_per_step"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": d["alg_GBps"] / HBM_PEAK_GBPS, "traffic": load_traffic(dom, workload),
+            "alg_bytes_per_launch": S * kb[dom] / launches, "avg_launch_ms": d["ms_per_step"] / launches}
+    return roof, kern
+
+
+def bench_batched(args):
+    """Config 4: 64 views of uneven size (256^2..1024^2) and spp (1..16) over the
+    300k-triangle mesh, forward only, as one persistent pool captured in a
+    hipGraph with autotuned pool/workgroup sizes, against 64 separate
+    launches (one eager mrs_render per view, default sizes)."""
+    import torch
+    from paper_2406_16360_amd import autotune, mirres, synth
+    torch.cuda.set_device(0)
+    w = synth.config4()
+    S = w.samples
+    print(f"# workload {w.name}: {S} samples/pass, {w.scene.nf} triangles", file=sys.stderr, flush=True)
+    sc = mirres.GpuScene.from_synth(w.scene)
+    opts = mirres.RenderOptions.from_any(w.opts)
+    tune = autotune.autotune(sc, w.views, opts, reps=2, verbose=True)
+    opts.pool, opts.block = tune["pool"], tune["block"]
+    plan = mirres.Plan(sc, w.views, opts, use_graph=True)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    t_batched = timed(plan.forward)
+    plain_opts = mirres.RenderOptions.from_any(w.opts)
+    t_plain = timed(lambda: [mirres.render(sc, [v], plain_opts) for v in w.views])
+    mirres.profile_begin()
+    mirres.render(sc, w.views, opts)
+    torch.cuda.synchronize()
+    prof = mirres.profile_end()
+    cpu, roof, extra = None, None, {}
+    if not args.no_cpu_baseline:
+        from oracle.oracle import Oracle
+        orc = Oracle(w.scene)
+        ncores = len(os.sched_getaffinity(0))
+        items = synth.sample_items(w, 200000, 2024)
+        t0 = time.perf_counter()
+        _, _, cnt = orc.render(w.views, w.opts, items, nthreads=ncores, counters=True)
+        dt = time.perf_counter() - t0
+        cpu = {"value": len(items) / dt, "unit": "samples/s", "cores": ncores, "kind": "oracle",
+               "sample": f"{len(items)} seeded samples of {w.name} (render only) in {dt:.1f}s"}
+        kb = kernel_bytes(cnt, len(items), sum(v.spp for v in w.views) / len(w.views), True)
+        kb.pop("adjoint")
+        roof, kern = roofline_from(prof, kb, S, 1, "c4")
+        extra = {"path_roofline": {"alg_bytes_per_sample": sum(kb.values()),
+                                   "frac": S / t_batched * sum(kb.values()) / (HBM_PEAK_GBPS * 1e9)},
+                 "kernels": kern}
+    out = {"metric": "forward path samples/s, 64 uneven views in one persistent graph-replayed launch",
+           "value": S / t_batched, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t_batched * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "views": len(w.views), "samples_per_step": S, "bounces": w.opts.bounces,
+                      "ris_m": w.opts.ris_m, "triangles": w.scene.nf, "pool": opts.pool, "block": opts.block},
+           "plain_64_launches": {"value": S / t_plain, "ms_per_step": t_plain * 1e3},
+           "batched_speedup": t_plain / t_batched, "autotune": tune["table"],
+           "roofline": roof, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--mode", default="fwdbwd", choices=["fwdbwd", "fwd"])
     ap.add_argument("--tape", default="on", choices=["auto", "on", "off"])
     ap.add_argument("--pool", type=int, default=0)
@@ -126,6 +208,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would render its own "
               "share of the views; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c4":
+        bench_batched(args)
+        return
 
     import torch
     from paper_2406_16360_amd import mirres, synth
@@ -204,21 +289,7 @@ def main():
         if args.mode == "fwd":
             kb.pop("adjoint")
         balg = sum(kb.values())
-        kern = {}
-        for name, (launches, ms) in prof.items():
-            if name in kb:
-                per_step_ms = ms / args.steps
-                kern[name] = {"ms_per_step": per_step_ms, "launches_per_step": launches / args.steps,
-                              "alg_bytes_per_sample": kb[name],
-                              "alg_GBps": S * kb[name] / (per_step_ms * 1e-3) / 1e9}
-        dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-        d = kern[dom]
-        launches = d["launches_per_step"]
-        traffic = load_traffic(dom, args.workload)
-        roof = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": d["alg_GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
-                "alg_bytes_per_launch": S * kb[dom] / launches,
-                "avg_launch_ms": d["ms_per_step"] / launches}
+        roof, kern = roofline_from(prof, kb, S, args.steps, args.workload)
         extra = {"path_roofline": {"alg_bytes_per_sample": balg,
                                    "frac": value * balg / (HBM_PEAK_GBPS * 1e9),
                                    "counts_per_sample": {k: v / nsub for k, v in cnt.items()}},
