@@ -98,7 +98,7 @@ def cpu_baseline(w, seconds, nthreads):
     orc.render(w.views, w.opts, probe, nthreads=nthreads)
     orc.grad(w.views, w.opts, probe, np.ones((len(probe), 3)), nthreads=nthreads)
     per = (time.perf_counter() - t0) / len(probe)
-    n = int(min(max(seconds / max(per, 1e-9), 4000), 4_000_000))
+    n = int(min(max(seconds / max(per, 1e-9), 4000), 16_000_000))
     items = synth.sample_items(w, n, 2024)
     dl = np.random.default_rng(7).random((n, 3))
     t0 = time.perf_counter()

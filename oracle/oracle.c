@@ -358,7 +358,8 @@ static int tri_hit(const orc_ctx *c, int32_t f, const double o[3], const double 
     return 1;
 }
 
-static int box_hit(const bnode *nd, const double o[3], const double d[3], double tmax) {
+/* slab test of a node box against [0, tmax]; *tnear = entry distance */
+static int box_hit(const bnode *nd, const double o[3], const double d[3], double tmax, double *tnear) {
     double t0 = 0.0, t1 = tmax;
     for (int a = 0; a < 3; ++a) {
         if (d[a] != 0.0) {
@@ -372,13 +373,31 @@ static int box_hit(const bnode *nd, const double o[3], const double d[3], double
             return 0;
         }
     }
+    *tnear = t0;
     return 1;
 }
 
 typedef struct { int32_t prim; double t, b1, b2; } hitrec;
 
+static void leaf_closest(const orc_ctx *c, const bnode *nd, const double o[3], const double d[3], hitrec *h,
+                         int64_t *tris) {
+    double t, b1, b2;
+    for (int32_t i = nd->first; i < nd->first + nd->count; ++i) {
+        int32_t f = c->order[i];
+        if (tris) (*tris)++;
+        if (tri_hit(c, f, o, d, &t, &b1, &b2) && (t < h->t || (t == h->t && f < h->prim))) {
+            h->prim = f; h->t = t; h->b1 = b1; h->b2 = b2;
+        }
+    }
+}
+
 /* Closest hit: smallest t > 0, ties to the lower primitive id (plain
- * definition of Eq. intersect for a triangle mesh). */
+ * definition of Eq. intersect for a triangle mesh).  The BVH only prunes:
+ * visiting an internal node tests both child boxes (counted as two box
+ * tests), hit leaves are tested at once, the nearer hit child is visited
+ * next and the farther one is stacked with its entry distance and skipped
+ * when popped if a closer hit was found meanwhile (boxes touching the current
+ * closest distance are still visited, for the tie rule). */
 static hitrec trace_closest(const orc_ctx *c, const double o[3], const double d[3], int brute,
                             int64_t *nodes, int64_t *tris) {
     hitrec h = { -1, INFINITY, 0.0, 0.0 };
@@ -392,29 +411,50 @@ static hitrec trace_closest(const orc_ctx *c, const double o[3], const double d[
         }
         return h;
     }
-    int32_t stack[512]; int sp = 0;
-    stack[sp++] = 0;
-    while (sp) {
-        const bnode *nd = &c->nodes[stack[--sp]];
-        if (nodes) (*nodes)++;
-        if (!box_hit(nd, o, d, h.t)) continue;
-        if (nd->left < 0) {
-            for (int32_t i = nd->first; i < nd->first + nd->count; ++i) {
-                int32_t f = c->order[i];
-                if (tris) (*tris)++;
-                if (tri_hit(c, f, o, d, &t, &b1, &b2) && (t < h.t || (t == h.t && f < h.prim))) {
-                    h.prim = f; h.t = t; h.b1 = b1; h.b2 = b2;
-                }
-            }
-        } else {
-            stack[sp++] = nd->right;
-            stack[sp++] = nd->left;
+    double t0;
+    if (nodes) (*nodes)++;
+    if (!box_hit(&c->nodes[0], o, d, h.t, &t0)) return h;
+    if (c->nodes[0].left < 0) { leaf_closest(c, &c->nodes[0], o, d, &h, tris); return h; }
+    int32_t stack[512]; double stackt[512]; int sp = 0;
+    int32_t cur = 0;
+    for (;;) {
+        const bnode *nd = &c->nodes[cur];
+        int32_t ch[2] = { nd->left, nd->right };
+        double tn[2] = { 0.0, 0.0 };
+        int hit[2];
+        for (int k = 0; k < 2; ++k) {
+            if (nodes) (*nodes)++;
+            hit[k] = box_hit(&c->nodes[ch[k]], o, d, h.t, &tn[k]);
+            if (hit[k] && c->nodes[ch[k]].left < 0) { leaf_closest(c, &c->nodes[ch[k]], o, d, &h, tris); hit[k] = 0; }
         }
+        if (hit[0] && hit[1]) {
+            int nr = tn[0] <= tn[1] ? 0 : 1;
+            stack[sp] = ch[1 - nr]; stackt[sp] = tn[1 - nr]; ++sp;
+            cur = ch[nr];
+            continue;
+        }
+        if (hit[0] || hit[1]) { cur = hit[0] ? ch[0] : ch[1]; continue; }
+        int found = 0;
+        while (sp) {
+            --sp;
+            if (stackt[sp] <= h.t) { cur = stack[sp]; found = 1; break; }
+        }
+        if (!found) break;
     }
     return h;
 }
 
-/* Visibility (Appendix A): 1 if any triangle is hit at t > 0. */
+static int leaf_any(const orc_ctx *c, const bnode *nd, const double o[3], const double d[3], int64_t *tris) {
+    double t, b1, b2;
+    for (int32_t i = nd->first; i < nd->first + nd->count; ++i) {
+        if (tris) (*tris)++;
+        if (tri_hit(c, c->order[i], o, d, &t, &b1, &b2)) return 1;
+    }
+    return 0;
+}
+
+/* Visibility (Appendix A): 1 if any triangle is hit at t > 0; same visiting
+ * order and counting as the closest-hit traversal, stopping at the first hit. */
 static int trace_any(const orc_ctx *c, const double o[3], const double d[3], int brute,
                      int64_t *nodes, int64_t *tris) {
     double t, b1, b2;
@@ -425,21 +465,34 @@ static int trace_any(const orc_ctx *c, const double o[3], const double d[3], int
         }
         return 0;
     }
+    double t0;
+    if (nodes) (*nodes)++;
+    if (!box_hit(&c->nodes[0], o, d, INFINITY, &t0)) return 0;
+    if (c->nodes[0].left < 0) return leaf_any(c, &c->nodes[0], o, d, tris);
     int32_t stack[512]; int sp = 0;
-    stack[sp++] = 0;
-    while (sp) {
-        const bnode *nd = &c->nodes[stack[--sp]];
-        if (nodes) (*nodes)++;
-        if (!box_hit(nd, o, d, INFINITY)) continue;
-        if (nd->left < 0) {
-            for (int32_t i = nd->first; i < nd->first + nd->count; ++i) {
-                if (tris) (*tris)++;
-                if (tri_hit(c, c->order[i], o, d, &t, &b1, &b2)) return 1;
+    int32_t cur = 0;
+    for (;;) {
+        const bnode *nd = &c->nodes[cur];
+        int32_t ch[2] = { nd->left, nd->right };
+        double tn[2] = { 0.0, 0.0 };
+        int hit[2];
+        for (int k = 0; k < 2; ++k) {
+            if (nodes) (*nodes)++;
+            hit[k] = box_hit(&c->nodes[ch[k]], o, d, INFINITY, &tn[k]);
+            if (hit[k] && c->nodes[ch[k]].left < 0) {
+                if (leaf_any(c, &c->nodes[ch[k]], o, d, tris)) return 1;
+                hit[k] = 0;
             }
-        } else {
-            stack[sp++] = nd->right;
-            stack[sp++] = nd->left;
         }
+        if (hit[0] && hit[1]) {
+            int nr = tn[0] <= tn[1] ? 0 : 1;
+            stack[sp++] = ch[1 - nr];
+            cur = ch[nr];
+            continue;
+        }
+        if (hit[0] || hit[1]) { cur = hit[0] ? ch[0] : ch[1]; continue; }
+        if (!sp) break;
+        cur = stack[--sp];
     }
     return 0;
 }

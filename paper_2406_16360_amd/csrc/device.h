@@ -173,6 +173,22 @@ __device__ __forceinline__ V3 brdf_eval(const Lobe &L, V3 wi) {
     return f;
 }
 
+// f and the mixture pdf of a local wi from one microfacet evaluation
+__device__ __forceinline__ V3 brdf_eval_pdf(const Lobe &L, V3 wi, float &pdf) {
+    pdf = 0.0f;
+    if (!(wi.z > 0.0f) || !(L.wo.z > 0.0f)) return V3{0, 0, 0};
+    V3 f = L.kd;
+    pdf = (1.0f - L.pspec) * wi.z * kInvPi;
+    if (L.spec) {
+        Micro m = micro(L, wi);
+        float k = m.D * L.g1o * m.g1i / (4.0f * wi.z * L.wo.z);
+        f = f + V3{(L.f0.x + (1.0f - L.f0.x) * m.fw) * k, (L.f0.y + (1.0f - L.f0.y) * m.fw) * k,
+                   (L.f0.z + (1.0f - L.f0.z) * m.fw) * k};
+        pdf += L.pspec * L.g1o * m.D / (4.0f * L.wo.z);
+    }
+    return f;
+}
+
 __device__ __forceinline__ float mix_pdf(const Lobe &L, V3 wi) {
     if (!(wi.z > 0.0f) || !(L.wo.z > 0.0f)) return 0.0f;
     float p = (1.0f - L.pspec) * wi.z * kInvPi;
@@ -191,7 +207,7 @@ __device__ __forceinline__ V3 vndf(V3 wo, float alpha, float u1, float u2) {
     V3 T2 = cross(vh, T1);
     float r = sqrtf(u1);
     float sp, cp;
-    sincosf(2.0f * kPi * u2, &sp, &cp);
+    sincospif(2.0f * u2, &sp, &cp);   // sin, cos of 2 pi u2 (exact argument)
     float t1 = r * cp, t2 = r * sp;
     float s = 0.5f * (1.0f + vh.z);
     t2 = (1.0f - s) * sqrtf(1.0f - t1 * t1) + s * t2;
@@ -210,7 +226,7 @@ __device__ __forceinline__ int mix_sample(const Lobe &L, float u0, float u1, flo
         lobe = 2;
     } else {
         float r = sqrtf(u1), sp, cp;
-        sincosf(2.0f * kPi * u2, &sp, &cp);
+        sincospif(2.0f * u2, &sp, &cp);
         wi = V3{r * cp, r * sp, sqrtf(fmaxf(0.0f, 1.0f - u1))};
         lobe = 1;
     }
@@ -299,17 +315,16 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, float u0f, float 
     double u0 = u0f, u1 = u1f;
     int gi = min((int)(u0 * e.H), e.H - 1);
     int i = cdf_walk(e.marg, e.gmarg[gi], e.H, u0);
-    double fv = (u0 - e.marg[i]) / (e.marg[i + 1] - e.marg[i]);
+    // the CDF differences are formed in double, the in-texel fractions in float
+    float fv = __fdividef((float)(u0 - e.marg[i]), (float)(e.marg[i + 1] - e.marg[i]));
     const double *cr = e.cond + (size_t)i * (e.W + 1);
     int gj = min((int)(u1 * e.W), e.W - 1);
     int j = cdf_walk(cr, e.gcond[(size_t)i * e.W + gj], e.W, u1);
-    double fu = (u1 - cr[j]) / (cr[j + 1] - cr[j]);
-    double v = (i + fv) / e.H, u = (j + fu) / e.W;
-    float theta = (float)(3.14159265358979323846 * v);
-    float phi = (float)(6.28318530717958647692 * (u - 0.5));
+    float fu = __fdividef((float)(u1 - cr[j]), (float)(cr[j + 1] - cr[j]));
+    float v = ((float)i + fv) / (float)e.H, u = ((float)j + fu) / (float)e.W;
     float st, ct, sp, cp;
-    sincosf(theta, &st, &ct);
-    sincosf(phi, &sp, &cp);
+    sincospif(v, &st, &ct);                   // theta = pi v
+    sincospif(2.0f * u - 1.0f, &sp, &cp);     // phi = 2 pi (u - 1/2)
     if (!(st > 0.0f)) return false;
     dir = V3{st * sp, ct, -st * cp};
     texel = i * e.W + j;

@@ -94,7 +94,8 @@ struct ProfScope {
 // jobs and buffers
 // ============================================================================
 constexpr uint64_t kOutChunkMax = 1ull << 26;   // samples per super-chunk of the output buffer
-constexpr uint32_t kPoolDefault = 1u << 22;      // paths in flight
+constexpr uint32_t kPoolDefault = 1u << 23;      // paths in flight
+constexpr int kBlockDefault = 64;                // threads per workgroup of the trace and shade kernels
 constexpr uint64_t kTapeRecBytes = 36;           // tape bytes per path vertex
 constexpr uint64_t kAdjChunk = 1ull << 24;        // samples per adjoint launch
 
@@ -134,7 +135,7 @@ struct Job {
     Opts op{};
     ViewTable vt{};
     uint32_t pool = kPoolDefault;
-    int block = 256;
+    int block = kBlockDefault;
 };
 
 inline unsigned nblocks(uint64_t n, int b) { return (unsigned)std::max<uint64_t>(1, (n + b - 1) / b); }
@@ -156,8 +157,11 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
     } else {
         return fail(MRS_EINVAL, "unknown mat_mode %d", sc->mat_mode);
     }
-    if (!sc->env || sc->ew <= 0 || sc->eh <= 0 || (int64_t)sc->ew * sc->eh >= (1ll << 28))
-        return fail(MRS_EINVAL, "bad environment map %dx%d", sc->ew, sc->eh);
+    if (!sc->env || sc->ew <= 0 || sc->eh <= 0) return fail(MRS_EINVAL, "bad environment map %dx%d", sc->ew, sc->eh);
+    // gradient elements are addressed with 29-bit indices
+    if (3ll * sc->ew * sc->eh >= (1ll << 29) || 5ll * sc->nv >= (1ll << 29) ||
+        (sc->mat_mode == MRS_MAT_TEXTURE && 3ll * sc->tw * sc->th >= (1ll << 29)))
+        return fail(MRS_EOVERFLOW, "parameter arrays too large (more than 2^29 gradient elements)");
     if (n_views < 1 || n_views > MRS_MAX_VIEWS) return fail(MRS_EINVAL, "n_views must be in [1, %d]", MRS_MAX_VIEWS);
     if (op->bounces < 1 || op->bounces > MRS_MAX_BOUNCES) return fail(MRS_EINVAL, "bounces must be in [1, %d]", MRS_MAX_BOUNCES);
     if (op->ris_m < 1 || op->ris_m > 0xFFFE) return fail(MRS_EINVAL, "ris_m must be in [1, 65534]");
@@ -199,7 +203,7 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
     job.op.spec = op->brdf == MRS_BRDF_LAMBERT_GGX; job.op.background = op->background; job.op.grad_mode = op->grad_mode;
     job.op.k0 = (uint32_t)op->seed; job.op.k1 = (uint32_t)(op->seed >> 32);
     job.pool = op->pool > 0 ? (uint32_t)op->pool : kPoolDefault;
-    job.block = op->block > 0 ? op->block : 256;
+    job.block = op->block > 0 ? op->block : kBlockDefault;
     return MRS_OK;
 }
 
@@ -326,7 +330,7 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
         {
             PROF(KID_CLOSEST, s);
             TraceArgs ta{job.sd.nodes, job.sd.tris, qa, r.hits.as<float4>(), ctr, it};
-            k_trace_closest<<<nblocks(P, bs), bs, 0, s>>>(ta);
+            k_trace_closest<<<nblocks(P, bs), bs, kLdsStackBytes * bs, s>>>(ta);
         }
         {
             PROF(KID_SHADE, s);
@@ -338,7 +342,7 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
             PROF(KID_SHADOW, s);
             ShadowArgs sh{job.sd.nodes, job.sd.tris, r.so.as<float4>(), r.sd.as<float4>(), r.sc.as<float4>(), ctr, it,
                           r.out.as<float4>(), ch.c0, hash, tape, use_tape};
-            k_trace_shadow<<<nblocks(P, bs), bs, 0, s>>>(sh);
+            k_trace_shadow<<<nblocks(P, bs), bs, kLdsStackBytes * bs, s>>>(sh);
         }
         std::swap(qa, qb);
     }
@@ -550,7 +554,7 @@ extern "C" mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const f
     hipStream_t s = (hipStream_t)stream;
     {
         PROF(KID_TRACE, s);
-        k_trace_batch<<<nblocks((uint64_t)n, 256), 256, 0, s>>>(bvh->nodes.as<BvhNode>(), bvh->tris.as<TriRec>(),
+        k_trace_batch<<<nblocks((uint64_t)n, 256), 256, kLdsStackBytes * 256, s>>>(bvh->nodes.as<BvhNode>(), bvh->tris.as<TriRec>(),
                                                                d_orig, d_dir, n, any_hit ? 1 : 0, (float4 *)d_hit);
     }
     return hip_check(hipGetLastError(), "mrs_trace launch");
@@ -593,6 +597,17 @@ extern "C" mrs_status mrs_profile_end(mrs_kernel_time *out, int32_t cap, int32_t
     *n = k;
     return MRS_OK;
 }
+
+#ifdef MRS_COUNT_VISITS
+// measurement builds only: read and clear the traversal visit counters
+extern "C" int mrs_debug_visits(unsigned long long out[4]) {
+    if (hipDeviceSynchronize() != hipSuccess) return -1;
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_visit_counts), sizeof(unsigned long long) * 4) != hipSuccess) return -1;
+    unsigned long long z[4] = {0, 0, 0, 0};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_visit_counts), z, sizeof(z)) != hipSuccess) return -1;
+    return 0;
+}
+#endif
 
 extern "C" void mrs_release_workspace(void) {
     std::lock_guard<std::mutex> lk(g_ws.mu);

@@ -79,18 +79,98 @@ __device__ __forceinline__ bool tri_test(const RayPre &r, V3 a, V3 b, V3 c, floa
 
 struct Hit { float t, b1, b2; int leaf; int prim; };
 
+// Visit counters for measurement builds (-DMRS_COUNT_VISITS): node fetches
+// and triangle tests of closest-hit [0, 1] and any-hit [2, 3] traversals.
+#ifdef MRS_COUNT_VISITS
+__device__ unsigned long long g_visit_counts[4];
+#define MRS_COUNT(k) atomicAdd(&g_visit_counts[(k)], 1ull)
+#else
+#define MRS_COUNT(k) ((void)0)
+#endif
+
+#ifndef MRS_LDS_STACK
+#define MRS_LDS_STACK 16   // stack entries per thread kept in LDS
+#endif
+#ifndef MRS_STACK_T
+// 1: also keep each entry's box-entry distance, to skip it after a closer hit
+// (doubles the LDS per thread, which cost more occupancy than it saved)
+#define MRS_STACK_T 0
+#endif
+constexpr int kLdsStack = MRS_LDS_STACK;
+
+// LDS bytes a traversal kernel needs per thread
+constexpr int kLdsStackBytes = kLdsStack * (MRS_STACK_T ? 8 : 4);
+
+// Traversal stack: the first kLdsStack entries live in LDS, one column per
+// thread (entry i of thread t at [i * stride + t], so a wavefront touches
+// consecutive words); deeper entries spill to a private array.
+struct TStack {
+    int *ref;          // LDS column of node refs
+    float *tn;         // LDS column of entry distances (MRS_STACK_T)
+    int stride;
+    int sp = 0;
+    int spill_ref[kStackSize - kLdsStack];
+#if MRS_STACK_T
+    float spill_t[kStackSize - kLdsStack];
+#endif
+    // the build rejects trees deeper than the stack, so a full stack is never
+    // reached; if it were, the entry is dropped rather than written out of bounds
+    __device__ __forceinline__ void push(int x, float t) {
+        if (sp >= kStackSize) return;
+        if (sp < kLdsStack) {
+            ref[sp * stride] = x;
+#if MRS_STACK_T
+            tn[sp * stride] = t;
+#endif
+        } else {
+            spill_ref[sp - kLdsStack] = x;
+#if MRS_STACK_T
+            spill_t[sp - kLdsStack] = t;
+#endif
+        }
+        ++sp;
+    }
+    __device__ __forceinline__ int pop(float &t) {
+        --sp;
+        if (sp < kLdsStack) {
+#if MRS_STACK_T
+            t = tn[sp * stride];
+#else
+            t = 0.0f;
+#endif
+            return ref[sp * stride];
+        }
+#if MRS_STACK_T
+        t = spill_t[sp - kLdsStack];
+#else
+        t = 0.0f;
+#endif
+        return spill_ref[sp - kLdsStack];
+    }
+};
+
+// per-thread view of the kernel's dynamic LDS (kLdsStackBytes * blockDim bytes)
+__device__ __forceinline__ TStack make_stack(void *lds) {
+    TStack st;
+    int *base = (int *)lds;
+    st.stride = blockDim.x;
+    st.ref = base + threadIdx.x;
+    st.tn = (float *)(base + kLdsStack * blockDim.x) + threadIdx.x;
+    return st;
+}
+
 // closest hit: smallest t > 0, ties to the lower original face id
 __device__ __forceinline__ Hit trace_closest(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
-                                             V3 o, V3 d) {
+                                             V3 o, V3 d, void *lds) {
+    constexpr int kNodeCtr = 0, kTriCtr = 1;
     RayPre r = ray_pre(o, d);
     Hit h;
     h.t = INFINITY; h.b1 = h.b2 = 0.0f; h.leaf = -1; h.prim = 0x7FFFFFFF;
-    int stack[kStackSize];
-    float stackt[kStackSize];
-    int sp = 0;
+    TStack st = make_stack(lds);
     int node = 0;
     while (true) {
         BvhNode nd = nodes[node];
+        MRS_COUNT(kNodeCtr);
         float tl, tr;
         bool hl = slab(r, nd.n0.x, nd.n0.y, nd.n0.z, nd.n0.w, nd.n2.x, nd.n2.y, h.t, tl);
         bool hr = slab(r, nd.n1.x, nd.n1.y, nd.n1.z, nd.n1.w, nd.n2.z, nd.n2.w, h.t, tr);
@@ -103,6 +183,7 @@ __device__ __forceinline__ Hit trace_closest(const BvhNode *__restrict__ nodes, 
                 int first = code >> 3, cnt = (code & 7) + 1;
                 for (int q = first; q < first + cnt; ++q) {
                     TriRec tr3 = tris[q];
+                    MRS_COUNT(kTriCtr);
                     float t, b1, b2;
                     int prim = __float_as_int(tr3.a.w);
                     if (tri_test(r, xyz(tr3.a), xyz(tr3.b), xyz(tr3.c), h.t, t, b1, b2) &&
@@ -116,18 +197,17 @@ __device__ __forceinline__ Hit trace_closest(const BvhNode *__restrict__ nodes, 
         hl = hits[0]; hr = hits[1];
         if (hl && hr) {
             bool lfirst = tl <= tr;
-            int nearn = lfirst ? refs[0] : refs[1];
-            int farn = lfirst ? refs[1] : refs[0];
-            if (sp < kStackSize) { stack[sp] = farn; stackt[sp] = lfirst ? tr : tl; ++sp; }
-            node = nearn;
+            st.push(lfirst ? refs[1] : refs[0], lfirst ? tr : tl);
+            node = lfirst ? refs[0] : refs[1];
             continue;
         }
         if (hl) { node = refs[0]; continue; }
         if (hr) { node = refs[1]; continue; }
         bool found = false;
-        while (sp > 0) {
-            --sp;
-            if (stackt[sp] <= h.t * 1.0000008f) { node = stack[sp]; found = true; break; }
+        while (st.sp > 0) {
+            float t;
+            int n = st.pop(t);
+            if (!MRS_STACK_T || t <= h.t * 1.0000008f) { node = n; found = true; break; }
         }
         if (!found) break;
     }
@@ -136,14 +216,15 @@ __device__ __forceinline__ Hit trace_closest(const BvhNode *__restrict__ nodes, 
 
 // any hit in (0, inf): visibility of a shadow ray
 __device__ __forceinline__ bool trace_any(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
-                                          V3 o, V3 d) {
+                                          V3 o, V3 d, void *lds) {
+    constexpr int kNodeCtr = 2, kTriCtr = 3;
     RayPre r = ray_pre(o, d);
-    int stack[kStackSize];
-    int sp = 0;
+    TStack st = make_stack(lds);
     int node = 0;
     const float tmax = INFINITY;
     while (true) {
         BvhNode nd = nodes[node];
+        MRS_COUNT(kNodeCtr);
         float tl, tr;
         bool hl = slab(r, nd.n0.x, nd.n0.y, nd.n0.z, nd.n0.w, nd.n2.x, nd.n2.y, tmax, tl);
         bool hr = slab(r, nd.n1.x, nd.n1.y, nd.n1.z, nd.n1.w, nd.n2.z, nd.n2.w, tmax, tr);
@@ -156,6 +237,7 @@ __device__ __forceinline__ bool trace_any(const BvhNode *__restrict__ nodes, con
                 int first = code >> 3, cnt = (code & 7) + 1;
                 for (int q = first; q < first + cnt; ++q) {
                     TriRec tr3 = tris[q];
+                    MRS_COUNT(kTriCtr);
                     float t, b1, b2;
                     if (tri_test(r, xyz(tr3.a), xyz(tr3.b), xyz(tr3.c), tmax, t, b1, b2)) return true;
                 }
@@ -165,14 +247,15 @@ __device__ __forceinline__ bool trace_any(const BvhNode *__restrict__ nodes, con
         hl = hits[0]; hr = hits[1];
         if (hl && hr) {
             bool lfirst = tl <= tr;
-            if (sp < kStackSize) { stack[sp] = lfirst ? refs[1] : refs[0]; ++sp; }
+            st.push(lfirst ? refs[1] : refs[0], 0.0f);
             node = lfirst ? refs[0] : refs[1];
             continue;
         }
         if (hl) { node = refs[0]; continue; }
         if (hr) { node = refs[1]; continue; }
-        if (sp == 0) break;
-        node = stack[--sp];
+        if (st.sp == 0) break;
+        float t;
+        node = st.pop(t);
     }
     return false;
 }

@@ -341,10 +341,11 @@ struct TraceArgs {
 };
 
 __global__ void k_trace_closest(TraceArgs a) {
+    extern __shared__ int lds_stack[];
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.ctr[a.it].n_live) return;
     float4 o = a.q.o[i], d = a.q.d[i];
-    Hit h = trace_closest(a.nodes, a.tris, xyz(o), xyz(d));
+    Hit h = trace_closest(a.nodes, a.tris, xyz(o), xyz(d), lds_stack);
     a.hits[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf));
 }
 
@@ -409,19 +410,17 @@ __global__ void k_shade(ShadeArgs a) {
                     if (s < Me) {
                         if (!env_sample(a.s.env, u.x, u.y, dir, tex, lp, qe)) continue;
                         wl = to_local(S.F, dir);
-                        qb = mix_pdf(L, wl);
                     } else {
                         int lb = mix_sample(L, u.x, u.y, u.z, wl);
                         if (!lb) continue;
                         dir = to_world(S.F, wl);
-                        qb = mix_pdf(L, wl);
                         tex = env_texel_of(a.s.env, dir);
                         if (a.hash) hcand ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
                         lp = a.s.env.lp[tex];
                         qe = env_pdf_dir(a.s.env, dir, tex, lp);
                     }
                     if (!(wl.z > 0.0f)) continue;
-                    V3 f = brdf_eval(L, wl);
+                    V3 f = brdf_eval_pdf(L, wl, qb);
                     float phat = (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
                     float den = (float)Me * qe + (float)Mb * qb;
                     if (!(phat > 0.0f) || !(den > 0.0f)) continue;
@@ -449,9 +448,9 @@ __global__ void k_shade(ShadeArgs a) {
                 float4 u = rng.draw((uint32_t)k, kBlockCont);
                 V3 wl;
                 int lobe = wo.z > 0.0f ? mix_sample(L, u.x, u.y, u.z, wl) : 0;
-                float q = lobe ? mix_pdf(L, wl) : 0.0f;
+                float q = 0.0f;
+                V3 f = lobe ? brdf_eval_pdf(L, wl, q) : V3{0, 0, 0};
                 if (lobe && q > 0.0f) {
-                    V3 f = brdf_eval(L, wl);
                     V3 Tn = T * f * (wl.z / q);
                     bool alive = true;
                     rrf = 1.0f;
@@ -494,12 +493,13 @@ struct ShadowArgs {
 };
 
 __global__ void k_trace_shadow(ShadowArgs a) {
+    extern __shared__ int lds_stack[];
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.ctr[a.it].n_shadow) return;
     float4 o = a.so[i], d = a.sd[i];
     uint32_t g = __float_as_uint(o.w);
     int k = __float_as_int(d.w);
-    bool occl = trace_any(a.nodes, a.tris, xyz(o), xyz(d));
+    bool occl = trace_any(a.nodes, a.tris, xyz(o), xyz(d), lds_stack);
     if (!occl) {
         float4 c = a.sc[i];
         float4 &acc = a.out[g - a.out_base];
@@ -556,8 +556,48 @@ struct AdjArgs {
     float *gvmat, *galb, *grough, *gmetal, *genv;
 };
 
-__device__ __forceinline__ void scatter_material(const AdjArgs &a, const Interp &ip, const MatRaw &raw,
-                                                 V3 ga, float gr, float gmu) {
+// Gradient arrays addressed by the cache keys
+enum GradKind : uint32_t { GK_VMAT = 0, GK_ALBEDO, GK_ROUGH, GK_METAL, GK_ENV };
+__device__ __forceinline__ float *grad_base(const AdjArgs &a, uint32_t kind) {
+    switch (kind) {
+        case GK_VMAT: return a.gvmat;
+        case GK_ALBEDO: return a.galb;
+        case GK_ROUGH: return a.grough;
+        case GK_METAL: return a.gmetal;
+        default: return a.genv;
+    }
+}
+
+// Per-workgroup gradient cache in LDS: an open-addressing hash table keyed by
+// (array, element).  Neighbouring samples of a workgroup hit overlapping texels,
+// so their contributions are summed with LDS atomics and each distinct element
+// costs one global atomic when the workgroup flushes the table.  A probe
+// sequence that finds no slot falls back to a direct global atomic.
+constexpr int kGradCacheLog2 = 11;
+constexpr int kGradCacheSize = 1 << kGradCacheLog2;
+constexpr uint32_t kGradEmpty = 0xFFFFFFFFu;
+constexpr int kGradMaxProbe = 16;
+
+struct GradCache {
+    uint32_t *keys;
+    float *vals;
+    __device__ __forceinline__ void add(const AdjArgs &a, uint32_t kind, uint32_t idx, float v) {
+        uint32_t key = (kind << 29) | idx;
+        uint32_t h = (key * 2654435761u) >> (32 - kGradCacheLog2);
+        for (int p = 0; p < kGradMaxProbe; ++p) {
+            uint32_t prev = atomicCAS(&keys[h], kGradEmpty, key);
+            if (prev == kGradEmpty || prev == key) {
+                atomicAdd(&vals[h], v);
+                return;
+            }
+            h = (h + 1) & (kGradCacheSize - 1);
+        }
+        atomicAdd(grad_base(a, kind) + idx, v);
+    }
+};
+
+__device__ __forceinline__ void scatter_material(const AdjArgs &a, GradCache &gc, const Interp &ip,
+                                                 const MatRaw &raw, V3 ga, float gr, float gmu) {
     // clamp masks: the derivative passes on the closed interval
     float ma[3] = {(raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f,
                    (raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f,
@@ -568,44 +608,43 @@ __device__ __forceinline__ void scatter_material(const AdjArgs &a, const Interp 
         if (!a.gvmat) return;
         for (int q = 0; q < 3; ++q) {
             float w = ip.w[q];
-            float *dst = a.gvmat + 5 * (size_t)ip.idx[q];
-            if (ma[0] != 0.0f) atomicAdd(dst + 0, w * ma[0]);
-            if (ma[1] != 0.0f) atomicAdd(dst + 1, w * ma[1]);
-            if (ma[2] != 0.0f) atomicAdd(dst + 2, w * ma[2]);
-            if (mr != 0.0f) atomicAdd(dst + 3, w * mr);
-            if (mm != 0.0f) atomicAdd(dst + 4, w * mm);
+            uint32_t e = 5u * (uint32_t)ip.idx[q];
+            if (ma[0] != 0.0f) gc.add(a, GK_VMAT, e + 0, w * ma[0]);
+            if (ma[1] != 0.0f) gc.add(a, GK_VMAT, e + 1, w * ma[1]);
+            if (ma[2] != 0.0f) gc.add(a, GK_VMAT, e + 2, w * ma[2]);
+            if (mr != 0.0f) gc.add(a, GK_VMAT, e + 3, w * mr);
+            if (mm != 0.0f) gc.add(a, GK_VMAT, e + 4, w * mm);
         }
         return;
     }
     for (int q = 0; q < 4; ++q) {
         float w = ip.w[q];
         if (w == 0.0f) continue;
-        size_t t = (size_t)ip.idx[q];
+        uint32_t t = (uint32_t)ip.idx[q];
         if (a.galb) {
-            if (ma[0] != 0.0f) atomicAdd(a.galb + 3 * t + 0, w * ma[0]);
-            if (ma[1] != 0.0f) atomicAdd(a.galb + 3 * t + 1, w * ma[1]);
-            if (ma[2] != 0.0f) atomicAdd(a.galb + 3 * t + 2, w * ma[2]);
+            if (ma[0] != 0.0f) gc.add(a, GK_ALBEDO, 3u * t + 0, w * ma[0]);
+            if (ma[1] != 0.0f) gc.add(a, GK_ALBEDO, 3u * t + 1, w * ma[1]);
+            if (ma[2] != 0.0f) gc.add(a, GK_ALBEDO, 3u * t + 2, w * ma[2]);
         }
-        if (a.grough && mr != 0.0f) atomicAdd(a.grough + t, w * mr);
-        if (a.gmetal && mm != 0.0f) atomicAdd(a.gmetal + t, w * mm);
+        if (a.grough && mr != 0.0f) gc.add(a, GK_ROUGH, t, w * mr);
+        if (a.gmetal && mm != 0.0f) gc.add(a, GK_METAL, t, w * mm);
     }
 }
 
-__device__ __forceinline__ void scatter_env(const AdjArgs &a, int tex, V3 g) {
+__device__ __forceinline__ void scatter_env(const AdjArgs &a, GradCache &gc, int tex, V3 g) {
     if (!a.genv || tex < 0) return;
     const float *raw = a.s.env.raw + 3 * (size_t)tex;
-    if (raw[0] >= 0.0f && g.x != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 0, g.x);
-    if (raw[1] >= 0.0f && g.y != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 1, g.y);
-    if (raw[2] >= 0.0f && g.z != 0.0f) atomicAdd(a.genv + 3 * (size_t)tex + 2, g.z);
+    uint32_t e = 3u * (uint32_t)tex;
+    if (raw[0] >= 0.0f && g.x != 0.0f) gc.add(a, GK_ENV, e + 0, g.x);
+    if (raw[1] >= 0.0f && g.y != 0.0f) gc.add(a, GK_ENV, e + 1, g.y);
+    if (raw[2] >= 0.0f && g.z != 0.0f) gc.add(a, GK_ENV, e + 2, g.z);
 }
 
 // Detached-sampling gradient of one sample: with directions, selections and
 // all pdf / reservoir weights held fixed, C = sum_k T_k (.) D_k and
 // T_{k+1} = T_k (.) beta_k, so dC/dm_k = T_k (.) (dD_k/dm_k + dbeta_k/dm_k (.) Li_{k+1})
 // with Li_k = D_k + beta_k (.) Li_{k+1} accumulated from the last vertex back.
-__global__ void k_adjoint(AdjArgs a) {
-    uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
+__device__ __forceinline__ void adjoint_sample(const AdjArgs &a, uint64_t j, GradCache &gc) {
     uint64_t g = a.g0 + j;
     SampleId sid = decode(a.vt, g);
     const ViewDev &vw = a.vt.v[sid.view];
@@ -626,7 +665,7 @@ __global__ void k_adjoint(AdjArgs a) {
         float4 th = a.tape.hit[ti];
         int leaf = __float_as_int(th.z);
         if (leaf < 0) {
-            if (k == 1) scatter_env(a, __float_as_int(th.w), gp);
+            if (k == 1) scatter_env(a, gc, __float_as_int(th.w), gp);
             break;
         }
         dk[k - 1] = d;
@@ -650,9 +689,10 @@ __global__ void k_adjoint(AdjArgs a) {
         float4 uc = rng.draw((uint32_t)k, kBlockCont);
         V3 wl;
         mix_sample(L, uc.x, uc.y, uc.z, wl);
-        float q = mix_pdf(L, wl);
+        float q;
+        V3 fc = brdf_eval_pdf(L, wl, q);
         if (!(q > 0.0f)) break;
-        Bk[k - 1] = brdf_eval(L, wl) * (wl.z / q * rr);
+        Bk[k - 1] = fc * (wl.z / q * rr);
         d = to_world(S.F, wl);
     }
     // suffix radiance Li_{k+1}
@@ -690,7 +730,7 @@ __global__ void k_adjoint(AdjArgs a) {
             gr += dot(wl, bg.dr);
             gmu += dot(wl, bg.dmu);
             V3 f = brdf_eval(L, yl);
-            scatter_env(a, tex, w * f * cw);
+            scatter_env(a, gc, tex, w * f * cw);
         }
         if (k < nv) {
             float rr = a.tape.rr[ti];
@@ -706,22 +746,42 @@ __global__ void k_adjoint(AdjArgs a) {
                 gmu += dot(wb, bg.dmu);
             }
         }
-        scatter_material(a, ip, raw, ga, gr, gmu);
+        scatter_material(a, gc, ip, raw, ga, gr, gmu);
         T = T * Bk[k - 1];
+    }
+}
+
+// one thread per sample; the workgroup's gradient cache is flushed at the end
+__global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
+    __shared__ uint32_t keys[kGradCacheSize];
+    __shared__ float vals[kGradCacheSize];
+    for (int i = threadIdx.x; i < kGradCacheSize; i += blockDim.x) {
+        keys[i] = kGradEmpty;
+        vals[i] = 0.0f;
+    }
+    __syncthreads();
+    GradCache gc{keys, vals};
+    uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (j < a.n) adjoint_sample(a, j, gc);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kGradCacheSize; i += blockDim.x) {
+        uint32_t key = keys[i];
+        if (key != kGradEmpty) atomicAdd(grad_base(a, key >> 29) + (key & 0x1FFFFFFFu), vals[i]);
     }
 }
 
 __global__ void k_trace_batch(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                               const float *__restrict__ orig, const float *__restrict__ dir, int64_t n, int any,
                               float4 *__restrict__ out) {
+    extern __shared__ int lds_stack[];
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     V3 o = ld3(orig + 3 * i), d = ld3(dir + 3 * i);
     if (any) {
-        bool h = trace_any(nodes, tris, o, d);
+        bool h = trace_any(nodes, tris, o, d, lds_stack);
         out[i] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(h ? 0 : -1));
     } else {
-        Hit h = trace_closest(nodes, tris, o, d);
+        Hit h = trace_closest(nodes, tris, o, d, lds_stack);
         out[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf >= 0 ? h.prim : -1));
     }
 }

@@ -19,7 +19,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmirres.so")
+# MIRRES_LIB selects another build of the same library (e.g. a variant for an A/B timing run)
+LIB_PATH = os.environ.get("MIRRES_LIB") or os.path.join(_HERE, "libmirres.so")
 
 MRS_OK, MRS_EINVAL, MRS_ENOMEM, MRS_EHIP, MRS_EOVERFLOW, MRS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAT_VERTEX, MAT_TEXTURE = 0, 1
