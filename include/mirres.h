@@ -115,7 +115,8 @@ typedef struct {
     int32_t  tape_mode;      /* MRS_TAPE_*: keep per-vertex records for the adjoint or recompute */
     int64_t  tape_budget;    /* bytes the tape may use in AUTO mode; 0 = half of free device memory */
     int32_t  pool;           /* paths in flight; 0 = library default (2^23) */
-    int32_t  block;          /* threads per block of the trace/shade kernels; 0 = default (64) */
+    int32_t  block;          /* threads per block of the trace/shade kernels: 0 = default (64),
+                                else a multiple of 64 in [64, 256] */
     float   *debug_sample_rgb;   /* nullable device [S][3]: per-sample radiance, S = sum W*H*spp */
     uint32_t*debug_hash;         /* nullable device [S]: per-sample decision hash */
 } mrs_options;

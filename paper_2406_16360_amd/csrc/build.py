@@ -13,6 +13,9 @@ FLAGS = [
     # packed-FP32 instructions stay off (they have given silent wrong results on these boxes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",          # hardware float atomics for the gradient scatter
+    # fp32 division and square root as reciprocal/multiply and the hardware
+    # square root (about 1 ulp) instead of the correctly rounded sequences
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wno-unused-result",
 ]
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -140,6 +141,21 @@ struct Job {
 
 inline unsigned nblocks(uint64_t n, int b) { return (unsigned)std::max<uint64_t>(1, (n + b - 1) / b); }
 
+// Grid of a persistent traversal launch: enough blocks of b threads to hold
+// every wavefront slot of the current device (32 wave64 per CU), capped by
+// the blocks needed for n rays.  Extra blocks find the queue drained and exit.
+unsigned persistent_blocks(uint64_t n, int b) {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+        cus[dev].store(c, std::memory_order_relaxed);
+    }
+    return std::min<unsigned>(nblocks(n, b), (unsigned)((uint64_t)c * 2048 / b));
+}
+
 mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views, const mrs_options *op, Job &job) {
     if (!sc) return fail(MRS_EINVAL, "scene is NULL");
     if (!views) return fail(MRS_EINVAL, "views is NULL");
@@ -172,7 +188,7 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
     if (op->grad_mode != MRS_GRAD_FULL && op->grad_mode != MRS_GRAD_PRIMARY) return fail(MRS_EINVAL, "unknown grad_mode %d", op->grad_mode);
     if (op->tape_mode < MRS_TAPE_AUTO || op->tape_mode > MRS_TAPE_OFF) return fail(MRS_EINVAL, "unknown tape_mode %d", op->tape_mode);
     if (op->pool < 0) return fail(MRS_EINVAL, "pool must be >= 0");
-    if (op->block != 0 && (op->block < 64 || op->block > 1024 || op->block % 64)) return fail(MRS_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
+    if (op->block != 0 && (op->block < 64 || op->block > 256 || op->block % 64)) return fail(MRS_EINVAL, "block must be 0 or a multiple of 64 in [64, 256]");
     job.vd.resize(n_views);
     uint64_t S = 0, P = 0;
     for (int i = 0; i < n_views; ++i) {
@@ -270,10 +286,16 @@ mrs_status reserve_env(const mrs_scene *sc, Res &r) {
     return MRS_OK;
 }
 
+// Counter buffer of one super-chunk: IterCtr per iteration (+1), then, from
+// the next 128-byte boundary, the claim counters of the persistent
+// closest-hit launch of every iteration.  All of it is zeroed per chunk.
+size_t claim_offset_words(int n_iter) { return ((sizeof(IterCtr) * (size_t)(n_iter + 1) + 127) / 128) * 32; }
+size_t ctr_words(int n_iter) { return claim_offset_words(n_iter) + (size_t)n_iter * kClaimWords; }
+
 mrs_status reserve_pool(Res &r, uint32_t P, uint64_t out_samples, int n_iter) {
     size_t q = sizeof(float4) * (size_t)P;
     for (DevBuf *b : {&r.qa_o, &r.qa_d, &r.qa_t, &r.qb_o, &r.qb_d, &r.qb_t, &r.hits, &r.so, &r.sd, &r.sc}) TRY(b->reserve(q));
-    TRY(r.ctr.reserve(sizeof(IterCtr) * (size_t)(n_iter + 1)));
+    TRY(r.ctr.reserve(4 * ctr_words(n_iter)));
     TRY(r.sched.reserve(sizeof(Sched)));
     TRY(r.out.reserve(sizeof(float4) * (size_t)out_samples));
     return MRS_OK;
@@ -310,8 +332,9 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
     uint32_t P = (uint32_t)std::min<uint64_t>(job.pool, n);
     int n_iter = iterations(job, n, P);
     TRY(reserve_pool(r, P, n, n_iter));
-    size_t nctr = (sizeof(IterCtr) / 4) * (size_t)(n_iter + 1);
+    size_t nctr = ctr_words(n_iter);
     k_fill_u32<<<nblocks(nctr, 256), 256, 0, s>>>(r.ctr.as<uint32_t>(), nctr, 0u);
+    uint32_t *claim = r.ctr.as<uint32_t>() + claim_offset_words(n_iter);
     k_set_sched<<<1, 64, 0, s>>>(r.sched.as<Sched>(), ch.c0, ch.c1);
     Queue qa{r.qa_o.as<float4>(), r.qa_d.as<float4>(), r.qa_t.as<float4>()};
     Queue qb{r.qb_o.as<float4>(), r.qb_d.as<float4>(), r.qb_t.as<float4>()};
@@ -329,14 +352,14 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
         }
         {
             PROF(KID_CLOSEST, s);
-            TraceArgs ta{job.sd.nodes, job.sd.tris, qa, r.hits.as<float4>(), ctr, it};
-            k_trace_closest<<<nblocks(P, bs), bs, kLdsStackBytes * bs, s>>>(ta);
+            TraceArgs ta{job.sd.nodes, job.sd.tris, qa, r.hits.as<float4>(), ctr, it, claim + it * kClaimWords};
+            k_trace_closest<<<persistent_blocks(P, bs), bs, kLdsStackBytes * bs, s>>>(ta);
         }
         {
             PROF(KID_SHADE, s);
             ShadeArgs sa{job.sd, job.vt, job.op, qa, qb, r.hits.as<float4>(), ctr, it, r.so.as<float4>(),
                          r.sd.as<float4>(), r.sc.as<float4>(), r.out.as<float4>(), ch.c0, hash, tape, use_tape};
-            k_shade<<<nblocks(P, bs), bs, 0, s>>>(sa);
+            k_shade<<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
         }
         {
             PROF(KID_SHADOW, s);

@@ -4,6 +4,7 @@
 // inside, only t > 0 hits, degenerate triangles never hit, equal t resolves
 // to the lower original face id.
 #pragma once
+#include <climits>
 #include "device.h"
 
 namespace mrs {
@@ -91,173 +92,230 @@ __device__ unsigned long long g_visit_counts[4];
 #ifndef MRS_LDS_STACK
 #define MRS_LDS_STACK 16   // stack entries per thread kept in LDS
 #endif
-#ifndef MRS_STACK_T
-// 1: also keep each entry's box-entry distance, to skip it after a closer hit
-// (doubles the LDS per thread, which cost more occupancy than it saved)
-#define MRS_STACK_T 0
-#endif
 constexpr int kLdsStack = MRS_LDS_STACK;
 
 // LDS bytes a traversal kernel needs per thread
-constexpr int kLdsStackBytes = kLdsStack * (MRS_STACK_T ? 8 : 4);
+constexpr int kLdsStackBytes = kLdsStack * 4;
 
 // Traversal stack: the first kLdsStack entries live in LDS, one column per
 // thread (entry i of thread t at [i * stride + t], so a wavefront touches
 // consecutive words); deeper entries spill to a private array.
 struct TStack {
     int *ref;          // LDS column of node refs
-    float *tn;         // LDS column of entry distances (MRS_STACK_T)
     int stride;
     int sp = 0;
     int spill_ref[kStackSize - kLdsStack];
-#if MRS_STACK_T
-    float spill_t[kStackSize - kLdsStack];
-#endif
     // the build rejects trees deeper than the stack, so a full stack is never
     // reached; if it were, the entry is dropped rather than written out of bounds
-    __device__ __forceinline__ void push(int x, float t) {
+    __device__ __forceinline__ void push(int x) {
         if (sp >= kStackSize) return;
-        if (sp < kLdsStack) {
-            ref[sp * stride] = x;
-#if MRS_STACK_T
-            tn[sp * stride] = t;
-#endif
-        } else {
-            spill_ref[sp - kLdsStack] = x;
-#if MRS_STACK_T
-            spill_t[sp - kLdsStack] = t;
-#endif
-        }
+        if (sp < kLdsStack) ref[sp * stride] = x;
+        else spill_ref[sp - kLdsStack] = x;
         ++sp;
     }
-    __device__ __forceinline__ int pop(float &t) {
+    __device__ __forceinline__ int pop() {
         --sp;
-        if (sp < kLdsStack) {
-#if MRS_STACK_T
-            t = tn[sp * stride];
-#else
-            t = 0.0f;
-#endif
-            return ref[sp * stride];
-        }
-#if MRS_STACK_T
-        t = spill_t[sp - kLdsStack];
-#else
-        t = 0.0f;
-#endif
-        return spill_ref[sp - kLdsStack];
+        return sp < kLdsStack ? ref[sp * stride] : spill_ref[sp - kLdsStack];
     }
 };
 
 // per-thread view of the kernel's dynamic LDS (kLdsStackBytes * blockDim bytes)
 __device__ __forceinline__ TStack make_stack(void *lds) {
     TStack st;
-    int *base = (int *)lds;
     st.stride = blockDim.x;
-    st.ref = base + threadIdx.x;
-    st.tn = (float *)(base + kLdsStack * blockDim.x) + threadIdx.x;
+    st.ref = (int *)lds + threadIdx.x;
     return st;
+}
+
+__device__ __forceinline__ Hit no_hit() {
+    Hit h;
+    h.t = INFINITY; h.b1 = h.b2 = 0.0f; h.leaf = -1; h.prim = 0x7FFFFFFF;
+    return h;
+}
+
+// Traversal state of a lane: the next node reference to process, >= 0 an
+// inner node, another negative value a leaf, kNone once the ray is finished
+// (kNone never encodes a leaf: a leaf holds at most kLeafMax triangles).
+constexpr int kNone = INT_MIN;
+static_assert(kLeafMax <= 7, "leaf references encode count - 1 in three bits");
+
+// Inner-node visit: tests both child boxes against [0, tmax]; the nearer hit
+// child is next, the farther one is stacked; with no hit child the next
+// reference comes off the stack.
+__device__ __forceinline__ int inner_step(const BvhNode *__restrict__ nodes, const RayPre &r, float tmax, TStack &st,
+                                          int node, int ctr) {
+    BvhNode nd = nodes[node];
+    MRS_COUNT(ctr);
+    float tl, tr;
+    bool hl = slab(r, nd.n0.x, nd.n0.y, nd.n0.z, nd.n0.w, nd.n2.x, nd.n2.y, tmax, tl);
+    bool hr = slab(r, nd.n1.x, nd.n1.y, nd.n1.z, nd.n1.w, nd.n2.z, nd.n2.w, tmax, tr);
+    const int a = nd.n3.x, b = nd.n3.y;
+    if (hl && hr) {
+        bool lfirst = tl <= tr;
+        st.push(lfirst ? b : a);
+        return lfirst ? a : b;
+    }
+    if (hl) return a;
+    if (hr) return b;
+    return st.sp > 0 ? st.pop() : kNone;
+}
+
+// Leaf visit for the closest hit: all its triangles, then the next stacked
+// reference.
+__device__ __forceinline__ int closest_leaf(const TriRec *__restrict__ tris, const RayPre &r, Hit &h, TStack &st,
+                                            int ref) {
+    const int code = ~ref, first = code >> 3, cnt = (code & 7) + 1;
+    for (int q = first; q < first + cnt; ++q) {
+        TriRec tr3 = tris[q];
+        MRS_COUNT(1);
+        float t, b1, b2;
+        int prim = __float_as_int(tr3.a.w);
+        if (tri_test(r, xyz(tr3.a), xyz(tr3.b), xyz(tr3.c), h.t, t, b1, b2) && (t < h.t || prim < h.prim)) {
+            h.t = t; h.b1 = b1; h.b2 = b2; h.leaf = q; h.prim = prim;
+        }
+    }
+    return st.sp > 0 ? st.pop() : kNone;
+}
+
+// Leaf visit for any hit in (0, inf): finishes the ray on the first hit.
+__device__ __forceinline__ int any_leaf(const TriRec *__restrict__ tris, const RayPre &r, TStack &st, int ref,
+                                        bool &occl) {
+    const int code = ~ref, first = code >> 3, cnt = (code & 7) + 1;
+    for (int q = first; q < first + cnt; ++q) {
+        TriRec tr3 = tris[q];
+        MRS_COUNT(3);
+        float t, b1, b2;
+        if (tri_test(r, xyz(tr3.a), xyz(tr3.b), xyz(tr3.c), INFINITY, t, b1, b2)) { occl = true; return kNone; }
+    }
+    return st.sp > 0 ? st.pop() : kNone;
+}
+
+#ifndef MRS_LEAF_BATCH
+#define MRS_LEAF_BATCH 8   // lanes waiting at a leaf that start a leaf phase
+#endif
+
+// One traversal iteration of a wavefront (while-while traversal with
+// postponed leaves, after Aila and Laine, HPG 2009).  A lane whose next
+// reference is a leaf waits until at least MRS_LEAF_BATCH lanes of the
+// wavefront are at a leaf, or none is at an inner node; then those lanes
+// test their leaves together.  Lanes at an inner node then visit it.  `live`
+// marks lanes with a ray; the closest-hit result (smallest t, ties to the
+// lower face id) does not depend on the order of the visits.  Every lane
+// that is in the calling loop must call this.
+template <bool kAny>
+__device__ __forceinline__ void trace_iter(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+                                           bool live, const RayPre &r, Hit &h, bool &occl, TStack &st, int &node) {
+    const bool at_leaf = live && node < 0;
+    const uint64_t leaves = __ballot(at_leaf), inner = __ballot(live && node >= 0);
+    if (inner == 0 || __popcll(leaves) >= MRS_LEAF_BATCH) {
+        if (at_leaf) node = kAny ? any_leaf(tris, r, st, node, occl) : closest_leaf(tris, r, h, st, node);
+    }
+    if (live && node >= 0) node = inner_step(nodes, r, kAny ? INFINITY : h.t, st, node, kAny ? 2 : 0);
+}
+
+// One ray per lane, all lanes of the wavefront iterating together.
+template <bool kAny>
+__device__ __forceinline__ void trace_wave(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris, V3 o,
+                                           V3 d, void *lds, Hit &h, bool &occl) {
+    RayPre r = ray_pre(o, d);
+    h = no_hit();
+    occl = false;
+    TStack st = make_stack(lds);
+    int node = 0;
+    while (__ballot(node != kNone) != 0) trace_iter<kAny>(nodes, tris, node != kNone, r, h, occl, st, node);
 }
 
 // closest hit: smallest t > 0, ties to the lower original face id
 __device__ __forceinline__ Hit trace_closest(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                              V3 o, V3 d, void *lds) {
-    constexpr int kNodeCtr = 0, kTriCtr = 1;
-    RayPre r = ray_pre(o, d);
     Hit h;
-    h.t = INFINITY; h.b1 = h.b2 = 0.0f; h.leaf = -1; h.prim = 0x7FFFFFFF;
-    TStack st = make_stack(lds);
-    int node = 0;
-    while (true) {
-        BvhNode nd = nodes[node];
-        MRS_COUNT(kNodeCtr);
-        float tl, tr;
-        bool hl = slab(r, nd.n0.x, nd.n0.y, nd.n0.z, nd.n0.w, nd.n2.x, nd.n2.y, h.t, tl);
-        bool hr = slab(r, nd.n1.x, nd.n1.y, nd.n1.z, nd.n1.w, nd.n2.z, nd.n2.w, h.t, tr);
-        int refs[2] = {nd.n3.x, nd.n3.y};
-        bool hits[2] = {hl, hr};
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            if (hits[c] && refs[c] < 0) {
-                int code = ~refs[c];
-                int first = code >> 3, cnt = (code & 7) + 1;
-                for (int q = first; q < first + cnt; ++q) {
-                    TriRec tr3 = tris[q];
-                    MRS_COUNT(kTriCtr);
-                    float t, b1, b2;
-                    int prim = __float_as_int(tr3.a.w);
-                    if (tri_test(r, xyz(tr3.a), xyz(tr3.b), xyz(tr3.c), h.t, t, b1, b2) &&
-                        (t < h.t || prim < h.prim)) {
-                        h.t = t; h.b1 = b1; h.b2 = b2; h.leaf = q; h.prim = prim;
-                    }
-                }
-                hits[c] = false;
-            }
-        }
-        hl = hits[0]; hr = hits[1];
-        if (hl && hr) {
-            bool lfirst = tl <= tr;
-            st.push(lfirst ? refs[1] : refs[0], lfirst ? tr : tl);
-            node = lfirst ? refs[0] : refs[1];
-            continue;
-        }
-        if (hl) { node = refs[0]; continue; }
-        if (hr) { node = refs[1]; continue; }
-        bool found = false;
-        while (st.sp > 0) {
-            float t;
-            int n = st.pop(t);
-            if (!MRS_STACK_T || t <= h.t * 1.0000008f) { node = n; found = true; break; }
-        }
-        if (!found) break;
-    }
+    bool occl;
+    trace_wave<false>(nodes, tris, o, d, lds, h, occl);
     return h;
 }
 
 // any hit in (0, inf): visibility of a shadow ray
 __device__ __forceinline__ bool trace_any(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                           V3 o, V3 d, void *lds) {
-    constexpr int kNodeCtr = 2, kTriCtr = 3;
-    RayPre r = ray_pre(o, d);
+    Hit h;
+    bool occl;
+    trace_wave<true>(nodes, tris, o, d, lds, h, occl);
+    return occl;
+}
+
+#ifndef MRS_REFILL
+#define MRS_REFILL 48      // idle lanes that trigger a refill of a wavefront
+#endif
+
+// Work partitions of a persistent traversal queue, each with its own claim
+// counter on its own 128-byte line, so that claims do not serialise on one
+// address.  kClaimWords u32 words per launch.
+constexpr int kWorkParts = 64;
+constexpr int kClaimStride = 32;
+constexpr int kClaimWords = kWorkParts * kClaimStride;
+static_assert(MRS_REFILL >= 1 && MRS_REFILL <= 64, "a refill needs between 1 and 64 idle lanes");
+
+// Persistent traversal of queue entries [0, n).  Each lane traces one ray at
+// a time; once at least MRS_REFILL lanes of the wavefront have finished, the
+// idle lanes claim the next unclaimed entries of the wavefront's current
+// partition with one atomic per wavefront, so a wavefront runs until the
+// queue is drained instead of as long as its slowest ray (ray replacement,
+// after Aila and Laine, HPG 2009).  A drained partition sends the wavefront on
+// to the next one; after seeing all of them drained it stops.  claim points at
+// kClaimWords zeroed words.  load(i, o, d) fetches entry i's ray;
+// done(i, hit, occluded) stores its result.  Every lane of the launch must
+// call this (block sizes are multiples of 64).
+template <bool kAny, class Load, class Done>
+__device__ __forceinline__ void persistent_trace(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+                                                 uint32_t n, uint32_t *claim, void *lds, Load load, Done done) {
     TStack st = make_stack(lds);
-    int node = 0;
-    const float tmax = INFINITY;
+    RayPre r;
+    Hit h = no_hit();
+    bool occl = false;
+    int node = kNone;
+    int64_t item = -1;             // queue entry of this lane, -1 when idle
+    const uint32_t lane = __lane_id();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // starting partition: blocks are dealt round-robin to the 8 XCDs, so
+    // partition p is first worked on by the XCD p % 8
+    const uint32_t wave = blockIdx.x / 8 * (blockDim.x / 64) + threadIdx.x / 64;
+    int part = (int)(blockIdx.x % 8 + 8 * (wave % (kWorkParts / 8)));
+    int seen = 0;                  // drained partitions seen (wave-uniform)
     while (true) {
-        BvhNode nd = nodes[node];
-        MRS_COUNT(kNodeCtr);
-        float tl, tr;
-        bool hl = slab(r, nd.n0.x, nd.n0.y, nd.n0.z, nd.n0.w, nd.n2.x, nd.n2.y, tmax, tl);
-        bool hr = slab(r, nd.n1.x, nd.n1.y, nd.n1.z, nd.n1.w, nd.n2.z, nd.n2.w, tmax, tr);
-        int refs[2] = {nd.n3.x, nd.n3.y};
-        bool hits[2] = {hl, hr};
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            if (hits[c] && refs[c] < 0) {
-                int code = ~refs[c];
-                int first = code >> 3, cnt = (code & 7) + 1;
-                for (int q = first; q < first + cnt; ++q) {
-                    TriRec tr3 = tris[q];
-                    MRS_COUNT(kTriCtr);
-                    float t, b1, b2;
-                    if (tri_test(r, xyz(tr3.a), xyz(tr3.b), xyz(tr3.c), tmax, t, b1, b2)) return true;
+        if (seen < kWorkParts) {
+            uint64_t idle = __ballot(item < 0);
+            uint32_t nidle = (uint32_t)__popcll(idle);
+            if (nidle >= MRS_REFILL) {
+                const uint64_t lo = (uint64_t)n * part / kWorkParts, hi = (uint64_t)n * (part + 1) / kWorkParts;
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(claim + part * kClaimStride, nidle);
+                base = __builtin_amdgcn_readfirstlane(base);
+                if (lo + base + nidle >= hi) {
+                    part = part + 1 == kWorkParts ? 0 : part + 1;
+                    ++seen;
                 }
-                hits[c] = false;
+                if (item < 0) {
+                    uint64_t idx = lo + base + (uint64_t)__popcll(idle & below);
+                    if (idx < hi) {
+                        V3 o, d;
+                        load((uint32_t)idx, o, d);
+                        r = ray_pre(o, d);
+                        h = no_hit();
+                        occl = false;
+                        st.sp = 0;
+                        node = 0;
+                        item = (int64_t)idx;
+                    }
+                }
             }
         }
-        hl = hits[0]; hr = hits[1];
-        if (hl && hr) {
-            bool lfirst = tl <= tr;
-            st.push(lfirst ? refs[1] : refs[0], 0.0f);
-            node = lfirst ? refs[0] : refs[1];
-            continue;
+        if (__ballot(item >= 0) == 0 && seen >= kWorkParts) break;
+        trace_iter<kAny>(nodes, tris, item >= 0, r, h, occl, st, node);
+        if (item >= 0 && node == kNone) {
+            done((uint32_t)item, h, occl);
+            item = -1;
         }
-        if (hl) { node = refs[0]; continue; }
-        if (hr) { node = refs[1]; continue; }
-        if (st.sp == 0) break;
-        float t;
-        node = st.pop(t);
     }
-    return false;
 }
 
 }  // namespace mrs

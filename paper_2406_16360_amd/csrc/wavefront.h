@@ -338,15 +338,21 @@ __global__ void k_generate(GenArgs a) {
 struct TraceArgs {
     const BvhNode *nodes; const TriRec *tris;
     Queue q; float4 *hits; IterCtr *ctr; int it;
+    uint32_t *claim;      // kClaimWords zeroed claim counters
 };
 
-__global__ void k_trace_closest(TraceArgs a) {
+// persistent: launched with a fixed grid that fills the device once
+__global__ __launch_bounds__(256) void k_trace_closest(TraceArgs a) {
     extern __shared__ int lds_stack[];
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.ctr[a.it].n_live) return;
-    float4 o = a.q.o[i], d = a.q.d[i];
-    Hit h = trace_closest(a.nodes, a.tris, xyz(o), xyz(d), lds_stack);
-    a.hits[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf));
+    IterCtr &c = a.ctr[a.it];
+    const uint32_t n = c.n_live;
+    if (blockIdx.x * blockDim.x >= n) return;
+    persistent_trace<false>(
+        a.nodes, a.tris, n, a.claim, lds_stack,
+        [&](uint32_t i, V3 &o, V3 &d) { o = xyz(a.q.o[i]); d = xyz(a.q.d[i]); },
+        [&](uint32_t i, const Hit &h, bool) {
+            a.hits[i] = make_float4(h.t, h.b1, h.b2, __int_as_float(h.leaf));
+        });
 }
 
 struct ShadeArgs {
@@ -357,10 +363,38 @@ struct ShadeArgs {
     Tape tape; int use_tape;
 };
 
-__global__ void k_shade(ShadeArgs a) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kShadeBlock = 256;
+
+// One path vertex per thread.  A block first partitions its kShadeBlock queue
+// entries so that the hits, which run the RIS loop, fill the leading
+// wavefronts and the misses the trailing ones; results do not depend on
+// which thread handles an entry.
+__global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeArgs a) {
+    __shared__ uint32_t s_idx[kShadeBlock];
+    __shared__ uint32_t s_hit[kShadeBlock / 64], s_valid[kShadeBlock / 64];
     const uint32_t n = a.ctr[a.it].n_live;
-    const bool active = i < n;
+    const uint32_t i0 = blockIdx.x * kShadeBlock;
+    if (i0 >= n) return;
+    {
+        const uint32_t e = i0 + threadIdx.x;
+        const bool valid = e < n;
+        const bool hit = valid && __float_as_int(a.hits[e].w) >= 0;
+        const uint64_t mh = __ballot(hit), mv = __ballot(valid);
+        const int w = threadIdx.x / 64, lane = __lane_id();
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if (lane == 0) { s_hit[w] = (uint32_t)__popcll(mh); s_valid[w] = (uint32_t)__popcll(mv); }
+        __syncthreads();
+        uint32_t hits_before = 0, misses_before = 0, hits_total = 0;
+        for (int q = 0; q < kShadeBlock / 64; ++q) {
+            if (q < w) { hits_before += s_hit[q]; misses_before += s_valid[q] - s_hit[q]; }
+            hits_total += s_hit[q];
+        }
+        if (hit) s_idx[hits_before + __popcll(mh & below)] = e;
+        else if (valid) s_idx[hits_total + misses_before + __popcll(mv & ~mh & below)] = e;
+        __syncthreads();
+    }
+    const bool active = threadIdx.x < n - i0;
+    const uint32_t i = active ? s_idx[threadIdx.x] : 0u;
     bool emit = false, cont = false;
     float4 e_o, e_d, e_c, c_o, c_d, c_t;
     if (active) {
@@ -492,7 +526,12 @@ struct ShadowArgs {
     Tape tape; int use_tape;
 };
 
-__global__ void k_trace_shadow(ShadowArgs a) {
+// One shadow ray per thread.  (A persistent launch with ray replacement, as
+// for closest hits, measured slower: any-hit rays are short, and each refill
+// stalls the whole wavefront on the new rays' loads.)  A sample has at most
+// one shadow ray per iteration, so the accumulation into its output slot
+// needs no atomics.
+__global__ __launch_bounds__(256) void k_trace_shadow(ShadowArgs a) {
     extern __shared__ int lds_stack[];
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.ctr[a.it].n_shadow) return;
