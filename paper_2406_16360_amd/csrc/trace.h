@@ -106,16 +106,19 @@ struct TStack {
     int sp = 0;
     int spill_ref[kStackSize - kLdsStack];
     // the build rejects trees deeper than the stack, so a full stack is never
-    // reached; if it were, the entry is dropped rather than written out of bounds
+    // reached; if it were, the entry is dropped rather than written out of bounds.
+    // The LDS accesses are relaxed workgroup-scope atomics, which the compiler
+    // cannot fold with the private spill access into one slower flat access.
     __device__ __forceinline__ void push(int x) {
         if (sp >= kStackSize) return;
-        if (sp < kLdsStack) ref[sp * stride] = x;
+        if (sp < kLdsStack) __hip_atomic_store(ref + sp * stride, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else spill_ref[sp - kLdsStack] = x;
         ++sp;
     }
     __device__ __forceinline__ int pop() {
         --sp;
-        return sp < kLdsStack ? ref[sp * stride] : spill_ref[sp - kLdsStack];
+        if (sp < kLdsStack) return __hip_atomic_load(ref + sp * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return spill_ref[sp - kLdsStack];
     }
 };
 

@@ -369,7 +369,12 @@ constexpr int kShadeBlock = 256;
 // entries so that the hits, which run the RIS loop, fill the leading
 // wavefronts and the misses the trailing ones; results do not depend on
 // which thread handles an entry.
-__global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeArgs a) {
+// At least 4 wavefronts per SIMD (at most 128 VGPRs): the RIS loop waits on
+// chains of dependent table loads, and occupancy is what hides them.
+#ifndef MRS_SHADE_WAVES
+#define MRS_SHADE_WAVES 4
+#endif
+__global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS_SHADE_WAVES))) void k_shade(ShadeArgs a) {
     __shared__ uint32_t s_idx[kShadeBlock];
     __shared__ uint32_t s_hit[kShadeBlock / 64], s_valid[kShadeBlock / 64];
     const uint32_t n = a.ctr[a.it].n_live;
@@ -595,88 +600,95 @@ struct AdjArgs {
     float *gvmat, *galb, *grough, *gmetal, *genv;
 };
 
-// Gradient arrays addressed by the cache keys
-enum GradKind : uint32_t { GK_VMAT = 0, GK_ALBEDO, GK_ROUGH, GK_METAL, GK_ENV };
-__device__ __forceinline__ float *grad_base(const AdjArgs &a, uint32_t kind) {
-    switch (kind) {
-        case GK_VMAT: return a.gvmat;
-        case GK_ALBEDO: return a.galb;
-        case GK_ROUGH: return a.grough;
-        case GK_METAL: return a.gmetal;
-        default: return a.genv;
-    }
-}
-
-// Per-workgroup gradient cache in LDS: an open-addressing hash table keyed by
-// (array, element).  Neighbouring samples of a workgroup hit overlapping texels,
-// so their contributions are summed with LDS atomics and each distinct element
-// costs one global atomic when the workgroup flushes the table.  A probe
-// sequence that finds no slot falls back to a direct global atomic.
-constexpr int kGradCacheLog2 = 11;
+// Per-workgroup gradient cache in LDS: an open-addressing hash table with one
+// entry per gradient element group -- a material texel (albedo rgb, roughness,
+// metallic), a mesh vertex (its five material values) or an env texel (rgb) --
+// holding kGradVals partial sums.  Neighbouring samples of a workgroup hit
+// overlapping texels at the first vertex, and importance sampling sends many
+// of them to the same bright env texels, so their contributions are summed
+// with LDS atomics and each distinct element costs one global atomic when the
+// workgroup flushes the table.  Deeper vertices land on scattered texels with
+// little reuse and go straight to global atomics, as does a group whose probe
+// sequence finds no slot.
+constexpr int kGradCacheLog2 = 10;
 constexpr int kGradCacheSize = 1 << kGradCacheLog2;
+constexpr int kGradVals = 5;
 constexpr uint32_t kGradEmpty = 0xFFFFFFFFu;
 constexpr int kGradMaxProbe = 16;
+enum GradGroup : uint32_t { GG_TEXEL = 0, GG_VERTEX = 1, GG_ENV = 2 };
+
+// the gradient element of value c of group `group` at index i, or nullptr
+__device__ __forceinline__ float *grad_elem(const AdjArgs &a, uint32_t group, uint32_t i, int c) {
+    if (group == GG_ENV) return a.genv ? a.genv + 3u * i + c : nullptr;
+    if (group == GG_VERTEX) return a.gvmat ? a.gvmat + 5u * i + c : nullptr;
+    if (c < 3) return a.galb ? a.galb + 3u * i + c : nullptr;
+    if (c == 3) return a.grough ? a.grough + i : nullptr;
+    return a.gmetal ? a.gmetal + i : nullptr;
+}
 
 struct GradCache {
     uint32_t *keys;
-    float *vals;
-    __device__ __forceinline__ void add(const AdjArgs &a, uint32_t kind, uint32_t idx, float v) {
-        uint32_t key = (kind << 29) | idx;
+    float *vals;        // [kGradVals][kGradCacheSize]
+    // slot of the group's entry (claimed if new), or -1 when the probe fails
+    __device__ __forceinline__ int slot(uint32_t key) {
         uint32_t h = (key * 2654435761u) >> (32 - kGradCacheLog2);
         for (int p = 0; p < kGradMaxProbe; ++p) {
             uint32_t prev = atomicCAS(&keys[h], kGradEmpty, key);
-            if (prev == kGradEmpty || prev == key) {
-                atomicAdd(&vals[h], v);
-                return;
-            }
+            if (prev == kGradEmpty || prev == key) return (int)h;
             h = (h + 1) & (kGradCacheSize - 1);
         }
-        atomicAdd(grad_base(a, kind) + idx, v);
+        return -1;
+    }
+    // add the n values v[] (zeros skipped) of group `group` at index i
+    // (the LDS sums use workgroup scope and the global ones device scope, so
+    // the compiler cannot fold the two into one flat atomic)
+    template <int n>
+    __device__ __forceinline__ void add(const AdjArgs &a, bool cached, uint32_t group, uint32_t i, const float *v) {
+        int h = cached ? slot((group << 29) | i) : -1;
+        if (h >= 0) {
+#pragma unroll
+            for (int c = 0; c < n; ++c)
+                if (v[c] != 0.0f)
+                    __hip_atomic_fetch_add(&vals[c * kGradCacheSize + h], v[c], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+#pragma unroll
+        for (int c = 0; c < n; ++c)
+            if (v[c] != 0.0f)
+                if (float *p = grad_elem(a, group, i, c))
+                    __hip_atomic_fetch_add(p, v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
-__device__ __forceinline__ void scatter_material(const AdjArgs &a, GradCache &gc, const Interp &ip,
+// cached: the vertex is the first one of its path (coherent across a workgroup)
+__device__ __forceinline__ void scatter_material(const AdjArgs &a, GradCache &gc, bool cached, const Interp &ip,
                                                  const MatRaw &raw, V3 ga, float gr, float gmu) {
     // clamp masks: the derivative passes on the closed interval
-    float ma[3] = {(raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f,
-                   (raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f,
-                   (raw.a.z >= 0.0f && raw.a.z <= 1.0f) ? ga.z : 0.0f};
-    float mr = (raw.r >= kRoughMin && raw.r <= 1.0f) ? gr : 0.0f;
-    float mm = (raw.mu >= 0.0f && raw.mu <= 1.0f) ? gmu : 0.0f;
-    if (a.s.mat_mode == MRS_MAT_VERTEX) {
-        if (!a.gvmat) return;
-        for (int q = 0; q < 3; ++q) {
-            float w = ip.w[q];
-            uint32_t e = 5u * (uint32_t)ip.idx[q];
-            if (ma[0] != 0.0f) gc.add(a, GK_VMAT, e + 0, w * ma[0]);
-            if (ma[1] != 0.0f) gc.add(a, GK_VMAT, e + 1, w * ma[1]);
-            if (ma[2] != 0.0f) gc.add(a, GK_VMAT, e + 2, w * ma[2]);
-            if (mr != 0.0f) gc.add(a, GK_VMAT, e + 3, w * mr);
-            if (mm != 0.0f) gc.add(a, GK_VMAT, e + 4, w * mm);
-        }
-        return;
-    }
-    for (int q = 0; q < 4; ++q) {
+    float g[kGradVals] = {(raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f,
+                          (raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f,
+                          (raw.a.z >= 0.0f && raw.a.z <= 1.0f) ? ga.z : 0.0f,
+                          (raw.r >= kRoughMin && raw.r <= 1.0f) ? gr : 0.0f,
+                          (raw.mu >= 0.0f && raw.mu <= 1.0f) ? gmu : 0.0f};
+    const bool vertex = a.s.mat_mode == MRS_MAT_VERTEX;
+    if (vertex ? !a.gvmat : (!a.galb && !a.grough && !a.gmetal)) return;
+    const int nq = vertex ? 3 : 4;
+    for (int q = 0; q < nq; ++q) {
         float w = ip.w[q];
         if (w == 0.0f) continue;
-        uint32_t t = (uint32_t)ip.idx[q];
-        if (a.galb) {
-            if (ma[0] != 0.0f) gc.add(a, GK_ALBEDO, 3u * t + 0, w * ma[0]);
-            if (ma[1] != 0.0f) gc.add(a, GK_ALBEDO, 3u * t + 1, w * ma[1]);
-            if (ma[2] != 0.0f) gc.add(a, GK_ALBEDO, 3u * t + 2, w * ma[2]);
-        }
-        if (a.grough && mr != 0.0f) gc.add(a, GK_ROUGH, t, w * mr);
-        if (a.gmetal && mm != 0.0f) gc.add(a, GK_METAL, t, w * mm);
+        float v[kGradVals];
+#pragma unroll
+        for (int c = 0; c < kGradVals; ++c) v[c] = w * g[c];
+        gc.add<kGradVals>(a, cached, vertex ? GG_VERTEX : GG_TEXEL, (uint32_t)ip.idx[q], v);
     }
 }
 
 __device__ __forceinline__ void scatter_env(const AdjArgs &a, GradCache &gc, int tex, V3 g) {
     if (!a.genv || tex < 0) return;
     const float *raw = a.s.env.raw + 3 * (size_t)tex;
-    uint32_t e = 3u * (uint32_t)tex;
-    if (raw[0] >= 0.0f && g.x != 0.0f) gc.add(a, GK_ENV, e + 0, g.x);
-    if (raw[1] >= 0.0f && g.y != 0.0f) gc.add(a, GK_ENV, e + 1, g.y);
-    if (raw[2] >= 0.0f && g.z != 0.0f) gc.add(a, GK_ENV, e + 2, g.z);
+    float v[3] = {raw[0] >= 0.0f ? g.x : 0.0f, raw[1] >= 0.0f ? g.y : 0.0f, raw[2] >= 0.0f ? g.z : 0.0f};
+    if (v[0] == 0.0f && v[1] == 0.0f && v[2] == 0.0f) return;
+    gc.add<3>(a, true, GG_ENV, (uint32_t)tex, v);
 }
 
 // Detached-sampling gradient of one sample: with directions, selections and
@@ -785,7 +797,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, uint64_t j, Gra
                 gmu += dot(wb, bg.dmu);
             }
         }
-        scatter_material(a, gc, ip, raw, ga, gr, gmu);
+        scatter_material(a, gc, k == 1, ip, raw, ga, gr, gmu);
         T = T * Bk[k - 1];
     }
 }
@@ -793,10 +805,11 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, uint64_t j, Gra
 // one thread per sample; the workgroup's gradient cache is flushed at the end
 __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     __shared__ uint32_t keys[kGradCacheSize];
-    __shared__ float vals[kGradCacheSize];
+    __shared__ float vals[kGradVals * kGradCacheSize];
     for (int i = threadIdx.x; i < kGradCacheSize; i += blockDim.x) {
         keys[i] = kGradEmpty;
-        vals[i] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kGradVals; ++c) vals[c * kGradCacheSize + i] = 0.0f;
     }
     __syncthreads();
     GradCache gc{keys, vals};
@@ -805,7 +818,14 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     __syncthreads();
     for (int i = threadIdx.x; i < kGradCacheSize; i += blockDim.x) {
         uint32_t key = keys[i];
-        if (key != kGradEmpty) atomicAdd(grad_base(a, key >> 29) + (key & 0x1FFFFFFFu), vals[i]);
+        if (key == kGradEmpty) continue;
+        const uint32_t group = key >> 29, idx = key & 0x1FFFFFFFu;
+        const int n = group == GG_ENV ? 3 : kGradVals;
+        for (int c = 0; c < n; ++c) {
+            float v = vals[c * kGradCacheSize + i];
+            if (v == 0.0f) continue;
+            if (float *p = grad_elem(a, group, idx, c)) atomicAdd(p, v);
+        }
     }
 }
 
