@@ -110,12 +110,32 @@ struct Res {
     DevBuf qa_o, qa_d, qa_t, qb_o, qb_d, qb_t, hits, so, sd, sc; // path pool queues
     DevBuf ctr, sched, out;                                    // iteration counters, scheduler, sample radiance
     DevBuf ct_hit, ct_y, ct_rr;                                // chunk tape (recompute mode)
+    DevBuf grec;                                               // adjoint gradient records
     void release_all() {
         for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &views, &qa_o, &qa_d, &qa_t, &qb_o,
-                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr})
+                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec})
             b->release();
     }
 };
+
+// Layout of the adjoint's gradient records for a scene and the wanted arrays:
+// kMatRec floats per material texel (or mesh vertex) when any material
+// gradient is wanted, then kEnvRec floats per env texel when the env one is.
+// Offsets fit in 32 bits: validate() bounds the parameter arrays.
+struct GradRec {
+    uint32_t n_mat = 0, n_env = 0, env_base = 0;
+    size_t words = 0;
+};
+GradRec grad_rec(const mrs_scene *sc, const mrs_grads *gr) {
+    GradRec g;
+    const bool vertex = sc->mat_mode == MRS_MAT_VERTEX;
+    if (vertex ? gr->vmat != nullptr : (gr->albedo || gr->rough || gr->metal))
+        g.n_mat = vertex ? (uint32_t)sc->nv : (uint32_t)sc->tw * (uint32_t)sc->th;
+    if (gr->env) g.n_env = (uint32_t)sc->ew * (uint32_t)sc->eh;
+    g.env_base = kMatRec * g.n_mat;
+    g.words = (size_t)kMatRec * g.n_mat + (size_t)kEnvRec * g.n_env;
+    return g;
+}
 
 struct Workspace {
     std::mutex mu;
@@ -380,15 +400,31 @@ void resolve(const Job &job, const Chunk &ch, const Res &r, float *image, float 
 }
 
 mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, const float *dimg, const mrs_grads *gr,
-                   hipStream_t s) {
+                   const GradRec &gl, float *rec, hipStream_t s) {
+    if (gl.words == 0) return MRS_OK;
     for (uint64_t a0 = c0; a0 < c1; a0 += kAdjChunk) {
         uint64_t n = std::min<uint64_t>(kAdjChunk, c1 - a0);
         PROF(KID_ADJOINT, s);
-        AdjArgs aa{job.sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env};
-        k_adjoint<<<nblocks(n, 256), 256, 0, s>>>(aa);
+        AdjArgs aa{job.sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env,
+                   rec, gl.env_base, gl.n_mat > 0 ? 1 : 0};
+        k_adjoint<<<nblocks(n, kAdjBlock), kAdjBlock, 0, s>>>(aa);
     }
     HIPTRY(hipGetLastError(), "adjoint launch");
     return MRS_OK;
+}
+
+// zero the gradient records before the first adjoint launch of a backward pass
+void grad_rec_clear(const GradRec &gl, float *rec, hipStream_t s) {
+    if (gl.words) k_fill_u32<<<nblocks(gl.words, 256), 256, 0, s>>>((uint32_t *)rec, gl.words, 0u);
+}
+
+// add the gradient records into the caller's arrays after the last one
+void grad_rec_fold(const mrs_scene *sc, const GradRec &gl, const float *rec, const mrs_grads *gr, hipStream_t s) {
+    uint32_t n = std::max(gl.n_mat, gl.n_env);
+    if (n == 0) return;
+    FoldArgs f{rec, gl.n_mat, gl.n_env, gl.env_base, sc->mat_mode == MRS_MAT_VERTEX ? 1 : 0,
+               gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env};
+    k_grad_fold<<<nblocks(n, 256), 256, 0, s>>>(f);
 }
 
 mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B) {
@@ -448,17 +484,25 @@ mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, co
                             const mrs_tape *tape, const float *dimg, const mrs_grads *grads, hipStream_t s) {
     Job j = job;
     TRY(env_tables(sc, j, r, s));
-    if (tape) return adjoint(j, tape_view(tape), 0, j.S, dimg, grads, s);
-    uint64_t cap = max_chunk(chunks);
-    size_t n = (size_t)cap * j.op.B;
-    TRY(r.ct_hit.reserve(sizeof(float4) * n));
-    TRY(r.ct_y.reserve(sizeof(float4) * n));
-    TRY(r.ct_rr.reserve(sizeof(float) * n));
-    for (const Chunk &ch : chunks) {
-        Tape tp{r.ct_hit.as<float4>(), r.ct_y.as<float4>(), r.ct_rr.as<float>(), ch.c0, cap};
-        TRY(run_wavefront(j, ch, tp, 1, nullptr, r, s));
-        TRY(adjoint(j, tp, ch.c0, ch.c1, dimg, grads, s));
+    const GradRec gl = grad_rec(sc, grads);
+    if (gl.words) TRY(r.grec.reserve(4 * gl.words));
+    float *rec = r.grec.as<float>();
+    grad_rec_clear(gl, rec, s);
+    if (tape) {
+        TRY(adjoint(j, tape_view(tape), 0, j.S, dimg, grads, gl, rec, s));
+    } else {
+        uint64_t cap = max_chunk(chunks);
+        size_t n = (size_t)cap * j.op.B;
+        TRY(r.ct_hit.reserve(sizeof(float4) * n));
+        TRY(r.ct_y.reserve(sizeof(float4) * n));
+        TRY(r.ct_rr.reserve(sizeof(float) * n));
+        for (const Chunk &ch : chunks) {
+            Tape tp{r.ct_hit.as<float4>(), r.ct_y.as<float4>(), r.ct_rr.as<float>(), ch.c0, cap};
+            TRY(run_wavefront(j, ch, tp, 1, nullptr, r, s));
+            TRY(adjoint(j, tp, ch.c0, ch.c1, dimg, grads, gl, rec, s));
+        }
     }
+    grad_rec_fold(sc, gl, rec, grads, s);
     return MRS_OK;
 }
 
@@ -744,6 +788,7 @@ extern "C" mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *vi
             n_iter = std::max(n_iter, iterations(job, c.c1 - c.c0, (uint32_t)std::min<uint64_t>(job.pool, c.c1 - c.c0)));
     PTRY(reserve_pool(p->res, P, outmax, n_iter));
     if (p->has_grads) {
+        if (size_t words = grad_rec(scene, grads).words) PTRY(p->res.grec.reserve(4 * words));
         PTRY(decide_tape(job, opt, true, &p->tape));
         if (!p->tape) {
             size_t n = (size_t)max_chunk(p->bwd_chunks) * job.op.B;

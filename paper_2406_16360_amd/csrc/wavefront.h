@@ -597,126 +597,105 @@ struct AdjArgs {
     SceneDev s; ViewTable vt; Opts op; Tape tape;
     uint64_t g0, n;
     const float *dimg;
-    float *gvmat, *galb, *grough, *gmetal, *genv;
+    float *gvmat, *galb, *grough, *gmetal, *genv;   // the caller's arrays (null: not wanted)
+    float *rec;            // gradient records (see below), zeroed before the first chunk
+    uint32_t env_base;     // first word of the env records
+    int mat_on;            // some material gradient array is wanted
 };
 
-// Per-workgroup gradient cache in LDS: an open-addressing hash table with one
-// entry per gradient element group -- a material texel (albedo rgb, roughness,
-// metallic), a mesh vertex (its five material values) or an env texel (rgb) --
-// holding kGradVals partial sums.  Neighbouring samples of a workgroup hit
-// overlapping texels at the first vertex, and importance sampling sends many
-// of them to the same bright env texels, so their contributions are summed
-// with LDS atomics and each distinct element costs one global atomic when the
-// workgroup flushes the table.  Deeper vertices land on scattered texels with
-// little reuse and go straight to global atomics, as does a group whose probe
-// sequence finds no slot.
-constexpr int kGradCacheLog2 = 10;
-constexpr int kGradCacheSize = 1 << kGradCacheLog2;
-constexpr int kGradVals = 5;
-constexpr uint32_t kGradEmpty = 0xFFFFFFFFu;
-constexpr int kGradMaxProbe = 16;
-enum GradGroup : uint32_t { GG_TEXEL = 0, GG_VERTEX = 1, GG_ENV = 2 };
+// ---------------------------------------------------------------------------
+// Gradient scatter.  The adjoint accumulates into an internal record buffer:
+// one kMatRec-float record per material texel (texture mode: albedo rgb,
+// roughness, metallic) or per mesh vertex (vertex mode: its five values), then
+// one kEnvRec-float record per env texel (rgb).  A wavefront stages the
+// (offset, value) pairs of its lanes in LDS, lane after lane, and issues them
+// transposed, so that one atomic instruction covers a few lanes' consecutive
+// record words instead of 64 scattered words.  The atomics are carried out
+// past L2, one memory-side request per cache line an instruction touches, so
+// this cuts the requests several fold.  k_grad_fold then adds the records
+// into the caller's arrays.
+// ---------------------------------------------------------------------------
+constexpr int kMatRec = 8, kEnvRec = 4;
+constexpr int kScatSlots = 13;   // pairs a lane stages per flush
+constexpr int kAdjBlock = 256;
 
-// the gradient element of value c of group `group` at index i, or nullptr
-__device__ __forceinline__ float *grad_elem(const AdjArgs &a, uint32_t group, uint32_t i, int c) {
-    if (group == GG_ENV) return a.genv ? a.genv + 3u * i + c : nullptr;
-    if (group == GG_VERTEX) return a.gvmat ? a.gvmat + 5u * i + c : nullptr;
-    if (c < 3) return a.galb ? a.galb + 3u * i + c : nullptr;
-    if (c == 3) return a.grough ? a.grough + i : nullptr;
-    return a.gmetal ? a.gmetal + i : nullptr;
-}
-
-struct GradCache {
-    uint32_t *keys;
-    float *vals;        // [kGradVals][kGradCacheSize]
-    // slot of the group's entry (claimed if new), or -1 when the probe fails
-    __device__ __forceinline__ int slot(uint32_t key) {
-        uint32_t h = (key * 2654435761u) >> (32 - kGradCacheLog2);
-        for (int p = 0; p < kGradMaxProbe; ++p) {
-            uint32_t prev = atomicCAS(&keys[h], kGradEmpty, key);
-            if (prev == kGradEmpty || prev == key) return (int)h;
-            h = (h + 1) & (kGradCacheSize - 1);
-        }
-        return -1;
+struct WaveScatter {
+    uint32_t *off;       // this wavefront's staging in LDS: [64][kScatSlots] offsets,
+    float *val;          // values,
+    int *cnt;            // and [64] counts
+    float *rec;
+    uint32_t lane;
+    int n;               // pairs staged by this lane
+    __device__ __forceinline__ void put(uint32_t o, float v) {
+        if (v == 0.0f || n >= kScatSlots) return;
+        off[lane * kScatSlots + n] = o;
+        val[lane * kScatSlots + n] = v;
+        ++n;
     }
-    // add the n values v[] (zeros skipped) of group `group` at index i
-    // (the LDS sums use workgroup scope and the global ones device scope, so
-    // the compiler cannot fold the two into one flat atomic)
-    template <int n>
-    __device__ __forceinline__ void add(const AdjArgs &a, bool cached, uint32_t group, uint32_t i, const float *v) {
-        int h = cached ? slot((group << 29) | i) : -1;
-        if (h >= 0) {
+    // issues every staged pair; all lanes of the wavefront call it together
+    __device__ __forceinline__ void flush() {
+        cnt[lane] = n;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-            for (int c = 0; c < n; ++c)
-                if (v[c] != 0.0f)
-                    __hip_atomic_fetch_add(&vals[c * kGradCacheSize + h], v[c], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            return;
+        for (int j = 0; j < kScatSlots; ++j) {
+            const uint32_t e = j * 64 + lane, src = e / kScatSlots, r = e - src * kScatSlots;
+            if ((int)r < cnt[src]) atomicAdd(rec + off[e], val[e]);
         }
-#pragma unroll
-        for (int c = 0; c < n; ++c)
-            if (v[c] != 0.0f)
-                if (float *p = grad_elem(a, group, i, c))
-                    __hip_atomic_fetch_add(p, v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        n = 0;
     }
 };
 
-// cached: the vertex is the first one of its path (coherent across a workgroup)
-__device__ __forceinline__ void scatter_material(const AdjArgs &a, GradCache &gc, bool cached, const Interp &ip,
-                                                 const MatRaw &raw, V3 ga, float gr, float gmu) {
-    // clamp masks: the derivative passes on the closed interval
-    float g[kGradVals] = {(raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f,
-                          (raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f,
-                          (raw.a.z >= 0.0f && raw.a.z <= 1.0f) ? ga.z : 0.0f,
-                          (raw.r >= kRoughMin && raw.r <= 1.0f) ? gr : 0.0f,
-                          (raw.mu >= 0.0f && raw.mu <= 1.0f) ? gmu : 0.0f};
-    const bool vertex = a.s.mat_mode == MRS_MAT_VERTEX;
-    if (vertex ? !a.gvmat : (!a.galb && !a.grough && !a.gmetal)) return;
-    const int nq = vertex ? 3 : 4;
-    for (int q = 0; q < nq; ++q) {
-        float w = ip.w[q];
+// material pairs of interpolation entries q0 and q1 (those that exist)
+__device__ __forceinline__ void put_material(WaveScatter &ws, const Interp &ip, int q0, const float *gm) {
+    for (int q = q0; q < q0 + 2 && q < ip.n; ++q) {
+        const float w = ip.w[q];
         if (w == 0.0f) continue;
-        float v[kGradVals];
+        const uint32_t base = kMatRec * (uint32_t)ip.idx[q];
 #pragma unroll
-        for (int c = 0; c < kGradVals; ++c) v[c] = w * g[c];
-        gc.add<kGradVals>(a, cached, vertex ? GG_VERTEX : GG_TEXEL, (uint32_t)ip.idx[q], v);
+        for (int c = 0; c < 5; ++c) ws.put(base + c, w * gm[c]);
     }
-}
-
-__device__ __forceinline__ void scatter_env(const AdjArgs &a, GradCache &gc, int tex, V3 g) {
-    if (!a.genv || tex < 0) return;
-    const float *raw = a.s.env.raw + 3 * (size_t)tex;
-    float v[3] = {raw[0] >= 0.0f ? g.x : 0.0f, raw[1] >= 0.0f ? g.y : 0.0f, raw[2] >= 0.0f ? g.z : 0.0f};
-    if (v[0] == 0.0f && v[1] == 0.0f && v[2] == 0.0f) return;
-    gc.add<3>(a, true, GG_ENV, (uint32_t)tex, v);
 }
 
 // Detached-sampling gradient of one sample: with directions, selections and
 // all pdf / reservoir weights held fixed, C = sum_k T_k (.) D_k and
 // T_{k+1} = T_k (.) beta_k, so dC/dm_k = T_k (.) (dD_k/dm_k + dbeta_k/dm_k (.) Li_{k+1})
 // with Li_k = D_k + beta_k (.) Li_{k+1} accumulated from the last vertex back.
-__device__ __forceinline__ void adjoint_sample(const AdjArgs &a, uint64_t j, GradCache &gc) {
-    uint64_t g = a.g0 + j;
-    SampleId sid = decode(a.vt, g);
-    const ViewDev &vw = a.vt.v[sid.view];
-    Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
-    const float *gi = a.dimg + 3 * (uint64_t)(vw.pixel_offset + (int64_t)sid.pixel);
-    float inv_spp = 1.0f / (float)vw.spp;
-    V3 gp = V3{gi[0] * inv_spp, gi[1] * inv_spp, gi[2] * inv_spp};
-    if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return;
-    float4 u = rng.draw(0, 0);
-    V3 o, d;
-    camera_ray(vw, sid.pixel, u.x, u.y, o, d);
+// The vertex loop of the scatter runs in step across the wavefront.
+__device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uint64_t j, WaveScatter &ws) {
     const int B = a.op.B;
+    uint64_t g = a.g0 + j;
+    V3 gp = V3{0, 0, 0};
+    bool live = false;
+    Rng rng{a.op.k0, a.op.k1, 0, 0, 0};
+    V3 o, d;
+    if (valid) {
+        SampleId sid = decode(a.vt, g);
+        const ViewDev &vw = a.vt.v[sid.view];
+        rng = Rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
+        const float *gi = a.dimg + 3 * (uint64_t)(vw.pixel_offset + (int64_t)sid.pixel);
+        float inv_spp = 1.0f / (float)vw.spp;
+        gp = V3{gi[0] * inv_spp, gi[1] * inv_spp, gi[2] * inv_spp};
+        live = !(gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f);
+        if (live) {
+            float4 u = rng.draw(0, 0);
+            camera_ray(vw, sid.pixel, u.x, u.y, o, d);
+        }
+    }
     V3 Dk[MRS_MAX_BOUNCES], Bk[MRS_MAX_BOUNCES], Lk[MRS_MAX_BOUNCES], dk[MRS_MAX_BOUNCES];
     int nv = 0;
+    int miss_tex = -1;    // env texel of a primary miss
     // pass 1: per-vertex direct term D_k and continuation weight beta_k
-    for (int k = 1; k <= B; ++k) {
+    for (int k = 1; live && k <= B; ++k) {
         uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
         float4 th = a.tape.hit[ti];
         int leaf = __float_as_int(th.z);
         if (leaf < 0) {
-            if (k == 1) scatter_env(a, gc, __float_as_int(th.w), gp);
+            if (k == 1) miss_tex = __float_as_int(th.w);
             break;
         }
         dk[k - 1] = d;
@@ -754,78 +733,125 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, uint64_t j, Gra
     }
     // pass 2: local derivatives, scattered through interpolation weights
     V3 T = V3{1, 1, 1};
-    for (int k = 1; k <= nv; ++k) {
-        if (a.op.grad_mode == MRS_GRAD_PRIMARY && k > 1) break;
-        uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
-        float4 th = a.tape.hit[ti];
-        int leaf = __float_as_int(th.z);
-        V3 dd = dk[k - 1];
-        Surf S = surface(a.s, leaf, th.x, th.y, dd);
+    for (int k = 1; k <= B; ++k) {
+        const bool has = live && k <= nv && !(a.op.grad_mode == MRS_GRAD_PRIMARY && k > 1);
+        const bool miss = live && k == 1 && miss_tex >= 0;
+        if (__ballot(has || miss) == 0) break;
+        float gm[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         Interp ip;
-        MatRaw raw = fetch_material(a.s, S.prim, th.x, th.y, ip);
-        Mat m = clamp_material(raw);
-        Lobe L = make_lobe(m, to_local(S.F, dd * -1.0f), a.op.spec);
-        V3 ga = V3{0, 0, 0};
-        float gr = 0.0f, gmu = 0.0f;
-        V3 w = gp * T;   // dL/dC weighted by throughput
-        float4 ty = a.tape.y[ti];
-        if (ty.w > 0.0f) {
-            V3 yl = to_local(S.F, xyz(ty));
-            int tex = __float_as_int(th.w);
-            float4 lp = a.s.env.lp[tex];
-            V3 Lv = V3{lp.x, lp.y, lp.z};
-            float cw = yl.z * ty.w;
-            BrdfGrad bg = brdf_grad(L, m, yl);
-            V3 wl = w * Lv * cw;
-            ga = ga + wl * bg.da;
-            gr += dot(wl, bg.dr);
-            gmu += dot(wl, bg.dmu);
-            V3 f = brdf_eval(L, yl);
-            scatter_env(a, gc, tex, w * f * cw);
-        }
-        if (k < nv) {
-            float rr = a.tape.rr[ti];
-            float4 uc = rng.draw((uint32_t)k, kBlockCont);
-            V3 wl;
-            mix_sample(L, uc.x, uc.y, uc.z, wl);
-            float q = mix_pdf(L, wl);
-            if (q > 0.0f) {
-                BrdfGrad bg = brdf_grad(L, m, wl);
-                V3 wb = w * Lk[k - 1] * (wl.z / q * rr);
-                ga = ga + wb * bg.da;
-                gr += dot(wb, bg.dr);
-                gmu += dot(wb, bg.dmu);
+        ip.n = 0;
+        int etex = miss ? miss_tex : -1;
+        V3 ge = gp;
+        if (has) {
+            uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
+            float4 th = a.tape.hit[ti];
+            int leaf = __float_as_int(th.z);
+            V3 dd = dk[k - 1];
+            Surf S = surface(a.s, leaf, th.x, th.y, dd);
+            MatRaw raw = fetch_material(a.s, S.prim, th.x, th.y, ip);
+            Mat m = clamp_material(raw);
+            Lobe L = make_lobe(m, to_local(S.F, dd * -1.0f), a.op.spec);
+            V3 ga = V3{0, 0, 0};
+            float gr = 0.0f, gmu = 0.0f;
+            V3 w = gp * T;   // dL/dC weighted by throughput
+            float4 ty = a.tape.y[ti];
+            if (ty.w > 0.0f) {
+                V3 yl = to_local(S.F, xyz(ty));
+                int tex = __float_as_int(th.w);
+                float4 lp = a.s.env.lp[tex];
+                V3 Lv = V3{lp.x, lp.y, lp.z};
+                float cw = yl.z * ty.w;
+                BrdfGrad bg = brdf_grad(L, m, yl);
+                V3 wl = w * Lv * cw;
+                ga = ga + wl * bg.da;
+                gr += dot(wl, bg.dr);
+                gmu += dot(wl, bg.dmu);
+                etex = tex;
+                ge = w * brdf_eval(L, yl) * cw;
             }
+            if (k < nv) {
+                float rr = a.tape.rr[ti];
+                float4 uc = rng.draw((uint32_t)k, kBlockCont);
+                V3 wl;
+                mix_sample(L, uc.x, uc.y, uc.z, wl);
+                float q = mix_pdf(L, wl);
+                if (q > 0.0f) {
+                    BrdfGrad bg = brdf_grad(L, m, wl);
+                    V3 wb = w * Lk[k - 1] * (wl.z / q * rr);
+                    ga = ga + wb * bg.da;
+                    gr += dot(wb, bg.dr);
+                    gmu += dot(wb, bg.dmu);
+                }
+            }
+            // clamp masks (the derivative passes on the closed interval) and
+            // the arrays the caller wants
+            const bool vertex = a.s.mat_mode == MRS_MAT_VERTEX;
+            const bool alb = vertex ? a.gvmat != nullptr : a.galb != nullptr;
+            const bool rgh = vertex ? a.gvmat != nullptr : a.grough != nullptr;
+            const bool mtl = vertex ? a.gvmat != nullptr : a.gmetal != nullptr;
+            gm[0] = (alb && raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f;
+            gm[1] = (alb && raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f;
+            gm[2] = (alb && raw.a.z >= 0.0f && raw.a.z <= 1.0f) ? ga.z : 0.0f;
+            gm[3] = (rgh && raw.r >= kRoughMin && raw.r <= 1.0f) ? gr : 0.0f;
+            gm[4] = (mtl && raw.mu >= 0.0f && raw.mu <= 1.0f) ? gmu : 0.0f;
+            T = T * Bk[k - 1];
         }
-        scatter_material(a, gc, k == 1, ip, raw, ga, gr, gmu);
-        T = T * Bk[k - 1];
+        // group 1: interpolation entries 0 and 1, and the env texel
+        if (has && a.mat_on) put_material(ws, ip, 0, gm);
+        if (etex >= 0 && a.genv) {
+            const float *raw = a.s.env.raw + 3 * (size_t)etex;
+            const uint32_t base = a.env_base + kEnvRec * (uint32_t)etex;
+            ws.put(base + 0, raw[0] >= 0.0f ? ge.x : 0.0f);
+            ws.put(base + 1, raw[1] >= 0.0f ? ge.y : 0.0f);
+            ws.put(base + 2, raw[2] >= 0.0f ? ge.z : 0.0f);
+        }
+        ws.flush();
+        // group 2: interpolation entries 2 and 3
+        if (has && a.mat_on) put_material(ws, ip, 2, gm);
+        ws.flush();
     }
 }
 
-// one thread per sample; the workgroup's gradient cache is flushed at the end
-__global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
-    __shared__ uint32_t keys[kGradCacheSize];
-    __shared__ float vals[kGradVals * kGradCacheSize];
-    for (int i = threadIdx.x; i < kGradCacheSize; i += blockDim.x) {
-        keys[i] = kGradEmpty;
-#pragma unroll
-        for (int c = 0; c < kGradVals; ++c) vals[c * kGradCacheSize + i] = 0.0f;
-    }
-    __syncthreads();
-    GradCache gc{keys, vals};
-    uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (j < a.n) adjoint_sample(a, j, gc);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kGradCacheSize; i += blockDim.x) {
-        uint32_t key = keys[i];
-        if (key == kGradEmpty) continue;
-        const uint32_t group = key >> 29, idx = key & 0x1FFFFFFFu;
-        const int n = group == GG_ENV ? 3 : kGradVals;
-        for (int c = 0; c < n; ++c) {
-            float v = vals[c * kGradCacheSize + i];
-            if (v == 0.0f) continue;
-            if (float *p = grad_elem(a, group, idx, c)) atomicAdd(p, v);
+// one thread per sample, every lane in the vertex loop of the scatter
+__global__ void __launch_bounds__(kAdjBlock) k_adjoint(AdjArgs a) {
+    __shared__ uint32_t s_off[kAdjBlock * kScatSlots];
+    __shared__ float s_val[kAdjBlock * kScatSlots];
+    __shared__ int s_cnt[kAdjBlock];
+    const uint32_t w = threadIdx.x / 64;
+    WaveScatter ws{s_off + w * 64 * kScatSlots, s_val + w * 64 * kScatSlots, s_cnt + w * 64, a.rec,
+                   (uint32_t)__lane_id(), 0};
+    uint64_t j = blockIdx.x * (uint64_t)kAdjBlock + threadIdx.x;
+    adjoint_sample(a, j < a.n, j, ws);
+}
+
+// adds the gradient records into the caller's arrays, one record per thread
+struct FoldArgs {
+    const float *rec;
+    uint32_t n_mat, n_env, env_base;
+    int vertex_mode;
+    float *gvmat, *galb, *grough, *gmetal, *genv;
+};
+
+__global__ void k_grad_fold(FoldArgs f) {
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i < f.n_mat) {
+        const float4 r0 = *(const float4 *)(f.rec + kMatRec * i);
+        const float r4 = f.rec[kMatRec * i + 4];
+        if (f.vertex_mode) {
+            if (f.gvmat) {
+                float *p = f.gvmat + 5 * i;
+                p[0] += r0.x; p[1] += r0.y; p[2] += r0.z; p[3] += r0.w; p[4] += r4;
+            }
+        } else {
+            if (f.galb) { float *p = f.galb + 3 * i; p[0] += r0.x; p[1] += r0.y; p[2] += r0.z; }
+            if (f.grough) f.grough[i] += r0.w;
+            if (f.gmetal) f.gmetal[i] += r4;
         }
+    }
+    if (i < f.n_env && f.genv) {
+        const float4 r = *(const float4 *)(f.rec + f.env_base + kEnvRec * i);
+        float *p = f.genv + 3 * i;
+        p[0] += r.x; p[1] += r.y; p[2] += r.z;
     }
 }
 
