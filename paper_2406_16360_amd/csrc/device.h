@@ -269,15 +269,23 @@ __device__ __forceinline__ BrdfGrad brdf_grad(const Lobe &L, const Mat &m, V3 wi
 // environment map (equirectangular, +y up): theta = acos(d_y),
 // phi = atan2(d_x, -d_z), u = phi / 2pi + 1/2, v = theta / pi; nearest texel
 // ----------------------------------------------------------------------------
+// The normalised CDFs are stored as intervals, entry i = (cdf[i], cdf[i + 1]),
+// so one aligned 16-byte load gives both ends of a bin.
 struct EnvTables {
-    const double *marg;     // [H + 1] normalised marginal CDF over rows
-    const double *cond;     // [H][W + 1] normalised conditional CDFs
+    const double2 *mpair;   // [H] marginal CDF over rows, as intervals
+    const double2 *cpair;   // [H][W] conditional CDF of each row, as intervals
     const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
     const int32_t *gcond;   // [H][W] guide per row
     const float4 *lp;       // [H][W] (L_r, L_g, L_b clamped >= 0, pdf_uv / (2 pi^2))
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
     const double *total;    // device: total sampling weight (no valid sample when 0)
+};
+
+// the marginal intervals and guide, from the tables or from a copy in LDS
+struct MargView {
+    const double2 *pair;
+    const int32_t *guide;
 };
 
 __device__ __forceinline__ int env_texel_of(const EnvTables &e, V3 d) {
@@ -298,29 +306,30 @@ __device__ __forceinline__ float env_pdf_dir(const EnvTables &e, V3 d, int texel
 }
 
 // smallest i with cdf[i + 1] > u (cdf[0] = 0 <= u < 1 = cdf[n]): the unique i
-// with cdf[i] <= u < cdf[i + 1].  The guide entry is only a starting point;
-// walking back then forward makes the answer exact whatever the guide is.
-__device__ __forceinline__ int cdf_walk(const double *cdf, int start, int n, double u) {
+// with cdf[i] <= u < cdf[i + 1], over the intervals iv[i] = (cdf[i], cdf[i + 1]).
+// The guide entry is only a starting point; walking back then forward makes
+// the answer exact whatever the guide is.  p receives iv[i].
+__device__ __forceinline__ int interval_walk(const double2 *iv, int start, int n, double u, double2 &p) {
     int i = min(max(start, 0), n - 1);
-    while (i > 0 && cdf[i] > u) --i;
-    while (i < n - 1 && !(cdf[i + 1] > u)) ++i;
+    p = iv[i];
+    while (i > 0 && p.x > u) { --i; p = iv[i]; }
+    while (i < n - 1 && !(p.y > u)) { ++i; p = iv[i]; }
     return i;
 }
 
 // CDF inversion (row from the marginal, column from the row's conditional,
 // linear remainder inside the texel), in double like the tables.
-__device__ __forceinline__ bool env_sample(const EnvTables &e, float u0f, float u1f, V3 &dir, int &texel,
-                                           float4 &lp, float &pdf) {
+__device__ __forceinline__ bool env_sample(const EnvTables &e, const MargView &mv, float u0f, float u1f, V3 &dir,
+                                           int &texel, float4 &lp, float &pdf) {
     if (!(*e.total > 0.0)) return false;
     double u0 = u0f, u1 = u1f;
-    int gi = min((int)(u0 * e.H), e.H - 1);
-    int i = cdf_walk(e.marg, e.gmarg[gi], e.H, u0);
+    double2 pm, pc;
+    int i = interval_walk(mv.pair, mv.guide[min((int)(u0 * e.H), e.H - 1)], e.H, u0, pm);
     // the CDF differences are formed in double, the in-texel fractions in float
-    float fv = __fdividef((float)(u0 - e.marg[i]), (float)(e.marg[i + 1] - e.marg[i]));
-    const double *cr = e.cond + (size_t)i * (e.W + 1);
-    int gj = min((int)(u1 * e.W), e.W - 1);
-    int j = cdf_walk(cr, e.gcond[(size_t)i * e.W + gj], e.W, u1);
-    float fu = __fdividef((float)(u1 - cr[j]), (float)(cr[j + 1] - cr[j]));
+    float fv = __fdividef((float)(u0 - pm.x), (float)(pm.y - pm.x));
+    const size_t row = (size_t)i * e.W;
+    int j = interval_walk(e.cpair + row, e.gcond[row + min((int)(u1 * e.W), e.W - 1)], e.W, u1, pc);
+    float fu = __fdividef((float)(u1 - pc.x), (float)(pc.y - pc.x));
     float v = ((float)i + fv) / (float)e.H, u = ((float)j + fu) / (float)e.W;
     float st, ct, sp, cp;
     sincospif(v, &st, &ct);                   // theta = pi v

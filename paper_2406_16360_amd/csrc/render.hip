@@ -105,14 +105,14 @@ struct Chunk { uint64_t c0, c1, pix0, pix1; };
 // Device buffers one launch sequence works in: the library's shared
 // workspace for eager calls, or a plan's own set.
 struct Res {
-    DevBuf wts, cond, marg, rowsum, info, lp, gmarg, gcond;    // environment tables
+    DevBuf wts, cond, marg, rowsum, info, lp, gmarg, gcond, mpair, cpair;   // environment tables
     DevBuf views;                                              // ViewDev table
     DevBuf qa_o, qa_d, qa_t, qb_o, qb_d, qb_t, hits, so, sd, sc; // path pool queues
     DevBuf ctr, sched, out;                                    // iteration counters, scheduler, sample radiance
     DevBuf ct_hit, ct_y, ct_rr;                                // chunk tape (recompute mode)
     DevBuf grec;                                               // adjoint gradient records
     void release_all() {
-        for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &views, &qa_o, &qa_d, &qa_t, &qb_o,
+        for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &views, &qa_o, &qa_d, &qa_t, &qb_o,
                           &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec})
             b->release();
     }
@@ -303,6 +303,8 @@ mrs_status reserve_env(const mrs_scene *sc, Res &r) {
     TRY(r.lp.reserve(sizeof(float4) * nt));
     TRY(r.gmarg.reserve(sizeof(int32_t) * H));
     TRY(r.gcond.reserve(sizeof(int32_t) * nt));
+    TRY(r.mpair.reserve(sizeof(double2) * H));
+    TRY(r.cpair.reserve(sizeof(double2) * nt));
     return MRS_OK;
 }
 
@@ -332,10 +334,10 @@ mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
         k_env_marg<<<1, 64, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
         k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.info.as<double>(), r.marg.as<double>(),
                                             r.cond.as<double>(), r.lp.as<float4>(), r.gmarg.as<int32_t>(),
-                                            r.gcond.as<int32_t>());
+                                            r.gcond.as<int32_t>(), r.mpair.as<double2>(), r.cpair.as<double2>());
     }
     EnvTables &e = job.sd.env;
-    e.marg = r.marg.as<double>(); e.cond = r.cond.as<double>();
+    e.mpair = r.mpair.as<double2>(); e.cpair = r.cpair.as<double2>();
     e.gmarg = r.gmarg.as<int32_t>(); e.gcond = r.gcond.as<int32_t>();
     e.lp = r.lp.as<float4>(); e.raw = sc->env; e.total = r.info.as<double>();
     e.W = W; e.H = H;
@@ -379,7 +381,8 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
             PROF(KID_SHADE, s);
             ShadeArgs sa{job.sd, job.vt, job.op, qa, qb, r.hits.as<float4>(), ctr, it, r.so.as<float4>(),
                          r.sd.as<float4>(), r.sc.as<float4>(), r.out.as<float4>(), ch.c0, hash, tape, use_tape};
-            k_shade<<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
+            if (job.sd.env.H <= kEnvLdsRows) k_shade<true><<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
+            else k_shade<false><<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
         }
         {
             PROF(KID_SHADOW, s);

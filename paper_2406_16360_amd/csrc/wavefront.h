@@ -269,9 +269,16 @@ __global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__r
 __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
                              const double *__restrict__ info, const double *__restrict__ marg,
                              const double *__restrict__ cond, float4 *__restrict__ lp, int32_t *__restrict__ gmarg,
-                             int32_t *__restrict__ gcond) {
+                             int32_t *__restrict__ gcond, double2 *__restrict__ mpair, double2 *__restrict__ cpair) {
     int i = blockIdx.x;
     double total = info[0];
+    // the CDFs as intervals (cdf[t], cdf[t + 1])
+    if (i < H) {
+        const double *cr = cond + (size_t)i * (W + 1);
+        for (int j = threadIdx.x; j < W; j += blockDim.x) cpair[(size_t)i * W + j] = make_double2(cr[j], cr[j + 1]);
+    } else {
+        for (int t = threadIdx.x; t < H; t += blockDim.x) mpair[t] = make_double2(marg[t], marg[t + 1]);
+    }
     double scale = total > 0.0 ? (double)W * (double)H / (2.0 * 3.14159265358979323846 * 3.14159265358979323846 * total) : 0.0;
     if (i < H) {
         const double *cr = cond + (size_t)i * (W + 1);
@@ -371,16 +378,30 @@ constexpr int kShadeBlock = 256;
 // which thread handles an entry.
 // At least 4 wavefronts per SIMD (at most 128 VGPRs): the RIS loop waits on
 // chains of dependent table loads, and occupancy is what hides them.
+// kMargLds: the env's marginal intervals and guide (H <= kEnvLdsRows) are
+// copied into LDS first, so the row search of an env candidate costs no
+// vector-memory instructions.
 #ifndef MRS_SHADE_WAVES
 #define MRS_SHADE_WAVES 4
 #endif
+constexpr int kEnvLdsRows = 1024;
+template <bool kMargLds>
 __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS_SHADE_WAVES))) void k_shade(ShadeArgs a) {
     __shared__ uint32_t s_idx[kShadeBlock];
     __shared__ uint32_t s_hit[kShadeBlock / 64], s_valid[kShadeBlock / 64];
+    __shared__ double2 s_mpair[kMargLds ? kEnvLdsRows : 1];
+    __shared__ int32_t s_gmarg[kMargLds ? kEnvLdsRows : 1];
     const uint32_t n = a.ctr[a.it].n_live;
     const uint32_t i0 = blockIdx.x * kShadeBlock;
     if (i0 >= n) return;
-    {
+    if (kMargLds) {
+        for (int t = threadIdx.x; t < a.s.env.H; t += kShadeBlock) {
+            s_mpair[t] = a.s.env.mpair[t];
+            s_gmarg[t] = a.s.env.gmarg[t];
+        }
+    }
+    const MargView marg = kMargLds ? MargView{s_mpair, s_gmarg} : MargView{a.s.env.mpair, a.s.env.gmarg};
+    {   // (the partition's barrier also publishes the LDS copy)
         const uint32_t e = i0 + threadIdx.x;
         const bool valid = e < n;
         const bool hit = valid && __float_as_int(a.hits[e].w) >= 0;
@@ -447,7 +468,7 @@ __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS
                     float4 lp;
                     float qe, qb;
                     if (s < Me) {
-                        if (!env_sample(a.s.env, u.x, u.y, dir, tex, lp, qe)) continue;
+                        if (!env_sample(a.s.env, marg, u.x, u.y, dir, tex, lp, qe)) continue;
                         wl = to_local(S.F, dir);
                     } else {
                         int lb = mix_sample(L, u.x, u.y, u.z, wl);
