@@ -139,6 +139,22 @@ typedef struct {
  * 2^27), MRS_ENOMEM, MRS_EHIP. */
 mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
                          void *stream, mrs_bvh **out);
+
+/* Hierarchies mrs_build_bvh_with can build over the same Morton order. */
+enum {
+    MRS_BVH_LBVH = 0,   /* Karras radix tree: what mrs_build_bvh builds */
+    MRS_BVH_PLOC = 1    /* Meister and Bittner, "Parallel Locally-Ordered Clustering for Bounding
+                           Volume Hierarchy Construction" (TVCG 2018): rounds that merge mutual
+                           nearest neighbours within 16 sorted positions by the surface area of
+                           their union box.  Fewer node visits per ray, longer build. */
+};
+
+/* As mrs_build_bvh, with the hierarchy chosen by `builder` (an MRS_BVH_*
+ * value).  Both give the same leaf size bound, node layout and hit results
+ * (closest hit with ties to the lower face id); only the tree differs.
+ * Errors: as mrs_build_bvh, plus MRS_EINVAL for an unknown builder. */
+mrs_status mrs_build_bvh_with(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
+                              int32_t builder, void *stream, mrs_bvh **out);
 void       mrs_bvh_destroy(mrs_bvh *bvh);
 
 /* BVH statistics (host): number of triangles, nodes, tree depth. */

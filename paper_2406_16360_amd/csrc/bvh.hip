@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "device.h"
 #include "runtime.h"
 
@@ -226,8 +228,10 @@ __global__ void k_layout(int n, const int32_t *__restrict__ child, const int2 *_
     nodes[i] = nd;
 }
 
+// triangle of sorted position k to leaf slot slot[k] (k itself when slot is null)
 __global__ void k_tris(const float *__restrict__ pos, const int32_t *__restrict__ faces,
-                       const uint32_t *__restrict__ ids, int n, TriRec *__restrict__ tris) {
+                       const uint32_t *__restrict__ ids, const int32_t *__restrict__ slot, int n,
+                       TriRec *__restrict__ tris) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t f = ids[k];
@@ -238,16 +242,162 @@ __global__ void k_tris(const float *__restrict__ pos, const int32_t *__restrict_
     t.a = make_float4(a.x, a.y, a.z, __int_as_float((int)f));
     t.b = make_float4(b.x, b.y, b.z, 0.f);
     t.c = make_float4(c.x, c.y, c.z, 0.f);
-    tris[k] = t;
+    tris[slot ? slot[k] : k] = t;
 }
 
-// depth of every leaf (walk to the root); the maximum bounds the stack
-__global__ void k_depth(const int32_t *__restrict__ parent, int n, int32_t *__restrict__ out) {
+// depth of every leaf (walk to the root); the maximum bounds the stack.
+// Leaf k is node leaf_base + k.
+__global__ void k_depth(const int32_t *__restrict__ parent, int n, int leaf_base, int32_t *__restrict__ out) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    int d = 0, node = parent[n - 1 + k];
+    int d = 0, node = parent[leaf_base + k];
     while (node >= 0 && d < 1 << 20) { ++d; node = parent[node]; }
     atomicMax(out, d);
+}
+
+// ---------------------------------------------------------------------------
+// PLOC: parallel locally-ordered clustering (Meister and Bittner, TVCG 2018)
+// over the same Morton order.  Node ids: leaves 0..n-1 (sorted positions),
+// merged nodes n.. in creation order.  Each round finds every cluster's
+// nearest neighbour within kPlocRadius positions (smallest surface area of
+// the union box, ties to the lower position), merges mutual pairs into new
+// nodes placed where the left one was, and compacts.  Merge ids and the
+// compaction come from prefix sums, so the tree is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kPlocRadius = 16;
+constexpr int kPlocBlock = 256;
+
+__device__ __forceinline__ float half_area(float4 l, float4 h) {
+    float dx = h.x - l.x, dy = h.y - l.y, dz = h.z - l.z;
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_ploc_init(const float4 *__restrict__ tlo, const float4 *__restrict__ thi,
+                            const uint32_t *__restrict__ ids, int n, float4 *__restrict__ nlo,
+                            float4 *__restrict__ nhi, int32_t *__restrict__ clus, int32_t *__restrict__ cnt) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    nlo[k] = tlo[ids[k]];
+    nhi[k] = thi[ids[k]];
+    clus[k] = k;
+    cnt[k] = 1;
+}
+
+__global__ __launch_bounds__(kPlocBlock) void k_ploc_nn(const int32_t *__restrict__ clus, int count,
+                                                        const float4 *__restrict__ nlo, const float4 *__restrict__ nhi,
+                                                        int32_t *__restrict__ nn) {
+    __shared__ float4 slo[kPlocBlock + 2 * kPlocRadius], shi[kPlocBlock + 2 * kPlocRadius];
+    const int base = blockIdx.x * kPlocBlock - kPlocRadius;
+    for (int t = threadIdx.x; t < kPlocBlock + 2 * kPlocRadius; t += kPlocBlock) {
+        int p = base + t;
+        if (p >= 0 && p < count) {
+            int c = clus[p];
+            slo[t] = nlo[c];
+            shi[t] = nhi[c];
+        }
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kPlocBlock + threadIdx.x;
+    if (i >= count) return;
+    const int s = threadIdx.x + kPlocRadius;
+    const float4 l = slo[s], h = shi[s];
+    float best = INFINITY;
+    int bj = -1;
+    for (int d = -kPlocRadius; d <= kPlocRadius; ++d) {
+        int j = i + d;
+        if (d == 0 || j < 0 || j >= count) continue;
+        float4 l2 = slo[s + d], h2 = shi[s + d];
+        float a = half_area(make_float4(fminf(l.x, l2.x), fminf(l.y, l2.y), fminf(l.z, l2.z), 0.f),
+                            make_float4(fmaxf(h.x, h2.x), fmaxf(h.y, h2.y), fmaxf(h.z, h2.z), 0.f));
+        if (a < best) { best = a; bj = j; }
+    }
+    nn[i] = bj;
+}
+
+// merge[i]: i starts a mutual pair (i < nn[i]); keep[i]: i survives the round
+__global__ void k_ploc_flags(const int32_t *__restrict__ nn, int count, int32_t *__restrict__ merge,
+                             int32_t *__restrict__ keep) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int j = nn[i];
+    bool mutual = j >= 0 && nn[j] == i;
+    merge[i] = mutual && i < j;
+    keep[i] = !(mutual && i > j);
+}
+
+// totals of the two exclusive scans: out = (merges, survivors)
+__global__ void k_ploc_totals(const int32_t *__restrict__ merge, const int32_t *__restrict__ mo,
+                              const int32_t *__restrict__ keep, const int32_t *__restrict__ ko, int count,
+                              int32_t *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out[0] = mo[count - 1] + merge[count - 1];
+        out[1] = ko[count - 1] + keep[count - 1];
+    }
+}
+
+__global__ void k_ploc_merge(const int32_t *__restrict__ clus, const int32_t *__restrict__ nn, int count,
+                             const int32_t *__restrict__ merge, const int32_t *__restrict__ mo,
+                             const int32_t *__restrict__ keep, const int32_t *__restrict__ ko, int next_id,
+                             float4 *__restrict__ nlo, float4 *__restrict__ nhi, int2 *__restrict__ child,
+                             int32_t *__restrict__ parent, int32_t *__restrict__ cnt, int32_t *__restrict__ clus_next) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    if (merge[i]) {
+        int id = next_id + mo[i];
+        int a = clus[i], b = clus[nn[i]];
+        float4 la = nlo[a], lb = nlo[b], ha = nhi[a], hb = nhi[b];
+        nlo[id] = make_float4(fminf(la.x, lb.x), fminf(la.y, lb.y), fminf(la.z, lb.z), 0.f);
+        nhi[id] = make_float4(fmaxf(ha.x, hb.x), fmaxf(ha.y, hb.y), fmaxf(ha.z, hb.z), 0.f);
+        child[id] = make_int2(a, b);
+        parent[a] = id;
+        parent[b] = id;
+        cnt[id] = cnt[a] + cnt[b];
+        clus_next[ko[i]] = id;
+    } else if (keep[i]) {
+        clus_next[ko[i]] = clus[i];
+    }
+}
+
+// slot of leaf k in depth-first order (left subtree first)
+__global__ void k_ploc_slots(const int32_t *__restrict__ parent, const int2 *__restrict__ child,
+                             const int32_t *__restrict__ cnt, int n, int32_t *__restrict__ slot) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int p = 0, node = k;
+    for (int par = parent[node]; par >= 0; node = par, par = parent[node]) {
+        int2 c = child[par];
+        if (c.y == node) p += cnt[c.x];
+    }
+    slot[k] = p;
+}
+
+// Binary node layout for merged node id (slot (2n - 2) - id, the root first):
+// a child with at most kLeafMax triangles becomes a leaf over its contiguous
+// depth-first triangle range.
+__global__ void k_ploc_layout(int n, const int2 *__restrict__ child, const int32_t *__restrict__ cnt,
+                              const int32_t *__restrict__ slot, const float4 *__restrict__ nlo,
+                              const float4 *__restrict__ nhi, BvhNode *__restrict__ nodes) {
+    int id = n + blockIdx.x * blockDim.x + threadIdx.x;
+    if (id > 2 * n - 2) return;
+    int2 ch = child[id];
+    int c2[2] = {ch.x, ch.y}, ref[2];
+    for (int q = 0; q < 2; ++q) {
+        int c = c2[q];
+        if (cnt[c] <= kLeafMax) {
+            int f = c;
+            while (f >= n) f = child[f].x;   // leftmost leaf
+            ref[q] = ~((slot[f] << 3) | (cnt[c] - 1));
+        } else {
+            ref[q] = (2 * n - 2) - c;
+        }
+    }
+    float4 la = nlo[ch.x], ha = nhi[ch.x], lb = nlo[ch.y], hb = nhi[ch.y];
+    BvhNode nd;
+    nd.n0 = make_float4(pad_lo(la.x), pad_hi(ha.x), pad_lo(la.y), pad_hi(ha.y));
+    nd.n1 = make_float4(pad_lo(lb.x), pad_hi(hb.x), pad_lo(lb.y), pad_hi(hb.y));
+    nd.n2 = make_float4(pad_lo(la.z), pad_hi(ha.z), pad_lo(lb.z), pad_hi(hb.z));
+    nd.n3 = make_int4(ref[0], ref[1], 0, 0);
+    nodes[(2 * n - 2) - id] = nd;
 }
 
 __global__ void k_check_faces(const int32_t *__restrict__ faces, int nf, int nv, int32_t *__restrict__ bad) {
@@ -267,9 +417,10 @@ inline int blocks(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 
 using namespace mrs;
 
-extern "C" mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
-                                    void *stream, mrs_bvh **out) {
-    clear_error();
+namespace {
+
+mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf, int32_t builder, void *stream,
+                 mrs_bvh **out) {
     if (!out) return fail(MRS_EINVAL, "mrs_build_bvh: out is NULL");
     *out = nullptr;
     if (!d_pos || !d_faces) return fail(MRS_EINVAL, "mrs_build_bvh: null mesh pointer");
@@ -280,6 +431,8 @@ extern "C" mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_
     int npow2 = 1024;
     while (npow2 < n) npow2 *= 2;
     DevBuf tlo, thi, keys, ids, child, parent, range, flags, blo, bhi, part, depth, bad;
+    DevBuf pchild, cnt, clus, clus2, nn, mflag, kflag, mo, ko, tot, slot, scan_tmp;   // PLOC
+    const bool ploc = builder == MRS_BVH_PLOC && nf > 1;
     mrs_bvh *b = new mrs_bvh();
     b->nf = nf;
     b->nv = nv;
@@ -337,17 +490,66 @@ extern "C" mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_
         k_bitonic_local<<<npow2 / 1024, 256, 0, s>>>((uint64_t *)keys.p, (uint32_t *)ids.p, npow2, k, j);
     }
     TRY(hip_check(hipMemsetAsync(parent.p, 0xFF, sizeof(int32_t) * (2 * n - 1), s), "memset"));
-    TRY(hip_check(hipMemsetAsync(flags.p, 0, sizeof(int32_t) * std::max(n - 1, 1), s), "memset"));
     TRY(hip_check(hipMemsetAsync(depth.p, 0, sizeof(int32_t), s), "memset"));
-    if (n > 1)
-        k_karras<<<blocks(n - 1), 256, 0, s>>>((uint64_t *)keys.p, n, (int32_t *)child.p, (int32_t *)parent.p,
-                                               (int2 *)range.p);
-    k_boxes<<<blocks(n), 256, 0, s>>>((float4 *)tlo.p, (float4 *)thi.p, (uint32_t *)ids.p, n, (int32_t *)child.p,
-                                      (int32_t *)parent.p, (int32_t *)flags.p, (float4 *)blo.p, (float4 *)bhi.p);
-    k_layout<<<blocks(std::max(n - 1, 1)), 256, 0, s>>>(n, (int32_t *)child.p, (int2 *)range.p, (float4 *)blo.p,
-                                                        (float4 *)bhi.p, (BvhNode *)b->nodes.p);
-    k_tris<<<blocks(n), 256, 0, s>>>(d_pos, d_faces, (uint32_t *)ids.p, n, (TriRec *)b->tris.p);
-    k_depth<<<blocks(n), 256, 0, s>>>((int32_t *)parent.p, n, (int32_t *)depth.p);
+    if (!ploc) {
+        TRY(hip_check(hipMemsetAsync(flags.p, 0, sizeof(int32_t) * std::max(n - 1, 1), s), "memset"));
+        if (n > 1)
+            k_karras<<<blocks(n - 1), 256, 0, s>>>((uint64_t *)keys.p, n, (int32_t *)child.p, (int32_t *)parent.p,
+                                                   (int2 *)range.p);
+        k_boxes<<<blocks(n), 256, 0, s>>>((float4 *)tlo.p, (float4 *)thi.p, (uint32_t *)ids.p, n, (int32_t *)child.p,
+                                          (int32_t *)parent.p, (int32_t *)flags.p, (float4 *)blo.p, (float4 *)bhi.p);
+        k_layout<<<blocks(std::max(n - 1, 1)), 256, 0, s>>>(n, (int32_t *)child.p, (int2 *)range.p, (float4 *)blo.p,
+                                                            (float4 *)bhi.p, (BvhNode *)b->nodes.p);
+        k_tris<<<blocks(n), 256, 0, s>>>(d_pos, d_faces, (uint32_t *)ids.p, nullptr, n, (TriRec *)b->tris.p);
+        k_depth<<<blocks(n), 256, 0, s>>>((int32_t *)parent.p, n, n - 1, (int32_t *)depth.p);
+    } else {
+        // rounds of nearest-neighbour merging until one cluster is left
+        const size_t nn2 = 2 * (size_t)n - 1;
+        TRY(pchild.alloc(sizeof(int2) * nn2));
+        TRY(cnt.alloc(sizeof(int32_t) * nn2));
+        for (DevBuf *d : {&clus, &clus2, &nn, &mflag, &kflag, &mo, &ko, &slot}) TRY(d->alloc(sizeof(int32_t) * n));
+        TRY(tot.alloc(sizeof(int32_t) * 2));
+        size_t tmp_bytes = 0;
+        TRY(hip_check(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, (int32_t *)mflag.p, (int32_t *)mo.p, n, s),
+                      "scan size"));
+        TRY(scan_tmp.alloc(std::max<size_t>(tmp_bytes, 16)));
+        float4 *nlo = (float4 *)blo.p, *nhi = (float4 *)bhi.p;
+        k_ploc_init<<<blocks(n), 256, 0, s>>>((float4 *)tlo.p, (float4 *)thi.p, (uint32_t *)ids.p, n, nlo, nhi,
+                                              (int32_t *)clus.p, (int32_t *)cnt.p);
+        int count = n, next_id = n, rounds = 0;
+        while (count > 1) {
+            k_ploc_nn<<<blocks(count, kPlocBlock), kPlocBlock, 0, s>>>((int32_t *)clus.p, count, nlo, nhi, (int32_t *)nn.p);
+            k_ploc_flags<<<blocks(count), 256, 0, s>>>((int32_t *)nn.p, count, (int32_t *)mflag.p, (int32_t *)kflag.p);
+            TRY(hip_check(hipcub::DeviceScan::ExclusiveSum(scan_tmp.p, tmp_bytes, (int32_t *)mflag.p, (int32_t *)mo.p,
+                                                           count, s), "scan"));
+            TRY(hip_check(hipcub::DeviceScan::ExclusiveSum(scan_tmp.p, tmp_bytes, (int32_t *)kflag.p, (int32_t *)ko.p,
+                                                           count, s), "scan"));
+            k_ploc_totals<<<1, 64, 0, s>>>((int32_t *)mflag.p, (int32_t *)mo.p, (int32_t *)kflag.p, (int32_t *)ko.p,
+                                           count, (int32_t *)tot.p);
+            k_ploc_merge<<<blocks(count), 256, 0, s>>>((int32_t *)clus.p, (int32_t *)nn.p, count, (int32_t *)mflag.p,
+                                                       (int32_t *)mo.p, (int32_t *)kflag.p, (int32_t *)ko.p, next_id,
+                                                       nlo, nhi, (int2 *)pchild.p, (int32_t *)parent.p,
+                                                       (int32_t *)cnt.p, (int32_t *)clus2.p);
+            int32_t h_tot[2] = {0, 0};
+            TRY(hip_check(hipGetLastError(), "ploc kernels"));
+            TRY(hip_check(hipMemcpyAsync(h_tot, tot.p, sizeof(h_tot), hipMemcpyDeviceToHost, s), "copy"));
+            TRY(hip_check(hipStreamSynchronize(s), "sync"));
+            // the globally closest pair is always mutual, so every round merges
+            if (h_tot[0] < 1 || h_tot[1] != count - h_tot[0] || ++rounds > n) {
+                st = fail(MRS_EHIP, "mrs_build_bvh: clustering made no progress");
+                goto done;
+            }
+            next_id += h_tot[0];
+            count = h_tot[1];
+            std::swap(clus.p, clus2.p);
+        }
+        k_ploc_slots<<<blocks(n), 256, 0, s>>>((int32_t *)parent.p, (int2 *)pchild.p, (int32_t *)cnt.p, n,
+                                               (int32_t *)slot.p);
+        k_ploc_layout<<<blocks(n - 1), 256, 0, s>>>(n, (int2 *)pchild.p, (int32_t *)cnt.p, (int32_t *)slot.p, nlo, nhi,
+                                                    (BvhNode *)b->nodes.p);
+        k_tris<<<blocks(n), 256, 0, s>>>(d_pos, d_faces, (uint32_t *)ids.p, (int32_t *)slot.p, n, (TriRec *)b->tris.p);
+        k_depth<<<blocks(n), 256, 0, s>>>((int32_t *)parent.p, n, 0, (int32_t *)depth.p);
+    }
     {
         int32_t h_depth = 0;
         TRY(hip_check(hipGetLastError(), "bvh kernels"));
@@ -364,6 +566,24 @@ done:
     if (st != MRS_OK) { delete b; return st; }
     *out = b;
     return MRS_OK;
+}
+
+}  // namespace
+
+extern "C" mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
+                                    void *stream, mrs_bvh **out) {
+    clear_error();
+    return build(d_pos, nv, d_faces, nf, MRS_BVH_LBVH, stream, out);
+}
+
+extern "C" mrs_status mrs_build_bvh_with(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
+                                         int32_t builder, void *stream, mrs_bvh **out) {
+    clear_error();
+    if (builder != MRS_BVH_LBVH && builder != MRS_BVH_PLOC) {
+        if (out) *out = nullptr;
+        return fail(MRS_EINVAL, "mrs_build_bvh_with: unknown builder %d", builder);
+    }
+    return build(d_pos, nv, d_faces, nf, builder, stream, out);
 }
 
 extern "C" void mrs_bvh_destroy(mrs_bvh *b) { delete b; }

@@ -71,13 +71,14 @@ def _pixel_check(w, r, frac=1e-3):
 
 
 # ---------------------------------------------------------------------- a1/a4
-def test_bvh_closest_and_any_hit(mr, orc_mod):
+@pytest.mark.parametrize("builder", [0, 1], ids=["lbvh", "ploc"])
+def test_bvh_closest_and_any_hit(mr, orc_mod, builder):
     rng = np.random.default_rng(0)
     pos, faces, uv = synth.displaced_latlong_sphere(100, 200, 0.2, rng)
     sc = synth.Scene(pos=pos, faces=faces, env=np.ones((4, 8, 3), np.float32), mat_mode=0,
                      vmat=np.full((pos.shape[0], 5), 0.5, np.float32))
     o_ = orc_mod.Oracle(sc)
-    bvh = mr.build_bvh(torch.tensor(pos, device="cuda"), torch.tensor(faces, device="cuda"))
+    bvh = mr.build_bvh(torch.tensor(pos, device="cuda"), torch.tensor(faces, device="cuda"), builder=builder)
     nf, nodes, depth = bvh.info()
     assert nf == faces.shape[0] and depth < 96
     n = 50000
@@ -104,10 +105,11 @@ def test_bvh_closest_and_any_hit(mr, orc_mod):
     assert np.mean((anyh[:, 3].view(np.int32) >= 0) == (p >= 0)) >= 0.9995
 
 
-def test_bvh_ties_edges_degenerate(mr):
+@pytest.mark.parametrize("builder", [0, 1], ids=["lbvh", "ploc"])
+def test_bvh_ties_edges_degenerate(mr, builder):
     pos = np.array([[-1, -1, 0], [1, -1, 0], [0, 1, 0], [0, 0, 0], [1, 1, 0]], np.float32)
     faces = np.array([[0, 1, 2], [0, 1, 2], [3, 3, 4]], np.int32)
-    bvh = mr.build_bvh(torch.tensor(pos, device="cuda"), torch.tensor(faces, device="cuda"))
+    bvh = mr.build_bvh(torch.tensor(pos, device="cuda"), torch.tensor(faces, device="cuda"), builder=builder)
     o = torch.tensor([[0, 0, 1.0], [0, -1, 1.0], [0, 0, -1.0], [0.2, 0.2, 1.0], [0.5, 0.5, 1.0]], device="cuda")
     d = torch.tensor([[0, 0, -1.0]] * 5, device="cuda")
     h = bvh.trace(o, d).cpu().numpy()
@@ -119,10 +121,11 @@ def test_bvh_ties_edges_degenerate(mr):
     assert ids[4] == -1                        # only on the degenerate face 2: no hit
 
 
-def test_bvh_single_triangle(mr):
+@pytest.mark.parametrize("builder", [0, 1], ids=["lbvh", "ploc"])
+def test_bvh_single_triangle(mr, builder):
     pos = torch.tensor([[0, 0, 0], [1, 0, 0], [0, 1, 0]], dtype=torch.float32, device="cuda")
     faces = torch.tensor([[0, 1, 2]], dtype=torch.int32, device="cuda")
-    bvh = mr.build_bvh(pos, faces)
+    bvh = mr.build_bvh(pos, faces, builder=builder)
     h = bvh.trace(torch.tensor([[0.2, 0.2, 1.0], [2, 2, 1.0]], device="cuda"),
                   torch.tensor([[0, 0, -1.0], [0, 0, -1.0]], device="cuda")).cpu().numpy()
     assert h[0, 3].view(np.int32) == 0 and abs(h[0, 0] - 1.0) < 1e-6
