@@ -11,8 +11,8 @@ dL/denv-texel.  value = path samples per second of that fwd+bwd step.
 Also reported (one JSON line):
   roofline      the dominant kernel's algorithmic bytes per second (counts
                 from the FP64 oracle's own SAH BVH on a seeded subset of the
-                same samples, bytes per unit as stated in the design doc) over its
-                HIP-event-timed duration, against the 8 TB/s HBM3E peak;
+                same samples, bytes per unit as in kernel_bytes below) over
+                its HIP-event-timed duration, against the 8 TB/s HBM3E peak;
   cpu_baseline  the FP64 oracle, as it stands, on a bounded seeded subset of
                 the same samples, on this host's cores.
 """
@@ -93,7 +93,7 @@ def cpu_baseline(w, seconds, nthreads):
     from oracle.oracle import Oracle
     from paper_2406_16360_amd import synth
     orc = Oracle(w.scene)
-    probe = synth.sample_items(w, 4000, 12345)
+    probe = synth.sample_items(w, 40000, 12345)   # large enough to amortise thread start-up
     t0 = time.perf_counter()
     orc.render(w.views, w.opts, probe, nthreads=nthreads)
     orc.grad(w.views, w.opts, probe, np.ones((len(probe), 3)), nthreads=nthreads)
@@ -190,12 +190,53 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_bvh(args):
+    """Per-iteration acceleration-structure update: full builds (LBVH, PLOC)
+    and a refit after the vertices move, over the 300k- and 1M-triangle meshes
+    of configs 3 and 5 (median of `steps` timed runs after `warmup`)."""
+    import torch
+    from paper_2406_16360_amd import mirres, synth
+    torch.cuda.set_device(0)
+    out = {}
+    for name, w in (("c3_300k_tris", synth.config3()), ("c5_1m_tris", synth.config5())):
+        pos = torch.tensor(w.scene.pos, device="cuda")
+        faces = torch.tensor(w.scene.faces, device="cuda")
+        moved = pos + 0.01 * torch.randn(pos.shape, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+
+        def timed(fn):
+            for _ in range(args.warmup):
+                fn()
+            ts = []
+            for _ in range(args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return float(np.median(ts))
+
+        rec = {"triangles": int(faces.shape[0])}
+        for bname, b in (("lbvh", mirres.BVH_LBVH), ("ploc", mirres.BVH_PLOC)):
+            rec[f"build_{bname}_ms"] = timed(lambda: mirres.build_bvh(pos, faces, builder=b))
+            bvh = mirres.build_bvh(pos, faces, builder=b)
+            rec[f"refit_{bname}_ms"] = timed(lambda: bvh.refit(moved))
+            rec[f"depth_{bname}"] = bvh.info()[2]
+        out[name] = rec
+        print(f"# {name}: {rec}", file=sys.stderr, flush=True)
+    c5 = out["c5_1m_tris"]
+    line = {"metric": "BVH refit ms (1M triangles), per optimisation iteration", "value": c5["refit_ploc_ms"],
+            "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": c5["refit_ploc_ms"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "bvh_build_refit", **{k: v for k, v in out.items()}}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "bvh"])
     ap.add_argument("--mode", default="fwdbwd", choices=["fwdbwd", "fwd"])
     ap.add_argument("--tape", default="on", choices=["auto", "on", "off"])
     ap.add_argument("--pool", type=int, default=0)
@@ -205,11 +246,14 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would render its own "
-              "share of the views; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path here (each GPU would render its own "
+              "share of the views). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "c4":
         bench_batched(args)
+        return
+    if args.workload == "bvh":
+        bench_bvh(args)
         return
 
     import torch

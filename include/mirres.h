@@ -157,6 +157,16 @@ mrs_status mrs_build_bvh_with(const float *d_pos, int32_t nv, const int32_t *d_f
                               int32_t builder, void *stream, mrs_bvh **out);
 void       mrs_bvh_destroy(mrs_bvh *bvh);
 
+/* Refits the BVH to new positions of the same vertices (faces unchanged):
+ * the triangle records and every node box are recomputed bottom-up over the
+ * unchanged tree.  This is the per-iteration update of the acceleration
+ * structure while vertices move (the paper rebuilds its LBVH every
+ * iteration, Appendix A "Visibility estimation").  Hit results stay exact for
+ * any motion; only the tree quality degrades with large motion, when a
+ * rebuild pays again.  d_pos [nv][3] is a device array.  Enqueued on `stream`
+ * without waiting.  Errors: MRS_EINVAL (null, nv differs from the build). */
+mrs_status mrs_bvh_refit(mrs_bvh *bvh, const float *d_pos, int32_t nv, void *stream);
+
 /* BVH statistics (host): number of triangles, nodes, tree depth. */
 mrs_status mrs_bvh_info(const mrs_bvh *bvh, int32_t *nf, int32_t *nodes, int32_t *depth);
 

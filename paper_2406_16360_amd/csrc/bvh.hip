@@ -1,12 +1,16 @@
-// Linear BVH builder for gfx950 (the paper builds an LBVH with its own
-// kernels, Appendix A "Visibility estimation"; construction after Karras,
-// "Maximizing parallelism in the construction of BVHs, octrees and k-d
-// trees", HPG 2012):
+// BVH builders for gfx950 (the paper builds an LBVH with its own kernels,
+// Appendix A "Visibility estimation"):
 //   triangle boxes -> centroid bounds -> 63-bit Morton codes -> sort of
-//   (code, index) pairs -> binary radix tree from longest common prefixes ->
-//   bottom-up boxes with per-node arrival counters -> node layout with both
-//   child boxes per node, small subtrees collapsed into leaves of <= 4
-//   triangles, triangles copied in leaf order.
+//   (code, index) pairs, then either
+//   - LBVH (Karras, "Maximizing parallelism in the construction of BVHs,
+//     octrees and k-d trees", HPG 2012): binary radix tree from longest
+//     common prefixes, bottom-up boxes with per-node arrival counters; or
+//   - PLOC (Meister and Bittner, TVCG 2018): rounds of nearest-neighbour
+//     merging over the same order;
+//   -> node layout with both child boxes per node, small subtrees collapsed
+//   into leaves of <= 4 triangles, triangles copied in leaf order.
+// Refit moves the triangles to new vertex positions and recomputes the boxes
+// over the unchanged tree (the per-iteration update while vertices move).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -400,6 +404,93 @@ __global__ void k_ploc_layout(int n, const int2 *__restrict__ child, const int32
     nodes[(2 * n - 2) - id] = nd;
 }
 
+// ---------------------------------------------------------------------------
+// refit: new vertex positions over the unchanged tree
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *__restrict__ p, int n, int32_t v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// parent of every internal node slot, (slot << 1) | side; the root keeps -1
+__global__ void k_node_parents(const BvhNode *__restrict__ nodes, int nnodes, int32_t *__restrict__ npar) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnodes) return;
+    int4 r = nodes[i].n3;
+    if (r.x >= 0) npar[r.x] = (i << 1) | 0;
+    if (r.y >= 0) npar[r.y] = (i << 1) | 1;
+}
+
+// triangle records of the moved vertices (the face id travels in a.w)
+__global__ void k_refit_tris(const float *__restrict__ pos, const int32_t *__restrict__ faces, int n,
+                             TriRec *__restrict__ tris) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    int f = __float_as_int(tris[q].a.w);
+    V3 a = ld3(pos + 3 * (size_t)faces[3 * (size_t)f]);
+    V3 b = ld3(pos + 3 * (size_t)faces[3 * (size_t)f + 1]);
+    V3 c = ld3(pos + 3 * (size_t)faces[3 * (size_t)f + 2]);
+    TriRec t;
+    t.a = make_float4(a.x, a.y, a.z, __int_as_float(f));
+    t.b = make_float4(b.x, b.y, b.z, 0.f);
+    t.c = make_float4(c.x, c.y, c.z, 0.f);
+    tris[q] = t;
+}
+
+__device__ __forceinline__ void leaf_box(const TriRec *__restrict__ tris, int ref, float4 &lo, float4 &hi) {
+    const int code = ~ref, first = code >> 3, cnt = (code & 7) + 1;
+    lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+    hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+    for (int q = first; q < first + cnt; ++q) {
+        TriRec t = tris[q];
+        lo.x = fminf(lo.x, fminf(t.a.x, fminf(t.b.x, t.c.x)));
+        lo.y = fminf(lo.y, fminf(t.a.y, fminf(t.b.y, t.c.y)));
+        lo.z = fminf(lo.z, fminf(t.a.z, fminf(t.b.z, t.c.z)));
+        hi.x = fmaxf(hi.x, fmaxf(t.a.x, fmaxf(t.b.x, t.c.x)));
+        hi.y = fmaxf(hi.y, fmaxf(t.a.y, fmaxf(t.b.y, t.c.y)));
+        hi.z = fmaxf(hi.z, fmaxf(t.a.z, fmaxf(t.b.z, t.c.z)));
+    }
+}
+
+// Bottom-up boxes over the node slots: a thread starts at every node whose
+// children are both leaves and climbs; a node is finished by the thread that
+// brings its last internal child (arrival counters, as in the build).  Child
+// boxes are stored padded, as the build stores them; the unpadded node boxes
+// feed the level above.
+__global__ void k_refit_nodes(int nnodes, BvhNode *__restrict__ nodes, const int32_t *__restrict__ npar,
+                              const TriRec *__restrict__ tris, float4 *__restrict__ nlo, float4 *__restrict__ nhi,
+                              int32_t *__restrict__ arrive) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnodes) return;
+    int4 r0 = nodes[i].n3;
+    if (r0.x >= 0 || r0.y >= 0) return;
+    int node = i;
+    while (true) {
+        int4 r = nodes[node].n3;
+        int refs[2] = {r.x, r.y};
+        float4 lo[2], hi[2];
+        for (int q = 0; q < 2; ++q) {
+            if (refs[q] < 0) leaf_box(tris, refs[q], lo[q], hi[q]);
+            else { lo[q] = nlo[refs[q]]; hi[q] = nhi[refs[q]]; }
+        }
+        BvhNode &nd = nodes[node];
+        nd.n0 = make_float4(pad_lo(lo[0].x), pad_hi(hi[0].x), pad_lo(lo[0].y), pad_hi(hi[0].y));
+        nd.n1 = make_float4(pad_lo(lo[1].x), pad_hi(hi[1].x), pad_lo(lo[1].y), pad_hi(hi[1].y));
+        nd.n2 = make_float4(pad_lo(lo[0].z), pad_hi(hi[0].z), pad_lo(lo[1].z), pad_hi(hi[1].z));
+        nlo[node] = make_float4(fminf(lo[0].x, lo[1].x), fminf(lo[0].y, lo[1].y), fminf(lo[0].z, lo[1].z), 0.f);
+        nhi[node] = make_float4(fmaxf(hi[0].x, hi[1].x), fmaxf(hi[0].y, hi[1].y), fmaxf(hi[0].z, hi[1].z), 0.f);
+        __threadfence();
+        int p = npar[node];
+        if (p < 0) break;
+        int parent = p >> 1;
+        int4 pr = nodes[parent].n3;
+        int need = (pr.x >= 0) + (pr.y >= 0);
+        if (atomicAdd(&arrive[parent], 1) + 1 < need) break;
+        __threadfence();
+        node = parent;
+    }
+}
+
 __global__ void k_check_faces(const int32_t *__restrict__ faces, int nf, int nv, int32_t *__restrict__ bad) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
@@ -561,6 +652,15 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
             goto done;
         }
     }
+    // state for mrs_bvh_refit
+    TRY(b->npar.alloc(sizeof(int32_t) * b->nnodes));
+    TRY(b->nlo.alloc(sizeof(float4) * b->nnodes));
+    TRY(b->nhi.alloc(sizeof(float4) * b->nnodes));
+    TRY(b->arrive.alloc(sizeof(int32_t) * b->nnodes));
+    TRY(hip_check(hipMemsetAsync(b->npar.p, 0xFF, sizeof(int32_t) * b->nnodes, s), "memset"));
+    k_node_parents<<<blocks(b->nnodes), 256, 0, s>>>((BvhNode *)b->nodes.p, b->nnodes, (int32_t *)b->npar.p);
+    TRY(hip_check(hipGetLastError(), "bvh parents"));
+    TRY(hip_check(hipStreamSynchronize(s), "sync"));
 #undef TRY
 done:
     if (st != MRS_OK) { delete b; return st; }
@@ -587,6 +687,19 @@ extern "C" mrs_status mrs_build_bvh_with(const float *d_pos, int32_t nv, const i
 }
 
 extern "C" void mrs_bvh_destroy(mrs_bvh *b) { delete b; }
+
+extern "C" mrs_status mrs_bvh_refit(mrs_bvh *b, const float *d_pos, int32_t nv, void *stream) {
+    clear_error();
+    if (!b || !d_pos) return fail(MRS_EINVAL, "mrs_bvh_refit: null argument");
+    if (nv != b->nv) return fail(MRS_EINVAL, "mrs_bvh_refit: %d vertices, the BVH was built for %d", nv, b->nv);
+    hipStream_t s = (hipStream_t)stream;
+    k_refit_tris<<<blocks(b->nf), 256, 0, s>>>(d_pos, (const int32_t *)b->faces.p, b->nf, (TriRec *)b->tris.p);
+    k_fill_i32<<<blocks(b->nnodes), 256, 0, s>>>((int32_t *)b->arrive.p, b->nnodes, 0);
+    k_refit_nodes<<<blocks(b->nnodes), 256, 0, s>>>(b->nnodes, (BvhNode *)b->nodes.p, (const int32_t *)b->npar.p,
+                                                    (const TriRec *)b->tris.p, (float4 *)b->nlo.p, (float4 *)b->nhi.p,
+                                                    (int32_t *)b->arrive.p);
+    return hip_check(hipGetLastError(), "mrs_bvh_refit launch");
+}
 
 extern "C" mrs_status mrs_bvh_info(const mrs_bvh *b, int32_t *nf, int32_t *nodes, int32_t *depth) {
     clear_error();

@@ -54,6 +54,9 @@ struct mrs_bvh {
     mrs::DevBuf nodes;   // BvhNode[nnodes]
     mrs::DevBuf tris;    // TriRec[nf], leaf order
     mrs::DevBuf faces;   // int32 [nf][3], validated copy used for shading
+    // refit state: parent of every node slot ((slot << 1) | side, -1 at the
+    // root), unpadded node boxes and arrival counters for the bottom-up pass
+    mrs::DevBuf npar, nlo, nhi, arrive;
 };
 
 struct mrs_tape {

@@ -64,7 +64,7 @@ BVH_LBVH, BVH_PLOC = 0, 1
 DEFAULT_BUILDER = int(os.environ.get("MIRRES_BVH_BUILDER", BVH_PLOC))
 
 # the C-ABI symbols declared in include/mirres.h
-EXPORTS = ["mrs_build_bvh", "mrs_build_bvh_with", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
+EXPORTS = ["mrs_build_bvh", "mrs_build_bvh_with", "mrs_bvh_refit", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
            "mrs_plan_create", "mrs_plan_forward", "mrs_plan_backward", "mrs_plan_info", "mrs_plan_destroy",
            "mrs_tape_bytes", "mrs_tape_destroy", "mrs_profile_begin", "mrs_profile_end", "mrs_release_workspace",
            "mrs_last_error"]
@@ -84,6 +84,8 @@ def _load():
     lib.mrs_build_bvh.argtypes = [p, i32, p, i32, p, C.POINTER(p)]
     lib.mrs_build_bvh_with.restype = i32
     lib.mrs_build_bvh_with.argtypes = [p, i32, p, i32, i32, p, C.POINTER(p)]
+    lib.mrs_bvh_refit.restype = i32
+    lib.mrs_bvh_refit.argtypes = [p, p, i32, p]
     lib.mrs_bvh_destroy.argtypes = [p]
     lib.mrs_bvh_info.restype = i32
     lib.mrs_bvh_info.argtypes = [p, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
@@ -191,6 +193,12 @@ class Bvh:
     @property
     def handle(self):
         return self._h
+
+    def refit(self, pos: torch.Tensor, stream=None) -> None:
+        """Moves the triangles to new positions of the same vertices and
+        recomputes every box over the unchanged tree."""
+        pos = _dev(pos)
+        _check(_lib.mrs_bvh_refit(self._h, pos.data_ptr(), pos.shape[0], _stream(stream)))
 
     def info(self) -> Tuple[int, int, int]:
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

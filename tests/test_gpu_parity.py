@@ -309,3 +309,34 @@ def test_tape_off_and_budget(mr):
     o.tape_budget = 16                               # too small: AUTO falls back to recompute
     _, tape = mr.render(sc, w.views, o, keep_tape=True)
     assert tape is None
+
+
+# ------------------------------------------------------------------ f4 refit
+@pytest.mark.parametrize("builder", [0, 1], ids=["lbvh", "ploc"])
+def test_bvh_refit_moved_vertices(mr, orc_mod, builder):
+    """After the vertices move, a refitted tree gives exactly the hits of a
+    tree built over the moved mesh, and both agree with the oracle."""
+    rng = np.random.default_rng(5)
+    pos, faces, uv = synth.displaced_latlong_sphere(60, 120, 0.2, rng)
+    moved = (pos + rng.normal(scale=0.02, size=pos.shape)).astype(np.float32)
+    moved[:, 0] *= 1.3                       # a large, anisotropic motion as well
+    bvh = mr.build_bvh(torch.tensor(pos, device="cuda"), torch.tensor(faces, device="cuda"), builder=builder)
+    bvh.refit(torch.tensor(moved, device="cuda"))
+    fresh = mr.build_bvh(torch.tensor(moved, device="cuda"), torch.tensor(faces, device="cuda"), builder=builder)
+    n = 40000
+    o = rng.normal(size=(n, 3))
+    o = 3 * o / np.linalg.norm(o, axis=1, keepdims=True)
+    d = rng.normal(scale=0.7, size=(n, 3)) - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    ot, dt = torch.tensor(o, device="cuda"), torch.tensor(d, device="cuda")
+    h_ref = bvh.trace(ot, dt).cpu().numpy()
+    h_new = fresh.trace(ot, dt).cpu().numpy()
+    assert np.array_equal(h_ref[:, 3].view(np.int32), h_new[:, 3].view(np.int32))
+    assert np.array_equal(h_ref[:, :3], h_new[:, :3])
+    a_ref = bvh.trace(ot, dt, any_hit=True).cpu().numpy()
+    assert np.array_equal(a_ref[:, 3].view(np.int32) >= 0, h_new[:, 3].view(np.int32) >= 0)
+    sc = synth.Scene(pos=moved, faces=faces, env=np.ones((4, 8, 3), np.float32), mat_mode=0,
+                     vmat=np.full((moved.shape[0], 5), 0.5, np.float32))
+    p, t, b1, b2 = orc_mod.Oracle(sc).trace(o.astype(np.float64), d.astype(np.float64))
+    assert np.mean(h_ref[:, 3].view(np.int32) == p) >= 0.9995
