@@ -231,12 +231,75 @@ def bench_bvh(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_denoise(args):
+    """The denoiser row at the differentiation workload's image size (8 views
+    of 800x800): G-buffer, three a-trous levels forward and their adjoint.
+    value = pixels per second of one forward + adjoint; roofline against the
+    algorithmic bytes (per pixel and level: forward reads colour, normal and
+    position and writes colour and weight sum, 52 B; the adjoint reads those
+    plus dL/dout and the weight sum and writes dL/dc, 76 B)."""
+    import torch
+    from paper_2406_16360_amd import mirres, synth
+    torch.cuda.set_device(0)
+    w = synth.config3()
+    sc = mirres.GpuScene.from_synth(w.scene)
+    pos, nrm = mirres.gbuffer(sc, w.views)
+    img = mirres.render(sc, w.views, mirres.RenderOptions.from_any(w.opts))
+    den = mirres.Denoiser(w.views, nrm, pos, levels=3)
+    g = torch.randn_like(img)
+    npix = img.shape[0]
+
+    def step():
+        den.forward(img)
+        den.backward(g)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        den.forward(img)
+    ev[1].record()
+    for _ in range(args.steps):
+        den.backward(g)
+    ev[2].record()
+    torch.cuda.synchronize()
+    f_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    b_ms = ev[1].elapsed_time(ev[2]) / args.steps
+    ms = f_ms + b_ms
+    L = 3
+    f_gbps = npix * L * 52 / (f_ms * 1e-3) / 1e9
+    b_gbps = npix * L * 76 / (b_ms * 1e-3) / 1e9
+    dom = ("adjoint", b_gbps, b_ms, 76) if b_ms >= f_ms else ("forward", f_gbps, f_ms, 52)
+    line = {"metric": "denoiser fwd+adjoint pixels/s, 3 a-trous levels, 8 x 800x800", "value": npix / (ms * 1e-3),
+            "unit": "pixels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "denoise_8x800x800_3levels", "pixels": npix, "forward_ms": f_ms, "adjoint_ms": b_ms},
+            "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": dom[1], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": dom[1] / HBM_PEAK_GBPS, "traffic": None,
+                         "alg_bytes_per_launch": npix * dom[3], "avg_launch_ms": dom[2] / (L * len(w.views))},
+            "forward_roofline_frac": f_gbps / HBM_PEAK_GBPS, "adjoint_roofline_frac": b_gbps / HBM_PEAK_GBPS}
+    if not args.no_cpu_baseline:
+        from oracle import denoise as odn
+        v0 = w.views[0]
+        rng = np.random.default_rng(9)   # seeded buffers of one view's shape
+        c, n, x, gg = (rng.random((v0.w * v0.h, 3)) for _ in range(4))
+        t0 = time.perf_counter()
+        odn.denoise(c, n, x, [v0])
+        odn.denoise_grad(c, n, x, gg, [v0])
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": v0.w * v0.h / dt, "unit": "pixels/s", "cores": torch.get_num_threads(),
+                                "kind": "oracle", "sample": f"one 800x800 view, forward + autograd adjoint, {dt:.1f}s"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "bvh"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "bvh", "denoise"])
     ap.add_argument("--mode", default="fwdbwd", choices=["fwdbwd", "fwd"])
     ap.add_argument("--tape", default="on", choices=["auto", "on", "off"])
     ap.add_argument("--pool", type=int, default=0)
@@ -254,6 +317,9 @@ def main():
         return
     if args.workload == "bvh":
         bench_bvh(args)
+        return
+    if args.workload == "denoise":
+        bench_denoise(args)
         return
 
     import torch

@@ -201,6 +201,47 @@ mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, in
                                const mrs_options *opt, const float *d_grad_image,
                                const mrs_grads *grads, const mrs_tape *tape, void *stream);
 
+/* Denoiser G-buffer (Appendix A "Denoiser": its normal and position
+ * buffers): for the ray through every pixel centre, the closest hit's
+ * position o + t d and unit geometric normal turned towards the camera;
+ * zeros where the ray misses.  d_position, d_normal [sum W*H][3] device,
+ * packed like the image.  Errors: as mrs_render. */
+mrs_status mrs_gbuffer(const mrs_scene *scene, const mrs_view *views, int32_t n_views, float *d_position,
+                       float *d_normal, void *stream);
+
+#define MRS_DENOISE_MAX_LEVELS 3
+
+/* Edge-avoiding a-trous wavelet transform (Appendix A "Denoiser", after
+ * Dammertz et al., HPG 2010).  Level i (0-based) filters c_i into c_{i+1}
+ * with 5 x 5 B3-spline taps h = (1, 4, 6, 4, 1)/16 spaced 2^i pixels apart,
+ * weighted by w_rt w_n w_x = exp(-|dc_i|^2/sigma_rt^2 - |dn|^2/sigma_n^2 -
+ * |dx|^2/sigma_x^2) and normalised by the weight sum; taps outside the view
+ * are left out.  The paper runs three levels. */
+typedef struct {
+    int32_t levels;                      /* in [1, MRS_DENOISE_MAX_LEVELS] */
+    float   sigma_rt, sigma_n, sigma_x;  /* > 0 */
+} mrs_denoise_params;
+
+/* Bytes of the caller-owned device workspace mrs_denoise needs (every
+ * level's colour and weight sum, kept for the backward); -1 on bad input. */
+int64_t mrs_denoise_work_bytes(const mrs_view *views, int32_t n_views, const mrs_denoise_params *p);
+
+/* Denoises the packed colour image d_color_in [sum W*H][3] (views by their
+ * w, h and pixel_offset; other mrs_view fields are ignored) with the
+ * G-buffer into d_color_out, and keeps what the backward needs in d_work.
+ * Errors: MRS_EINVAL (null, empty view, bad levels or sigmas), MRS_EHIP. */
+mrs_status mrs_denoise(const mrs_view *views, int32_t n_views, const mrs_denoise_params *p,
+                       const float *d_color_in, const float *d_normal, const float *d_position,
+                       float *d_color_out, float *d_work, void *stream);
+
+/* Adjoint of the last mrs_denoise with this d_work: writes (overwrites)
+ * d_grad_in = dL/d color_in from d_grad_out = dL/d color_out, through the
+ * filters and through the colour weights' dependence on the image.  The
+ * G-buffer is not differentiated.  d_grad_in must not alias d_grad_out. */
+mrs_status mrs_denoise_backward(const mrs_view *views, int32_t n_views, const mrs_denoise_params *p,
+                                const float *d_normal, const float *d_position, const float *d_work,
+                                const float *d_grad_out, float *d_grad_in, void *stream);
+
 /* Plans: a render (and optionally its adjoint) for fixed views, options and
  * bound device arrays, with every buffer the passes need allocated by the
  * plan at creation (pool, output, env tables, tape or recompute chunk tape).

@@ -584,6 +584,29 @@ extern "C" mrs_status mrs_render(const mrs_scene *scene, const mrs_view *views, 
     return MRS_OK;
 }
 
+extern "C" mrs_status mrs_gbuffer(const mrs_scene *scene, const mrs_view *views, int32_t n_views, float *d_position,
+                                  float *d_normal, void *stream) {
+    clear_error();
+    if (!d_position || !d_normal) return fail(MRS_EINVAL, "mrs_gbuffer: output is NULL");
+    // the G-buffer samples nothing: any valid option set passes validation
+    mrs_options opt{};
+    opt.bounces = 1;
+    opt.ris_m = 1;
+    opt.rr_start = -1;
+    opt.brdf = MRS_BRDF_LAMBERT_GGX;
+    opt.background = MRS_BG_ENV;
+    Job job;
+    TRY(validate(scene, views, n_views, &opt, job));
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    hipStream_t s = (hipStream_t)stream;
+    TRY(begin(s));
+    TRY(upload_views_eager(job, s));
+    bind_scene(scene, job);
+    GbufArgs ga{job.sd.nodes, job.sd.tris, job.vt, job.pixels, d_position, d_normal};
+    k_gbuffer<<<nblocks(job.pixels, 256), 256, kLdsStackBytes * 256, s>>>(ga);
+    return finish(s);
+}
+
 extern "C" mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
                                           const mrs_options *opt, const float *d_grad_image, const mrs_grads *grads,
                                           const mrs_tape *tape, void *stream) {

@@ -892,6 +892,35 @@ __global__ void k_trace_batch(const BvhNode *__restrict__ nodes, const TriRec *_
     }
 }
 
+// denoiser G-buffer: closest hit of the ray through each pixel centre
+struct GbufArgs {
+    const BvhNode *nodes; const TriRec *tris;
+    ViewTable vt; uint64_t pixels;
+    float *position, *normal;
+};
+
+__global__ void k_gbuffer(GbufArgs a) {
+    extern __shared__ int lds_stack[];
+    const uint64_t P = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (P >= a.pixels) return;
+    const ViewDev &v = a.vt.v[find_view_pix(a.vt, P)];
+    const uint32_t p = (uint32_t)(P - v.pix_base);
+    V3 o, d;
+    camera_ray(v, p, 0.5f, 0.5f, o, d);
+    Hit h = trace_closest(a.nodes, a.tris, o, d, lds_stack);
+    V3 x = V3{0, 0, 0}, n = V3{0, 0, 0};
+    if (h.leaf >= 0) {
+        const TriRec tr = a.tris[h.leaf];
+        x = o + d * h.t;
+        n = normalize(cross(xyz(tr.b) - xyz(tr.a), xyz(tr.c) - xyz(tr.a)));
+        if (dot(n, d) > 0.0f) n = n * -1.0f;
+    }
+    float *px = a.position + 3 * (uint64_t)(v.pixel_offset + (int64_t)p);
+    float *pn = a.normal + 3 * (uint64_t)(v.pixel_offset + (int64_t)p);
+    px[0] = x.x; px[1] = x.y; px[2] = x.z;
+    pn[0] = n.x; pn[1] = n.y; pn[2] = n.z;
+}
+
 __global__ void k_set_sched(Sched *s, uint64_t a, uint64_t b) {
     if (threadIdx.x == 0 && blockIdx.x == 0) { s->next = a; s->end = b; }
 }

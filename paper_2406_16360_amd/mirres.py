@@ -66,7 +66,8 @@ DEFAULT_BUILDER = int(os.environ.get("MIRRES_BVH_BUILDER", BVH_PLOC))
 # the C-ABI symbols declared in include/mirres.h
 EXPORTS = ["mrs_build_bvh", "mrs_build_bvh_with", "mrs_bvh_refit", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
            "mrs_plan_create", "mrs_plan_forward", "mrs_plan_backward", "mrs_plan_info", "mrs_plan_destroy",
-           "mrs_tape_bytes", "mrs_tape_destroy", "mrs_profile_begin", "mrs_profile_end", "mrs_release_workspace",
+           "mrs_tape_bytes", "mrs_tape_destroy", "mrs_gbuffer", "mrs_denoise_work_bytes", "mrs_denoise",
+           "mrs_denoise_backward", "mrs_profile_begin", "mrs_profile_end", "mrs_release_workspace",
            "mrs_last_error"]
 
 
@@ -86,6 +87,14 @@ def _load():
     lib.mrs_build_bvh_with.argtypes = [p, i32, p, i32, i32, p, C.POINTER(p)]
     lib.mrs_bvh_refit.restype = i32
     lib.mrs_bvh_refit.argtypes = [p, p, i32, p]
+    lib.mrs_gbuffer.restype = i32
+    lib.mrs_gbuffer.argtypes = [p, p, i32, p, p, p]
+    lib.mrs_denoise_work_bytes.restype = i64
+    lib.mrs_denoise_work_bytes.argtypes = [p, i32, p]
+    lib.mrs_denoise.restype = i32
+    lib.mrs_denoise.argtypes = [p, i32, p, p, p, p, p, p, p]
+    lib.mrs_denoise_backward.restype = i32
+    lib.mrs_denoise_backward.argtypes = [p, i32, p, p, p, p, p, p, p]
     lib.mrs_bvh_destroy.argtypes = [p]
     lib.mrs_bvh_info.restype = i32
     lib.mrs_bvh_info.argtypes = [p, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
@@ -482,3 +491,72 @@ def render_autograd(scene: GpuScene, views: Sequence, opts, vmat=None, albedo=No
     metal = scene.metal if metal is None else metal
     env = scene.env if env is None else env
     return _RenderFn.apply(scene, list(views), opts, vmat, albedo, rough, metal, env)
+
+
+# ------------------------------------------------------------------ denoiser
+class _DenoiseParams(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("sigma_rt", C.c_float), ("sigma_n", C.c_float), ("sigma_x", C.c_float)]
+
+
+def gbuffer(scene: GpuScene, views: Sequence, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Position and normal of the closest hit through every pixel centre,
+    packed like render()'s image (zeros where the ray misses)."""
+    vs, npix, _ = views_struct(views)
+    dev = scene.pos.device
+    pos = torch.empty((npix, 3), dtype=torch.float32, device=dev)
+    nrm = torch.empty((npix, 3), dtype=torch.float32, device=dev)
+    sc = scene.struct()
+    _check(_lib.mrs_gbuffer(C.byref(sc), C.addressof(vs), len(views), pos.data_ptr(), nrm.data_ptr(),
+                            _stream(stream)))
+    return pos, nrm
+
+
+class Denoiser:
+    """Edge-avoiding a-trous wavelet denoiser over packed images of `views`
+    with a fixed G-buffer.  forward() keeps the per-level state in a device
+    workspace that backward() reads."""
+
+    def __init__(self, views: Sequence, normal: torch.Tensor, position: torch.Tensor, levels: int = 3,
+                 sigma_rt: float = 1.0, sigma_n: float = 0.5, sigma_x: float = 0.5):
+        self.vs, self.npix, _ = views_struct(views)
+        self.nviews = len(views)
+        self.params = _DenoiseParams(levels, sigma_rt, sigma_n, sigma_x)
+        self.normal = _dev(normal)
+        self.position = _dev(position)
+        nbytes = _lib.mrs_denoise_work_bytes(C.addressof(self.vs), self.nviews, C.byref(self.params))
+        if nbytes < 0:
+            raise MirresError(-1, "invalid denoiser views or parameters")
+        self.work = torch.empty(((nbytes + 3) // 4,), dtype=torch.float32, device=self.normal.device)
+
+    def forward(self, color: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        c = _dev(color)
+        res = out if out is not None else torch.empty_like(c)
+        _check(_lib.mrs_denoise(C.addressof(self.vs), self.nviews, C.byref(self.params), c.data_ptr(),
+                                self.normal.data_ptr(), self.position.data_ptr(), res.data_ptr(),
+                                self.work.data_ptr(), _stream(stream)))
+        return res
+
+    def backward(self, grad_out: torch.Tensor, stream=None) -> torch.Tensor:
+        g = _dev(grad_out)
+        gi = torch.empty_like(g)
+        _check(_lib.mrs_denoise_backward(C.addressof(self.vs), self.nviews, C.byref(self.params),
+                                         self.normal.data_ptr(), self.position.data_ptr(), self.work.data_ptr(),
+                                         g.data_ptr(), gi.data_ptr(), _stream(stream)))
+        return gi
+
+
+class _DenoiseFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, color, den):
+        ctx.den = den
+        return den.forward(color)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.den.backward(g.contiguous()), None
+
+
+def denoise_autograd(color: torch.Tensor, den: "Denoiser") -> torch.Tensor:
+    """Differentiable denoise(color); the backward of each call uses the
+    workspace of that call, so do not run another forward before it."""
+    return _DenoiseFn.apply(color, den)

@@ -73,7 +73,7 @@ def test_struct_layouts_match_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     structs = {"mrs_scene": mirres._Scene, "mrs_view": mirres._View, "mrs_options": mirres._Options,
-               "mrs_grads": mirres._Grads}
+               "mrs_grads": mirres._Grads, "mrs_denoise_params": mirres._DenoiseParams}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
