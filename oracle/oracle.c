@@ -25,6 +25,18 @@
  *                     tracing on a tiny scene.
  *   gradient        - central finite differences of the frozen functional;
  *                     closed form dI/da = L on the plane.
+ *   material field  - level resolutions of the paper's configuration (16 to
+ *                     2048 in 16 geometric steps); dense levels reproduce
+ *                     tables affine in the vertex coordinates; hashed levels
+ *                     are a partition of unity, continuous across cell faces,
+ *                     and read slot v0 mod T along the x axis; MLP closed
+ *                     forms (W2 = 0, W1 = 0); pull-back against central
+ *                     differences; a constant field renders like constant
+ *                     per-vertex materials, with the output-bias gradient
+ *                     equal to sigmoid' times the summed vertex gradient;
+ *                     path gradients against differences of the frozen
+ *                     functional.  The hash primes are the published ones
+ *                     (Mueller et al. 2022) and are pinned only on the x axis.
  * Parity with numbers printed in the paper is unpinned: the paper prints no
  * per-pixel or per-gradient values for this path.
  */
@@ -497,10 +509,14 @@ static int trace_any(const orc_ctx *c, const double o[3], const double d[3], int
     return 0;
 }
 
+static int field_valid(const orc_field *f);
+
 orc_ctx *orc_create(const orc_scene *s, int32_t use_bvh) {
     if (!s || !s->pos || !s->faces || s->nv <= 0 || s->nf <= 0 || !s->env || s->ew <= 0 || s->eh <= 0) return NULL;
     if (s->mat_mode == 0 && !s->vmat) return NULL;
     if (s->mat_mode == 1 && (!s->uv || !s->albedo || !s->rough || !s->metal || s->tw <= 0 || s->th <= 0)) return NULL;
+    if (s->mat_mode == 2 && !field_valid(s->field)) return NULL;
+    if (s->mat_mode < 0 || s->mat_mode > 2) return NULL;
     orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     c->s = *s;
     c->v = (double *)malloc(sizeof(double) * 9 * (size_t)s->nf);
@@ -731,10 +747,148 @@ static void material_interp(const orc_ctx *c, int32_t prim, double b1, double b2
     ip->f1 = x - x0; ip->f2 = y - y0;
 }
 
+/* ------------------------------------------------------------------ */
+/* material neural field F_m (Sec. 3 "Intrinsic decomposition"; Appendix */
+/* A "Network details"); hash encoding after Mueller et al. (SIGGRAPH    */
+/* 2022), Sec. 3.  The definition it follows is spelled out in oracle.h. */
+/* ------------------------------------------------------------------ */
+static int field_valid(const orc_field *f) {
+    if (!f || !f->table || !f->w1 || !f->b1 || !f->w2 || !f->b2) return 0;
+    if (f->levels < 1 || f->levels > ORC_FIELD_MAXL || f->log2_table < 1 || f->log2_table > 26) return 0;
+    if (f->n_min < 1 || f->n_max < f->n_min) return 0;
+    for (int a = 0; a < 3; ++a) if (!(f->hi[a] > f->lo[a])) return 0;
+    return 1;
+}
+
+/* N_l: geometric progression from N_min to N_max (Mueller et al., Eq. 2-3) */
+static int64_t field_res(const orc_field *f, int l) {
+    if (f->levels == 1) return f->n_min;
+    double g = log((double)f->n_max / (double)f->n_min) / (double)(f->levels - 1);
+    return (int64_t)floor((double)f->n_min * exp((double)l * g) + 1e-6);
+}
+
+/* slot of grid vertex v at a level of resolution N: one-to-one while the
+ * level's (N+1)^3 vertices fit in the table, else the spatial hash */
+static int64_t field_slot(int64_t N, int64_t T, const int64_t v[3]) {
+    int64_t side = N + 1;
+    if (side * side * side <= T) return v[0] + side * (v[1] + side * v[2]);
+    uint32_t h = (uint32_t)v[0] * 1u ^ (uint32_t)v[1] * 2654435761u ^ (uint32_t)v[2] * 805459861u;
+    return (int64_t)(h % (uint64_t)T);
+}
+
+/* the 8 cell corners of x at level l: slots and trilinear weights
+ * (corner bit a set = upper vertex along axis a) */
+static void field_corners(const orc_field *f, int l, const double x[3], int64_t slot[8], double w[8]) {
+    int64_t N = field_res(f, l), T = (int64_t)1 << f->log2_table;
+    int64_t c[3]; double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double u = clampd((x[a] - (double)f->lo[a]) / ((double)f->hi[a] - (double)f->lo[a]), 0.0, 1.0);
+        double sa = u * (double)N;
+        int64_t ca = (int64_t)floor(sa);
+        if (ca > N - 1) ca = N - 1;
+        c[a] = ca; t[a] = sa - (double)ca;
+    }
+    for (int k = 0; k < 8; ++k) {
+        int64_t v[3]; double wk = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            int up = (k >> a) & 1;
+            v[a] = c[a] + up;
+            wk *= up ? t[a] : 1.0 - t[a];
+        }
+        slot[k] = field_slot(N, T, v);
+        w[k] = wk;
+    }
+}
+
+/* forward pass at one point: encoding e[2L], pre-activations z1[32], m[4] */
+static void field_forward(const orc_field *f, const double x[3], double *e, double *z1, double m[4]) {
+    const int L = f->levels, I = 2 * L;
+    const int64_t T = (int64_t)1 << f->log2_table;
+    for (int l = 0; l < L; ++l) {
+        int64_t slot[8]; double w[8];
+        field_corners(f, l, x, slot, w);
+        for (int j = 0; j < 2; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 8; ++k) acc += w[k] * (double)f->table[((size_t)l * T + slot[k]) * 2 + j];
+            e[2 * l + j] = acc;
+        }
+    }
+    double a[ORC_FIELD_HIDDEN];
+    for (int h = 0; h < ORC_FIELD_HIDDEN; ++h) {
+        double acc = (double)f->b1[h];
+        for (int i = 0; i < I; ++i) acc += (double)f->w1[(size_t)h * I + i] * e[i];
+        z1[h] = acc;
+        a[h] = acc > 0.0 ? acc : 0.0;
+    }
+    for (int o = 0; o < ORC_FIELD_OUT; ++o) {
+        double acc = (double)f->b2[o];
+        for (int h = 0; h < ORC_FIELD_HIDDEN; ++h) acc += (double)f->w2[(size_t)o * ORC_FIELD_HIDDEN + h] * a[h];
+        m[o] = 1.0 / (1.0 + exp(-acc));
+    }
+}
+
+/* pull-back of g = dL/dm at one point onto the parameters (chain rule
+ * through the sigmoid, the two layers, the ReLU and the interpolation) */
+static void field_backward(const orc_field *f, const double x[3], const double g[4], double *g_table,
+                           double *g_w1, double *g_b1, double *g_w2, double *g_b2) {
+    const int L = f->levels, I = 2 * L, H = ORC_FIELD_HIDDEN;
+    const int64_t T = (int64_t)1 << f->log2_table;
+    double e[2 * ORC_FIELD_MAXL], z1[ORC_FIELD_HIDDEN], m[ORC_FIELD_OUT];
+    field_forward(f, x, e, z1, m);
+    double dz2[ORC_FIELD_OUT], dz1[ORC_FIELD_HIDDEN];
+    for (int o = 0; o < ORC_FIELD_OUT; ++o) dz2[o] = g[o] * m[o] * (1.0 - m[o]);
+    for (int h = 0; h < H; ++h) {
+        double da = 0.0;
+        for (int o = 0; o < ORC_FIELD_OUT; ++o) da += (double)f->w2[(size_t)o * H + h] * dz2[o];
+        dz1[h] = z1[h] > 0.0 ? da : 0.0;
+    }
+    if (g_b2) for (int o = 0; o < ORC_FIELD_OUT; ++o) g_b2[o] += dz2[o];
+    if (g_w2)
+        for (int o = 0; o < ORC_FIELD_OUT; ++o)
+            for (int h = 0; h < H; ++h) g_w2[(size_t)o * H + h] += dz2[o] * (z1[h] > 0.0 ? z1[h] : 0.0);
+    if (g_b1) for (int h = 0; h < H; ++h) g_b1[h] += dz1[h];
+    if (g_w1)
+        for (int h = 0; h < H; ++h)
+            for (int i = 0; i < I; ++i) g_w1[(size_t)h * I + i] += dz1[h] * e[i];
+    if (g_table) {
+        for (int l = 0; l < L; ++l) {
+            int64_t slot[8]; double w[8];
+            field_corners(f, l, x, slot, w);
+            for (int j = 0; j < 2; ++j) {
+                double de = 0.0;
+                for (int h = 0; h < H; ++h) de += (double)f->w1[(size_t)h * I + 2 * l + j] * dz1[h];
+                for (int k = 0; k < 8; ++k) g_table[((size_t)l * T + slot[k]) * 2 + j] += w[k] * de;
+            }
+        }
+    }
+}
+
+int32_t orc_field_levels(const orc_field *f, int64_t *res) {
+    if (!field_valid(f) || !res) return -1;
+    for (int l = 0; l < f->levels; ++l) res[l] = field_res(f, l);
+    return f->levels;
+}
+
+int32_t orc_field_eval(const orc_field *f, const double *x, int64_t n, double *m) {
+    if (!field_valid(f) || n < 0 || (n > 0 && (!x || !m))) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        double e[2 * ORC_FIELD_MAXL], z1[ORC_FIELD_HIDDEN];
+        field_forward(f, x + 3 * i, e, z1, m + 4 * i);
+    }
+    return 0;
+}
+
+int32_t orc_field_vjp(const orc_field *f, const double *x, const double *g, int64_t n,
+                      double *g_table, double *g_w1, double *g_b1, double *g_w2, double *g_b2) {
+    if (!field_valid(f) || n < 0 || (n > 0 && (!x || !g))) return -1;
+    for (int64_t i = 0; i < n; ++i) field_backward(f, x + 3 * i, g + 4 * i, g_table, g_w1, g_b1, g_w2, g_b2);
+    return 0;
+}
+
 static dual dlerp(dual a, dual b, double f) { return dadd(a, dscale(dsub(b, a), f)); }
 
 /* parameter kinds for derivative seeds */
-enum { PK_NONE = -1, PK_VMAT = 0, PK_ALBEDO, PK_ROUGH, PK_METAL, PK_ENV };
+enum { PK_NONE = -1, PK_VMAT = 0, PK_ALBEDO, PK_ROUGH, PK_METAL, PK_ENV, PK_FIELD };
 typedef struct { int kind; int64_t idx; } seed_t;
 
 static dual param_value(const orc_ctx *c, int kind, int64_t idx, seed_t sd) {
@@ -781,6 +935,21 @@ static dual env_d(const orc_ctx *c, int32_t texel, int ch, seed_t sd) {
     dual x = param_value(c, PK_ENV, (int64_t)texel * 3 + ch, sd);
     if (x.v < 0.0) return dc(0.0);
     return x;
+}
+
+/* field material at point p (mat_mode 2) as duals, clamped like the other
+ * sources; the derivative seed (PK_FIELD, 4 k + ch) marks output ch of the
+ * field at path vertex k */
+static void material_field_d(const orc_ctx *c, const double p[3], int k, seed_t sd, dual m[5]) {
+    double e[2 * ORC_FIELD_MAXL], z1[ORC_FIELD_HIDDEN], fm[ORC_FIELD_OUT];
+    field_forward(c->s.field, p, e, z1, fm);
+    for (int ch = 0; ch < 4; ++ch) {
+        dual x = { fm[ch], (sd.kind == PK_FIELD && sd.idx == 4 * (int64_t)k + ch) ? 1.0 : 0.0 };
+        m[ch] = x;
+    }
+    m[4] = dc(0.0);
+    for (int ch = 0; ch < 3; ++ch) m[ch] = dclamp(m[ch], 0.0, 1.0);
+    m[3] = dclamp(m[3], R_MIN, 1.0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -859,8 +1028,15 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
         for (int a = 0; a < 3; ++a) { V->n[a] = ng[a]; V->wo[a] = -d[a]; }
         double tf[3], bf[3];
         orc_frame(V->n, tf, bf);
-        interp ip; material_interp(c, hr.prim, hr.b1, hr.b2, &ip);
-        double m[5]; material_plain(c, &ip, m);
+        double m[5];
+        if (c->s.mat_mode == 2) {
+            dual md[5]; seed_t none = { PK_NONE, -1 };
+            material_field_d(c, V->p, rec->nv - 1, none, md);
+            for (int ch = 0; ch < 5; ++ch) m[ch] = md[ch].v;
+        } else {
+            interp ip; material_interp(c, hr.prim, hr.b1, hr.b2, &ip);
+            material_plain(c, &ip, m);
+        }
         double pn = fmax(fabs(V->p[0]), fmax(fabs(V->p[1]), fabs(V->p[2])));
         double eps = 1e-4 * fmax(1.0, pn);
         double org[3] = { V->p[0] + eps * V->n[0], V->p[1] + eps * V->n[1], V->p[2] + eps * V->n[2] };
@@ -958,8 +1134,13 @@ static void frozen_eval(const orc_ctx *c, const pathrec *rec, const orc_options 
     for (int k = 0; k < rec->nv; ++k) {
         const vtx *V = &rec->v[k];
         seed_t s_here = (opt->grad_mode == 1 && k > 0) ? none : sd;
-        interp ip; material_interp(c, V->prim, V->b1, V->b2, &ip);
-        dual m[5]; material_d(c, &ip, s_here, m);
+        dual m[5];
+        if (c->s.mat_mode == 2) {
+            material_field_d(c, V->p, k, s_here, m);
+        } else {
+            interp ip; material_interp(c, V->prim, V->b1, V->b2, &ip);
+            material_d(c, &ip, s_here, m);
+        }
         if (V->nee) {
             dual f[3];
             brdf_eval_d(V->n, V->wo, V->y, m, spec, f);
@@ -1029,6 +1210,11 @@ static int path_params(const orc_ctx *c, const pathrec *rec, const orc_options *
     for (int k = 0; k < rec->nv; ++k) {
         if (opt->grad_mode == 1 && k > 0) break;
         const vtx *V = &rec->v[k];
+        if (c->s.mat_mode == 2) {
+            for (int ch = 0; ch < 4; ++ch) ADDP(PK_FIELD, 4 * (int64_t)k + ch);
+            if (V->nee) for (int ch = 0; ch < 3; ++ch) ADDP(PK_ENV, (int64_t)V->ytex * 3 + ch);
+            continue;
+        }
         interp ip; material_interp(c, V->prim, V->b1, V->b2, &ip);
         for (int j = 0; j < ip.nw; ++j) {
             if (c->s.mat_mode == 0) {
@@ -1045,9 +1231,16 @@ static int path_params(const orc_ctx *c, const pathrec *rec, const orc_options *
     return np;
 }
 
-int32_t orc_grad(const orc_ctx *c, const orc_view *views, int32_t nviews, const orc_options *opt,
-                 const int32_t *items, int64_t n, const double *dldc, double *g_vmat, double *g_albedo,
-                 double *g_rough, double *g_metal, double *g_env, int32_t nthreads) {
+/* Shared gradient driver.  Per item: record the path, then one
+ * forward-mode evaluation of the frozen functional per parameter it reads.
+ * Texel and vertex parameters accumulate straight into dst[kind]; in field
+ * mode the derivatives with respect to the field's outputs at each vertex are
+ * collected and pulled back through the field (chain rule). */
+typedef struct { double *table, *w1, *b1, *w2, *b2; } field_grads;
+
+static int32_t grad_impl(const orc_ctx *c, const orc_view *views, int32_t nviews, const orc_options *opt,
+                         const int32_t *items, int64_t n, const double *dldc, double *dst_of[6],
+                         const field_grads *fg, int32_t nthreads) {
     if (check_args(c, views, nviews, opt, items, n) || !dldc) return -1;
     if (nthreads < 1) nthreads = 1;
 #pragma omp parallel num_threads(nthreads)
@@ -1055,32 +1248,50 @@ int32_t orc_grad(const orc_ctx *c, const orc_view *views, int32_t nviews, const 
         int64_t cnt[ORC_NCOUNT] = { 0 };
         pathrec *rec = (pathrec *)malloc(sizeof(pathrec));
         seed_t *ps = (seed_t *)malloc(sizeof(seed_t) * 64 * ORC_MAXB);
+        double gfield[ORC_MAXB][4];
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = 0; i < n; ++i) {
             double rgb[3]; uint32_t hh;
             trace_path(c, views, items[3 * i], items[3 * i + 1], items[3 * i + 2], opt, rgb, &hh, rec, cnt);
             int np = path_params(c, rec, opt, ps, 64 * ORC_MAXB);
+            memset(gfield, 0, sizeof(gfield));
             for (int j = 0; j < np; ++j) {
                 dual C[3];
                 frozen_eval(c, rec, opt, ps[j], C);
                 double g = dldc[3 * i] * C[0].d + dldc[3 * i + 1] * C[1].d + dldc[3 * i + 2] * C[2].d;
-                double *dst = NULL;
-                switch (ps[j].kind) {
-                    case PK_VMAT: dst = g_vmat; break;
-                    case PK_ALBEDO: dst = g_albedo; break;
-                    case PK_ROUGH: dst = g_rough; break;
-                    case PK_METAL: dst = g_metal; break;
-                    default: dst = g_env; break;
-                }
+                if (ps[j].kind == PK_FIELD) { gfield[ps[j].idx / 4][ps[j].idx % 4] = g; continue; }
+                double *dst = dst_of[ps[j].kind];
                 if (dst) {
 #pragma omp atomic
                     dst[ps[j].idx] += g;
                 }
             }
+            if (c->s.mat_mode == 2 && fg) {
+#pragma omp critical(field_pullback)
+                for (int k = 0; k < rec->nv; ++k)
+                    field_backward(c->s.field, rec->v[k].p, gfield[k], fg->table, fg->w1, fg->b1, fg->w2, fg->b2);
+            }
         }
         free(ps); free(rec);
     }
     return 0;
+}
+
+int32_t orc_grad(const orc_ctx *c, const orc_view *views, int32_t nviews, const orc_options *opt,
+                 const int32_t *items, int64_t n, const double *dldc, double *g_vmat, double *g_albedo,
+                 double *g_rough, double *g_metal, double *g_env, int32_t nthreads) {
+    if (c && c->s.mat_mode == 2) return -1;
+    double *dst_of[6] = { g_vmat, g_albedo, g_rough, g_metal, g_env, NULL };
+    return grad_impl(c, views, nviews, opt, items, n, dldc, dst_of, NULL, nthreads);
+}
+
+int32_t orc_grad_field(const orc_ctx *c, const orc_view *views, int32_t nviews, const orc_options *opt,
+                       const int32_t *items, int64_t n, const double *dldc, double *g_table, double *g_w1,
+                       double *g_b1, double *g_w2, double *g_b2, double *g_env, int32_t nthreads) {
+    if (!c || c->s.mat_mode != 2) return -1;
+    double *dst_of[6] = { NULL, NULL, NULL, NULL, g_env, NULL };
+    field_grads fg = { g_table, g_w1, g_b1, g_w2, g_b2 };
+    return grad_impl(c, views, nviews, opt, items, n, dldc, dst_of, &fg, nthreads);
 }
 
 int32_t orc_frozen(const orc_ctx *rc, const orc_ctx *ec, const orc_view *views, int32_t nviews,

@@ -21,8 +21,12 @@
  *     and mc_indir);
  *   - visibility by an explicit ray-mesh intersection (Appendix A
  *     "Visibility estimation");
+ *   - materials from per-vertex attributes, textures, or the material
+ *     neural field F_m (Sec. 3 "Intrinsic decomposition");
  *   - gradients of the detached-sampling path functional with respect to
- *     material texels and environment texels, by forward-mode dual numbers.
+ *     material texels and environment texels, by forward-mode dual numbers,
+ *     and with respect to the field parameters through the field's
+ *     pull-back.
  *
  * Parity status per function is stated in the header comment of oracle.c.
  */
@@ -34,12 +38,38 @@
 extern "C" {
 #endif
 
+/* Material neural field F_m (Sec. 3 "Intrinsic decomposition": m = F_m(x),
+ * an MLP over a multi-resolution hash grid; Appendix A "Network details":
+ * 16 levels, 2 features per entry, resolutions 16 to 2048, 2-layer MLP with
+ * 32 hidden units).  Encoding after Mueller et al., "Instant Neural Graphics
+ * Primitives with a Multiresolution Hash Encoding" (SIGGRAPH 2022), Sec. 3:
+ *   level l in [0, L): N_l = floor(N_min * exp(l * ln(N_max / N_min) / (L - 1))
+ *                      + 1e-6)  (N_0 = N_min when L = 1);
+ *   u = clamp((x - lo) / (hi - lo), 0, 1) per axis; s = u N_l;
+ *   cell c = min(floor(s), N_l - 1), fraction t = s - c;
+ *   grid vertex v in [0, N_l]^3 -> slot v0 + (N_l+1)(v1 + (N_l+1) v2) when
+ *   (N_l + 1)^3 <= T, else (v0 * 1 ^ v1 * 2654435761 ^ v2 * 805459861)
+ *   mod 2^32 mod T (T = 2^log2_table);
+ *   features e[2l + j] = trilinear interpolation of table[l][slot][j];
+ *   z1 = W1 e + b1 (32), a = max(z1, 0), z2 = W2 a + b2 (4),
+ *   m = sigmoid(z2) = (albedo r, g, b, roughness); metallic is 0.
+ * table [L][T][2], w1 [32][2L], b1 [32], w2 [4][32], b2 [4]. */
+#define ORC_FIELD_MAXL 16
+#define ORC_FIELD_HIDDEN 32
+#define ORC_FIELD_OUT 4
+typedef struct {
+    int32_t levels, log2_table, n_min, n_max;
+    float   lo[3], hi[3];
+    const float *table, *w1, *b1, *w2, *b2;
+} orc_field;
+
 /* Scene.  All arrays are host memory owned by the caller and must outlive
  * the context built from them.  faces are int32 triples into pos.
  * mat_mode 0: vmat[nv][5] = (albedo rgb, roughness, metallic) per vertex.
  * mat_mode 1: uv[nv][2] plus textures albedo[th][tw][3], rough[th][tw],
- *             metal[th][tw].  env[eh][ew][3] is linear HDR radiance,
- *             row 0 = +y pole. */
+ *             metal[th][tw].
+ * mat_mode 2: the material field `field` evaluated at the hit point.
+ * env[eh][ew][3] is linear HDR radiance, row 0 = +y pole. */
 typedef struct {
     const float   *pos;   int32_t nv;
     const int32_t *faces; int32_t nf;
@@ -48,6 +78,7 @@ typedef struct {
     const float   *vmat;
     const float   *albedo, *rough, *metal; int32_t tw, th;
     const float   *env;  int32_t ew, eh;
+    const orc_field *field;
 } orc_scene;
 
 /* Pinhole view.  c2w is row-major 4x4 camera-to-world; the camera looks
@@ -99,6 +130,24 @@ int32_t orc_grad(const orc_ctx *ctx, const orc_view *views, int32_t nviews,
                  const orc_options *opt, const int32_t *items, int64_t n,
                  const double *dldc, double *g_vmat, double *g_albedo,
                  double *g_rough, double *g_metal, double *g_env, int32_t nthreads);
+
+/* Gradient of sum_i dldc[i] . C_i for a field-material scene (mat_mode 2)
+ * with respect to the field's table and MLP parameters (shapes as in
+ * orc_field) and the env texels, accumulated (+=; each nullable).  Exact
+ * chain rule: the derivative of the path functional with respect to the
+ * field's output at each path vertex, pulled back through the field. */
+int32_t orc_grad_field(const orc_ctx *ctx, const orc_view *views, int32_t nviews,
+                       const orc_options *opt, const int32_t *items, int64_t n,
+                       const double *dldc, double *g_table, double *g_w1, double *g_b1,
+                       double *g_w2, double *g_b2, double *g_env, int32_t nthreads);
+
+/* The field alone: m[n][4] at points x[n][3]; and the pull-back of
+ * g[n][4] = dL/dm onto the parameters (accumulated, each nullable). */
+int32_t orc_field_eval(const orc_field *f, const double *x, int64_t n, double *m);
+int32_t orc_field_vjp(const orc_field *f, const double *x, const double *g, int64_t n,
+                      double *g_table, double *g_w1, double *g_b1, double *g_w2, double *g_b2);
+/* level resolutions N_l (test hook); returns L or a negative error */
+int32_t orc_field_levels(const orc_field *f, int64_t *res);
 
 /* Frozen-path evaluation: records the path of one item in rec_ctx's scene,
  * then evaluates the detached-sampling functional with the material and env

@@ -19,12 +19,18 @@ COUNTER_NAMES = ["closest_rays", "closest_nodes", "closest_tris", "shadow_rays",
                  "shadow_tris", "hits", "nee_visible", "candidates", "primary_miss"]
 
 
+class _Field(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("n_min", C.c_int32), ("n_max", C.c_int32),
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("table", C.c_void_p), ("w1", C.c_void_p),
+                ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p)]
+
+
 class _Scene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("nv", C.c_int32), ("faces", C.c_void_p), ("nf", C.c_int32),
                 ("uv", C.c_void_p), ("mat_mode", C.c_int32), ("vmat", C.c_void_p),
                 ("albedo", C.c_void_p), ("rough", C.c_void_p), ("metal", C.c_void_p),
                 ("tw", C.c_int32), ("th", C.c_int32), ("env", C.c_void_p), ("ew", C.c_int32),
-                ("eh", C.c_int32)]
+                ("eh", C.c_int32), ("field", C.c_void_p)]
 
 
 class _View(C.Structure):
@@ -57,6 +63,14 @@ def lib():
         _lib.orc_render.argtypes = [p, p, i32, C.POINTER(_Options), p, i64, p, p, p, i32]
         _lib.orc_grad.restype = i32
         _lib.orc_grad.argtypes = [p, p, i32, C.POINTER(_Options), p, i64, p, p, p, p, p, p, i32]
+        _lib.orc_grad_field.restype = i32
+        _lib.orc_grad_field.argtypes = [p, p, i32, C.POINTER(_Options), p, i64, p, p, p, p, p, p, p, i32]
+        _lib.orc_field_eval.restype = i32
+        _lib.orc_field_eval.argtypes = [C.POINTER(_Field), p, i64, p]
+        _lib.orc_field_vjp.restype = i32
+        _lib.orc_field_vjp.argtypes = [C.POINTER(_Field), p, p, i64, p, p, p, p, p]
+        _lib.orc_field_levels.restype = i32
+        _lib.orc_field_levels.argtypes = [C.POINTER(_Field), p]
         _lib.orc_frozen.restype = i32
         _lib.orc_frozen.argtypes = [p, p, p, i32, C.POINTER(_Options), p, p]
         _lib.orc_trace.restype = i32
@@ -115,6 +129,46 @@ def options_struct(o) -> _Options:
                     int(o.brdf), int(o.background), int(o.grad_mode))
 
 
+class FieldRef:
+    """The material field alone (TEST INFRASTRUCTURE): FP64 evaluation and
+    pull-back of the C oracle over float32 parameters."""
+
+    def __init__(self, field):
+        self.f = field
+        self._keep = [np.ascontiguousarray(a, np.float32) for a in (field.table, field.w1, field.b1, field.w2,
+                                                                      field.b2)]
+        t, w1, b1, w2, b2 = self._keep
+        L, T = t.shape[0], t.shape[1]
+        assert T & (T - 1) == 0 and t.shape[2] == 2 and w1.shape == (32, 2 * L)
+        self.s = _Field(L, T.bit_length() - 1, int(field.n_min), int(field.n_max),
+                        (C.c_float * 3)(*[float(v) for v in field.lo]), (C.c_float * 3)(*[float(v) for v in field.hi]),
+                        _ptr(t), _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2))
+
+    def levels(self) -> np.ndarray:
+        res = np.zeros(16, np.int64)
+        n = lib().orc_field_levels(C.byref(self.s), _ptr(res))
+        if n < 0:
+            raise ValueError("oracle: invalid field")
+        return res[:n]
+
+    def eval(self, x) -> np.ndarray:
+        x = _d(x).reshape(-1, 3)
+        m = np.zeros((x.shape[0], 4))
+        if lib().orc_field_eval(C.byref(self.s), _ptr(x), x.shape[0], _ptr(m)) != 0:
+            raise ValueError("oracle: invalid field")
+        return m
+
+    def vjp(self, x, g) -> Dict[str, np.ndarray]:
+        x = _d(x).reshape(-1, 3)
+        g = _d(g).reshape(-1, 4)
+        out = {k: np.zeros(a.shape) for k, a in zip(("table", "w1", "b1", "w2", "b2"), self._keep)}
+        rc = lib().orc_field_vjp(C.byref(self.s), _ptr(x), _ptr(g), x.shape[0], _ptr(out["table"]),
+                                 _ptr(out["w1"]), _ptr(out["b1"]), _ptr(out["w2"]), _ptr(out["b2"]))
+        if rc != 0:
+            raise ValueError("oracle: invalid field")
+        return out
+
+
 class Oracle:
     """FP64 reference renderer over one scene (mesh, materials, env)."""
 
@@ -127,9 +181,11 @@ class Oracle:
         if scene.mat_mode == 1:
             th, tw = k["rough"].shape
         self.scene = scene
+        self.field = FieldRef(scene.field) if scene.mat_mode == 2 else None
         s = _Scene(_ptr(k["pos"]), k["pos"].shape[0], _ptr(k["faces"]), k["faces"].shape[0], _ptr(k["uv"]),
                    int(scene.mat_mode), _ptr(k["vmat"]), _ptr(k["albedo"]), _ptr(k["rough"]),
-                   _ptr(k["metal"]), tw, th, _ptr(k["env"]), k["env"].shape[1], k["env"].shape[0])
+                   _ptr(k["metal"]), tw, th, _ptr(k["env"]), k["env"].shape[1], k["env"].shape[0],
+                   C.addressof(self.field.s) if self.field else None)
         self._h = lib().orc_create(C.byref(s), 1 if use_bvh else 0)
         if not self._h:
             raise ValueError("oracle: invalid scene")
@@ -166,15 +222,24 @@ class Oracle:
         assert dldc.shape[0] == items.shape[0]
         sc = self.scene
         g = {"env": np.zeros(sc.env.shape)}
+        vs = views_struct(views)
+        op = options_struct(opts)
+        nt = nthreads or os.cpu_count() or 1
+        if sc.mat_mode == 2:
+            for k, a in zip(("table", "w1", "b1", "w2", "b2"), self.field._keep):
+                g[k] = np.zeros(a.shape)
+            rc = lib().orc_grad_field(self._h, C.addressof(vs), len(views), C.byref(op), _ptr(items),
+                                      items.shape[0], _ptr(dldc), _ptr(g["table"]), _ptr(g["w1"]), _ptr(g["b1"]),
+                                      _ptr(g["w2"]), _ptr(g["b2"]), _ptr(g["env"]), nt)
+            if rc != 0:
+                raise ValueError("oracle.grad: invalid arguments")
+            return g
         if sc.mat_mode == 0:
             g["vmat"] = np.zeros(sc.vmat.shape)
         else:
             g["albedo"] = np.zeros(sc.albedo.shape)
             g["rough"] = np.zeros(sc.rough.shape)
             g["metal"] = np.zeros(sc.metal.shape)
-        vs = views_struct(views)
-        op = options_struct(opts)
-        nt = nthreads or os.cpu_count() or 1
         rc = lib().orc_grad(self._h, C.addressof(vs), len(views), C.byref(op), _ptr(items), items.shape[0],
                             _ptr(dldc), _ptr(g.get("vmat")), _ptr(g.get("albedo")), _ptr(g.get("rough")),
                             _ptr(g.get("metal")), _ptr(g["env"]), nt)

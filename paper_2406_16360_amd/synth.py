@@ -26,6 +26,31 @@ import numpy as np
 # --------------------------------------------------------------------------
 MAT_VERTEX = 0
 MAT_TEXTURE = 1
+MAT_FIELD = 2
+
+
+@dataclasses.dataclass
+class Field:
+    """Parameters of a material field: a multi-resolution hash grid
+    (levels x 2^log2_table entries of 2 features) and a 2-layer MLP
+    (2L -> 32 -> 4), over the box [lo, hi]."""
+    table: np.ndarray                  # float32 [L, T, 2]
+    w1: np.ndarray                     # float32 [32, 2L]
+    b1: np.ndarray                     # float32 [32]
+    w2: np.ndarray                     # float32 [4, 32]
+    b2: np.ndarray                     # float32 [4]
+    lo: np.ndarray                     # float32 [3]
+    hi: np.ndarray                     # float32 [3]
+    n_min: int = 16
+    n_max: int = 2048
+
+    @property
+    def levels(self) -> int:
+        return int(self.table.shape[0])
+
+    @property
+    def log2_table(self) -> int:
+        return int(self.table.shape[1]).bit_length() - 1
 
 
 @dataclasses.dataclass
@@ -39,6 +64,7 @@ class Scene:
     albedo: Optional[np.ndarray] = None  # float32 [th, tw, 3]
     rough: Optional[np.ndarray] = None   # float32 [th, tw]
     metal: Optional[np.ndarray] = None   # float32 [th, tw]
+    field: Optional[Field] = None        # MAT_FIELD
 
     @property
     def nv(self) -> int:
@@ -441,6 +467,32 @@ def plane_scene(albedo=(0.3, 0.5, 0.7), env_value: float = 2.0, env_hw=(8, 16)) 
     vmat = np.tile(np.array([[albedo[0], albedo[1], albedo[2], 0.5, 0.0]], np.float32), (4, 1))
     env = np.full((env_hw[0], env_hw[1], 3), env_value, np.float32)
     return Scene(pos=pos, faces=faces, env=env, mat_mode=MAT_VERTEX, vmat=vmat)
+
+
+def random_field(lo, hi, rng: np.random.Generator, levels: int = 16, log2_table: int = 19, n_min: int = 16,
+                 n_max: int = 2048, table_scale: float = 0.5) -> Field:
+    """Seeded field parameters: table entries uniform in +-table_scale,
+    layers with fan-in scaled normal weights, output biases around a mid-grey
+    albedo and mid roughness."""
+    T = 1 << log2_table
+    table = rng.uniform(-table_scale, table_scale, (levels, T, 2))
+    w1 = rng.normal(0.0, 1.0 / np.sqrt(2 * levels), (32, 2 * levels)) * 2.0
+    b1 = rng.normal(0.0, 0.1, 32)
+    w2 = rng.normal(0.0, 1.0 / np.sqrt(32), (4, 32)) * 2.0
+    b2 = np.array([0.0, -0.2, 0.2, 0.0]) + rng.normal(0.0, 0.1, 4)
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    return Field(table=f32(table), w1=f32(w1), b1=f32(b1), w2=f32(w2), b2=f32(b2), lo=f32(lo), hi=f32(hi),
+                 n_min=n_min, n_max=n_max)
+
+
+def with_field(scene: Scene, rng: np.random.Generator, margin: float = 0.05, **kw) -> Scene:
+    """The same mesh and environment with a material field over the mesh's
+    bounding box (enlarged by `margin` of its extent) instead of its
+    per-vertex or texture materials."""
+    lo, hi = scene.pos.min(0), scene.pos.max(0)
+    ext = np.maximum(hi - lo, 1e-3)
+    f = random_field(lo - margin * ext, hi + margin * ext, rng, **kw)
+    return Scene(pos=scene.pos, faces=scene.faces, env=scene.env, mat_mode=MAT_FIELD, field=f)
 
 
 def sample_items(workload: Workload, n: int, seed: int) -> np.ndarray:
