@@ -38,7 +38,8 @@
  *              uv [nv][2]; per-vertex materials [nv][5] = (albedo r, g, b,
  *              roughness, metallic); textures albedo [th][tw][3],
  *              roughness [th][tw], metallic [th][tw] (row 0 at v = 0,
- *              bilinear, wrap); env [eh][ew][3] linear HDR, equirectangular,
+ *              bilinear, wrap); or the material field (mrs_field) at the
+ *              hit point; env [eh][ew][3] linear HDR, equirectangular,
  *              +y up, row 0 at the +y pole.  Images are packed per view at
  *              pixel_offset: [sum_v W_v * H_v][3], row-major, row 0 on top.
  *   Random     Every uniform is Philox4x32-10 (Salmon et al., SC'11) with
@@ -63,7 +64,7 @@ typedef enum {
     MRS_EUNSUPPORTED = -5   /* option combination not implemented */
 } mrs_status;
 
-enum { MRS_MAT_VERTEX = 0, MRS_MAT_TEXTURE = 1 };
+enum { MRS_MAT_VERTEX = 0, MRS_MAT_TEXTURE = 1, MRS_MAT_FIELD = 2 };
 enum { MRS_BRDF_LAMBERT = 0, MRS_BRDF_LAMBERT_GGX = 1 };
 enum { MRS_BG_ENV = 0, MRS_BG_BLACK = 1 };
 enum { MRS_GRAD_FULL = 0, MRS_GRAD_PRIMARY = 1 };
@@ -75,6 +76,41 @@ enum { MRS_TAPE_AUTO = 0, MRS_TAPE_ON = 1, MRS_TAPE_OFF = 2 };
 typedef struct mrs_bvh mrs_bvh;     /* opaque, library-owned */
 typedef struct mrs_tape mrs_tape;   /* opaque, library-owned */
 
+/* Material neural field F_m (Sec. 3 "Intrinsic decomposition": m = F_m(x),
+ * a small MLP over a multi-resolution hash grid; Appendix A "Network
+ * details": 16 levels, 2 features per entry, coarsest resolution 16, finest
+ * 2048, 2-layer MLP with 32 hidden units).  The encoding follows Mueller et
+ * al., "Instant Neural Graphics Primitives with a Multiresolution Hash
+ * Encoding" (SIGGRAPH 2022), Sec. 3:
+ *   level l in [0, L): resolution N_l = floor(N_min exp(l ln(N_max/N_min) /
+ *     (L - 1)) + 1e-6), computed in double (N_0 = N_min when L = 1);
+ *   u = clamp((x - lo) / (hi - lo), 0, 1) per axis, s = u N_l, cell
+ *     c = min(floor(s), N_l - 1), fraction s - c;
+ *   grid vertex v in [0, N_l]^3 -> slot v0 + (N_l + 1)(v1 + (N_l + 1) v2)
+ *     while (N_l + 1)^3 <= T, else (v0 ^ 2654435761 v1 ^ 805459861 v2)
+ *     mod 2^32 mod T;
+ *   e[2l + j] = trilinear interpolation of table[l][slot][j] over the cell;
+ *   z1 = W1 e + b1 (32), a = max(z1, 0), z2 = W2 a + b2 (4), m = sigmoid(z2)
+ *     = (albedo r, g, b, roughness); the field's metallic is 0.
+ * All arrays are device float32: table [L][T][2], w1 [32][2L] (row-major),
+ * b1 [32], w2 [4][32], b2 [4]. */
+#define MRS_FIELD_MAX_LEVELS 16
+#define MRS_FIELD_MAX_LOG2_TABLE 24
+#define MRS_FIELD_MAX_RES 1048576
+typedef struct {
+    int32_t levels;          /* L in [1, MRS_FIELD_MAX_LEVELS] */
+    int32_t log2_table;      /* T = 2^log2_table slots per level, in [1, MRS_FIELD_MAX_LOG2_TABLE] */
+    int32_t n_min, n_max;    /* 1 <= n_min <= n_max <= MRS_FIELD_MAX_RES */
+    float   lo[3], hi[3];    /* box mapped onto the unit cube, hi > lo */
+    const float *table, *w1, *b1, *w2, *b2;
+} mrs_field;
+
+/* Gradients of the field parameters (device, accumulated with +=, each
+ * nullable; shapes as in mrs_field). */
+typedef struct {
+    float *table, *w1, *b1, *w2, *b2;
+} mrs_field_grads;
+
 /* Scene: mesh, materials, lighting (Sec. 3: mesh {V, F}, material m,
  * environment map L_env).  All pointers are device pointers. */
 typedef struct {
@@ -82,7 +118,7 @@ typedef struct {
     const int32_t *faces; int32_t nf;     /* [nf][3] */
     const float   *uv;                    /* [nv][2]; required for MRS_MAT_TEXTURE */
     const mrs_bvh *bvh;                   /* from mrs_build_bvh over the same pos/faces */
-    int32_t        mat_mode;              /* MRS_MAT_VERTEX or MRS_MAT_TEXTURE */
+    int32_t        mat_mode;              /* MRS_MAT_VERTEX, MRS_MAT_TEXTURE or MRS_MAT_FIELD */
     const float   *vmat;                  /* [nv][5] for MRS_MAT_VERTEX */
     const float   *albedo;                /* [th][tw][3] */
     const float   *rough;                 /* [th][tw] */
@@ -90,6 +126,7 @@ typedef struct {
     int32_t        tw, th;
     const float   *env;                   /* [eh][ew][3] */
     int32_t        ew, eh;
+    mrs_field      field;                 /* the material source for MRS_MAT_FIELD */
 } mrs_scene;
 
 /* Pinhole camera (Sec. 3 "Rendering": camera ray o + t d).  c2w is
@@ -129,6 +166,7 @@ typedef struct {
     float *rough;    /* [th][tw] */
     float *metal;    /* [th][tw] */
     float *env;      /* [eh][ew][3] */
+    mrs_field_grads field;   /* MRS_MAT_FIELD: the field's parameters */
 } mrs_grads;
 
 /* Builds a linear BVH (Karras, HPG 2012; the paper's LBVH, Appendix A) over
@@ -200,6 +238,18 @@ mrs_status mrs_render(const mrs_scene *scene, const mrs_view *views, int32_t n_v
 mrs_status mrs_render_backward(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
                                const mrs_options *opt, const float *d_grad_image,
                                const mrs_grads *grads, const mrs_tape *tape, void *stream);
+
+/* The material field alone at n points: d_x [n][3] positions, d_m [n][4]
+ * outputs (albedo rgb, roughness), device float32.  Errors: MRS_EINVAL
+ * (null, n < 0, field parameters out of range), MRS_EHIP. */
+mrs_status mrs_field_eval(const mrs_field *field, const float *d_x, int64_t n, float *d_m, void *stream);
+
+/* Pull-back of d_grad_m [n][4] = dL/dm at the points d_x [n][3] onto the
+ * field's parameters, accumulated (+=) into `grads` (null members skipped).
+ * Points whose four gradient values are all zero are skipped.  Errors: as
+ * mrs_field_eval. */
+mrs_status mrs_field_backward(const mrs_field *field, const float *d_x, const float *d_grad_m, int64_t n,
+                              const mrs_field_grads *grads, void *stream);
 
 /* Denoiser G-buffer (Appendix A "Denoiser": its normal and position
  * buffers): for the ray through every pixel centre, the closest hit's

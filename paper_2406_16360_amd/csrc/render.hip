@@ -53,10 +53,10 @@ namespace {
 // while a launch sequence is being captured into a graph)
 // ============================================================================
 enum KernelId { KID_ENV = 0, KID_SCHED, KID_GENERATE, KID_CLOSEST, KID_SHADE, KID_SHADOW, KID_RESOLVE, KID_ADJOINT,
-                KID_TRACE, KID_PLAN_FWD, KID_PLAN_BWD, KID_COUNT };
+                KID_TRACE, KID_FIELD, KID_FIELD_BWD, KID_PLAN_FWD, KID_PLAN_BWD, KID_COUNT };
 const char *const kKernelNames[KID_COUNT] = {"env_tables", "schedule", "generate", "trace_closest", "shade",
-                                             "trace_shadow", "resolve", "adjoint", "trace_batch",
-                                             "plan_forward_graph", "plan_backward_graph"};
+                                             "trace_shadow", "resolve", "adjoint", "trace_batch", "field_eval",
+                                             "field_backward", "plan_forward_graph", "plan_backward_graph"};
 struct Profiler {
     std::mutex mu;
     bool on = false;
@@ -111,9 +111,10 @@ struct Res {
     DevBuf ctr, sched, out;                                    // iteration counters, scheduler, sample radiance
     DevBuf ct_hit, ct_y, ct_rr;                                // chunk tape (recompute mode)
     DevBuf grec;                                               // adjoint gradient records
+    DevBuf fm, fvtx, gvtx;                                     // field mode: pool materials, vertex materials and gradients
     void release_all() {
         for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &views, &qa_o, &qa_d, &qa_t, &qb_o,
-                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec})
+                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec, &fm, &fvtx, &gvtx})
             b->release();
     }
 };
@@ -129,7 +130,7 @@ struct GradRec {
 GradRec grad_rec(const mrs_scene *sc, const mrs_grads *gr) {
     GradRec g;
     const bool vertex = sc->mat_mode == MRS_MAT_VERTEX;
-    if (vertex ? gr->vmat != nullptr : (gr->albedo || gr->rough || gr->metal))
+    if (sc->mat_mode != MRS_MAT_FIELD && (vertex ? gr->vmat != nullptr : (gr->albedo || gr->rough || gr->metal)))
         g.n_mat = vertex ? (uint32_t)sc->nv : (uint32_t)sc->tw * (uint32_t)sc->th;
     if (gr->env) g.n_env = (uint32_t)sc->ew * (uint32_t)sc->eh;
     g.env_base = kMatRec * g.n_mat;
@@ -149,7 +150,12 @@ struct Workspace {
 };
 Workspace g_ws;
 
+bool field_wanted(const mrs_grads *gr) {
+    return gr->field.table || gr->field.w1 || gr->field.b1 || gr->field.w2 || gr->field.b2;
+}
+
 struct Job {
+    FieldDev fd{};                // field mode: the field's device view
     std::vector<ViewDev> vd;
     uint64_t S = 0, pixels = 0;
     SceneDev sd{};
@@ -190,6 +196,9 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
     } else if (sc->mat_mode == MRS_MAT_TEXTURE) {
         if (!sc->uv || !sc->albedo || !sc->rough || !sc->metal) return fail(MRS_EINVAL, "texture mode needs uv, albedo, rough, metal");
         if (sc->tw <= 0 || sc->th <= 0 || (int64_t)sc->tw * sc->th >= (1ll << 31)) return fail(MRS_EINVAL, "bad texture size %dx%d", sc->tw, sc->th);
+    } else if (sc->mat_mode == MRS_MAT_FIELD) {
+        const char *why = nullptr;
+        if (!make_field_dev(&sc->field, job.fd, &why)) return fail(MRS_EINVAL, "scene.%s", why);
     } else {
         return fail(MRS_EINVAL, "unknown mat_mode %d", sc->mat_mode);
     }
@@ -314,9 +323,10 @@ mrs_status reserve_env(const mrs_scene *sc, Res &r) {
 size_t claim_offset_words(int n_iter) { return ((sizeof(IterCtr) * (size_t)(n_iter + 1) + 127) / 128) * 32; }
 size_t ctr_words(int n_iter) { return claim_offset_words(n_iter) + (size_t)n_iter * kClaimWords; }
 
-mrs_status reserve_pool(Res &r, uint32_t P, uint64_t out_samples, int n_iter) {
+mrs_status reserve_pool(Res &r, uint32_t P, uint64_t out_samples, int n_iter, bool field) {
     size_t q = sizeof(float4) * (size_t)P;
     for (DevBuf *b : {&r.qa_o, &r.qa_d, &r.qa_t, &r.qb_o, &r.qb_d, &r.qb_t, &r.hits, &r.so, &r.sd, &r.sc}) TRY(b->reserve(q));
+    if (field) TRY(r.fm.reserve(q));
     TRY(r.ctr.reserve(4 * ctr_words(n_iter)));
     TRY(r.sched.reserve(sizeof(Sched)));
     TRY(r.out.reserve(sizeof(float4) * (size_t)out_samples));
@@ -353,7 +363,8 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
     uint64_t n = ch.c1 - ch.c0;
     uint32_t P = (uint32_t)std::min<uint64_t>(job.pool, n);
     int n_iter = iterations(job, n, P);
-    TRY(reserve_pool(r, P, n, n_iter));
+    const bool field = job.sd.mat_mode == MRS_MAT_FIELD;
+    TRY(reserve_pool(r, P, n, n_iter, field));
     size_t nctr = ctr_words(n_iter);
     k_fill_u32<<<nblocks(nctr, 256), 256, 0, s>>>(r.ctr.as<uint32_t>(), nctr, 0u);
     uint32_t *claim = r.ctr.as<uint32_t>() + claim_offset_words(n_iter);
@@ -377,10 +388,16 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
             TraceArgs ta{job.sd.nodes, job.sd.tris, qa, r.hits.as<float4>(), ctr, it, claim + it * kClaimWords};
             k_trace_closest<<<persistent_blocks(P, bs), bs, kLdsStackBytes * bs, s>>>(ta);
         }
+        if (field) {
+            PROF(KID_FIELD, s);
+            PointsHits src{r.hits.as<float4>(), job.sd.tris, ctr, it};
+            k_field_eval<PointsHits><<<nblocks(P, kFieldTile), 64, 0, s>>>(job.fd, src, r.fm.as<float>());
+        }
         {
             PROF(KID_SHADE, s);
             ShadeArgs sa{job.sd, job.vt, job.op, qa, qb, r.hits.as<float4>(), ctr, it, r.so.as<float4>(),
                          r.sd.as<float4>(), r.sc.as<float4>(), r.out.as<float4>(), ch.c0, hash, tape, use_tape};
+            sa.s.fm = r.fm.as<float4>();
             if (job.sd.env.H <= kEnvLdsRows) k_shade<true><<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
             else k_shade<false><<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
         }
@@ -402,15 +419,48 @@ void resolve(const Job &job, const Chunk &ch, const Res &r, float *image, float 
     k_resolve<<<nblocks(ch.pix1 - ch.pix0, 256), 256, 0, s>>>(ra);
 }
 
+// Field mode around each adjoint launch: the field at every taped vertex
+// (the adjoint replays the materials), the adjoint writing dL/d(field
+// output) per vertex, then the field's pull-back over the vertices that
+// carry a gradient.  fvtx and gvtx hold B * min(kAdjChunk, samples) records.
+mrs_status reserve_field_vertices(const Job &job, uint64_t samples, Res &r) {
+    size_t n = (size_t)std::min<uint64_t>(kAdjChunk, samples) * job.op.B;
+    TRY(r.fvtx.reserve(sizeof(float4) * n));
+    TRY(r.gvtx.reserve(sizeof(float4) * n));
+    return MRS_OK;
+}
+
 mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, const float *dimg, const mrs_grads *gr,
-                   const GradRec &gl, float *rec, hipStream_t s) {
-    if (gl.words == 0) return MRS_OK;
+                   const GradRec &gl, float *rec, Res &r, hipStream_t s) {
+    const bool field = job.sd.mat_mode == MRS_MAT_FIELD && field_wanted(gr);
+    if (gl.words == 0 && !field) return MRS_OK;
+    const FieldGrads fg{gr->field.table, gr->field.w1, gr->field.b1, gr->field.w2, gr->field.b2};
     for (uint64_t a0 = c0; a0 < c1; a0 += kAdjChunk) {
         uint64_t n = std::min<uint64_t>(kAdjChunk, c1 - a0);
-        PROF(KID_ADJOINT, s);
-        AdjArgs aa{job.sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env,
-                   rec, gl.env_base, gl.n_mat > 0 ? 1 : 0};
-        k_adjoint<<<nblocks(n, kAdjBlock), kAdjBlock, 0, s>>>(aa);
+        SceneDev sd = job.sd;
+        if (job.sd.mat_mode == MRS_MAT_FIELD) {
+            PROF(KID_FIELD, s);
+            PointsTape src{tp, job.sd.tris, a0, n, job.op.B};
+            k_field_eval<PointsTape><<<nblocks(src.count(), kFieldTile), 64, 0, s>>>(job.fd, src, r.fvtx.as<float>());
+            sd.fm = r.fvtx.as<float4>();
+        }
+        const int kgrad = job.op.grad_mode == MRS_GRAD_PRIMARY ? 1 : job.op.B;
+        if (field) {
+            size_t words = 4 * (size_t)n * kgrad;
+            k_fill_u32<<<nblocks(words, 256), 256, 0, s>>>(r.gvtx.as<uint32_t>(), words, 0u);
+        }
+        {
+            PROF(KID_ADJOINT, s);
+            AdjArgs aa{sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env,
+                       rec, gl.env_base, gl.n_mat > 0 ? 1 : 0, r.gvtx.as<float4>(), field ? 1 : 0};
+            k_adjoint<<<nblocks(n, kAdjBlock), kAdjBlock, 0, s>>>(aa);
+        }
+        if (field) {
+            PROF(KID_FIELD_BWD, s);
+            PointsTape src{tp, job.sd.tris, a0, n, kgrad};
+            const uint64_t tiles = (src.count() + kFieldTile - 1) / kFieldTile;
+            k_field_backward<PointsTape><<<field_backward_blocks(tiles), 64, 0, s>>>(job.fd, src, r.gvtx.as<float>(), fg);
+        }
     }
     HIPTRY(hipGetLastError(), "adjoint launch");
     return MRS_OK;
@@ -489,10 +539,11 @@ mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, co
     TRY(env_tables(sc, j, r, s));
     const GradRec gl = grad_rec(sc, grads);
     if (gl.words) TRY(r.grec.reserve(4 * gl.words));
+    if (sc->mat_mode == MRS_MAT_FIELD) TRY(reserve_field_vertices(j, j.S, r));
     float *rec = r.grec.as<float>();
     grad_rec_clear(gl, rec, s);
     if (tape) {
-        TRY(adjoint(j, tape_view(tape), 0, j.S, dimg, grads, gl, rec, s));
+        TRY(adjoint(j, tape_view(tape), 0, j.S, dimg, grads, gl, rec, r, s));
     } else {
         uint64_t cap = max_chunk(chunks);
         size_t n = (size_t)cap * j.op.B;
@@ -502,7 +553,7 @@ mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, co
         for (const Chunk &ch : chunks) {
             Tape tp{r.ct_hit.as<float4>(), r.ct_y.as<float4>(), r.ct_rr.as<float>(), ch.c0, cap};
             TRY(run_wavefront(j, ch, tp, 1, nullptr, r, s));
-            TRY(adjoint(j, tp, ch.c0, ch.c1, dimg, grads, gl, rec, s));
+            TRY(adjoint(j, tp, ch.c0, ch.c1, dimg, grads, gl, rec, r, s));
         }
     }
     grad_rec_fold(sc, gl, rec, grads, s);
@@ -812,9 +863,10 @@ extern "C" mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *vi
     for (const std::vector<Chunk> *cs : {&p->fwd_chunks, &p->bwd_chunks})
         for (const Chunk &c : *cs)
             n_iter = std::max(n_iter, iterations(job, c.c1 - c.c0, (uint32_t)std::min<uint64_t>(job.pool, c.c1 - c.c0)));
-    PTRY(reserve_pool(p->res, P, outmax, n_iter));
+    PTRY(reserve_pool(p->res, P, outmax, n_iter, scene->mat_mode == MRS_MAT_FIELD));
     if (p->has_grads) {
         if (size_t words = grad_rec(scene, grads).words) PTRY(p->res.grec.reserve(4 * words));
+        if (scene->mat_mode == MRS_MAT_FIELD) PTRY(reserve_field_vertices(job, job.S, p->res));
         PTRY(decide_tape(job, opt, true, &p->tape));
         if (!p->tape) {
             size_t n = (size_t)max_chunk(p->bwd_chunks) * job.op.B;

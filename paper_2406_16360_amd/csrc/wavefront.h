@@ -27,6 +27,7 @@
 #include <cstdint>
 
 #include "device.h"
+#include "field.h"
 #include "trace.h"
 
 namespace mrs {
@@ -47,6 +48,7 @@ struct Sched { uint64_t next, end; };
 struct SceneDev {
     const int32_t *faces;
     const float *uv, *vmat, *albedo, *rough, *metal;
+    const float4 *fm;   // field mode: materials from the field pass (per pool entry in shade, per vertex in the adjoint)
     int mat_mode, tw, th;
     const BvhNode *nodes;
     const TriRec *tris;
@@ -163,6 +165,15 @@ __device__ __forceinline__ MatRaw fetch_material(const SceneDev &s, int prim, fl
     return m;
 }
 
+// field output (albedo rgb, roughness); the field's metallic is 0
+__device__ __forceinline__ MatRaw field_material(float4 f) {
+    MatRaw m;
+    m.a = V3{f.x, f.y, f.z};
+    m.r = f.w;
+    m.mu = 0.0f;
+    return m;
+}
+
 __device__ __forceinline__ Mat clamp_material(const MatRaw &r) {
     Mat m;
     m.a = V3{fminf(fmaxf(r.a.x, 0.0f), 1.0f), fminf(fmaxf(r.a.y, 0.0f), 1.0f), fminf(fmaxf(r.a.z, 0.0f), 1.0f)};
@@ -170,6 +181,46 @@ __device__ __forceinline__ Mat clamp_material(const MatRaw &r) {
     m.mu = fminf(fmaxf(r.mu, 0.0f), 1.0f);
     return m;
 }
+
+// hit position from the leaf-order triangle and barycentrics (as surface())
+__device__ __forceinline__ V3 hit_point(const TriRec *__restrict__ tris, int leaf, float b1, float b2) {
+    TriRec tr = tris[leaf];
+    return xyz(tr.a) * (1.0f - b1 - b2) + xyz(tr.b) * b1 + xyz(tr.c) * b2;
+}
+
+// Points of the field passes: the hits of an iteration's queue, and the
+// vertices of the taped paths of an adjoint launch (slot (k - 1) n + j for
+// vertex k of sample g0 + j; a vertex exists when every earlier vertex
+// continued the path and its own entry is a hit).
+struct PointsHits {
+    const float4 *hits; const TriRec *tris; const IterCtr *ctr; int it;
+    __device__ __forceinline__ uint64_t count() const { return ctr[it].n_live; }
+    __device__ __forceinline__ bool get(uint64_t i, V3 &p) const {
+        if (i >= count()) return false;
+        const float4 h = hits[i];
+        const int leaf = __float_as_int(h.w);
+        if (leaf < 0) return false;
+        p = hit_point(tris, leaf, h.y, h.z);
+        return true;
+    }
+};
+
+struct PointsTape {
+    Tape tape; const TriRec *tris; uint64_t g0, n; int kmax;
+    __host__ __device__ __forceinline__ uint64_t count() const { return (uint64_t)kmax * n; }
+    __device__ __forceinline__ bool get(uint64_t i, V3 &p) const {
+        if (i >= count()) return false;
+        const int k = (int)(i / n) + 1;
+        const uint64_t col = g0 + (i - (uint64_t)(k - 1) * n) - tape.base;
+        for (int kk = 1; kk < k; ++kk)
+            if (!(tape.rr[(uint64_t)(kk - 1) * tape.S + col] > 0.0f)) return false;
+        const float4 th = tape.hit[(uint64_t)(k - 1) * tape.S + col];
+        const int leaf = __float_as_int(th.z);
+        if (leaf < 0) return false;
+        p = hit_point(tris, leaf, th.x, th.y);
+        return true;
+    }
+};
 
 struct Surf { V3 p, n; Frame F; int prim; };
 __device__ __forceinline__ Surf surface(const SceneDev &s, int leaf, float b1, float b2, V3 d) {
@@ -450,7 +501,8 @@ __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS
             float b1 = hr.y, b2 = hr.z;
             Surf S = surface(a.s, leaf, b1, b2, d);
             Interp ip;
-            Mat m = clamp_material(fetch_material(a.s, S.prim, b1, b2, ip));
+            Mat m = clamp_material(a.s.mat_mode == MRS_MAT_FIELD ? field_material(a.s.fm[i])
+                                                                 : fetch_material(a.s, S.prim, b1, b2, ip));
             V3 wo = to_local(S.F, d * -1.0f);
             Lobe L = make_lobe(m, wo, a.op.spec);
             V3 org = spawn(S.p, S.n);
@@ -622,6 +674,8 @@ struct AdjArgs {
     float *rec;            // gradient records (see below), zeroed before the first chunk
     uint32_t env_base;     // first word of the env records
     int mat_on;            // some material gradient array is wanted
+    float4 *gvtx;          // field mode: dL/d(field output) per path vertex, slot (k - 1) n + j
+    int field_on;          // field mode: some field gradient array is wanted
 };
 
 // ---------------------------------------------------------------------------
@@ -722,7 +776,8 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
         dk[k - 1] = d;
         Surf S = surface(a.s, leaf, th.x, th.y, d);
         Interp ip;
-        Mat m = clamp_material(fetch_material(a.s, S.prim, th.x, th.y, ip));
+        Mat m = clamp_material(a.s.mat_mode == MRS_MAT_FIELD ? field_material(a.s.fm[(uint64_t)(k - 1) * a.n + j])
+                                                             : fetch_material(a.s, S.prim, th.x, th.y, ip));
         Lobe L = make_lobe(m, to_local(S.F, d * -1.0f), a.op.spec);
         float4 ty = a.tape.y[ti];
         V3 D = V3{0, 0, 0};
@@ -769,7 +824,9 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
             int leaf = __float_as_int(th.z);
             V3 dd = dk[k - 1];
             Surf S = surface(a.s, leaf, th.x, th.y, dd);
-            MatRaw raw = fetch_material(a.s, S.prim, th.x, th.y, ip);
+            const bool field = a.s.mat_mode == MRS_MAT_FIELD;
+            MatRaw raw = field ? field_material(a.s.fm[(uint64_t)(k - 1) * a.n + j])
+                               : fetch_material(a.s, S.prim, th.x, th.y, ip);
             Mat m = clamp_material(raw);
             Lobe L = make_lobe(m, to_local(S.F, dd * -1.0f), a.op.spec);
             V3 ga = V3{0, 0, 0};
@@ -807,14 +864,15 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
             // clamp masks (the derivative passes on the closed interval) and
             // the arrays the caller wants
             const bool vertex = a.s.mat_mode == MRS_MAT_VERTEX;
-            const bool alb = vertex ? a.gvmat != nullptr : a.galb != nullptr;
-            const bool rgh = vertex ? a.gvmat != nullptr : a.grough != nullptr;
-            const bool mtl = vertex ? a.gvmat != nullptr : a.gmetal != nullptr;
+            const bool alb = field ? a.field_on != 0 : vertex ? a.gvmat != nullptr : a.galb != nullptr;
+            const bool rgh = field ? a.field_on != 0 : vertex ? a.gvmat != nullptr : a.grough != nullptr;
+            const bool mtl = field ? false : vertex ? a.gvmat != nullptr : a.gmetal != nullptr;
             gm[0] = (alb && raw.a.x >= 0.0f && raw.a.x <= 1.0f) ? ga.x : 0.0f;
             gm[1] = (alb && raw.a.y >= 0.0f && raw.a.y <= 1.0f) ? ga.y : 0.0f;
             gm[2] = (alb && raw.a.z >= 0.0f && raw.a.z <= 1.0f) ? ga.z : 0.0f;
             gm[3] = (rgh && raw.r >= kRoughMin && raw.r <= 1.0f) ? gr : 0.0f;
             gm[4] = (mtl && raw.mu >= 0.0f && raw.mu <= 1.0f) ? gmu : 0.0f;
+            if (field && a.field_on) a.gvtx[(uint64_t)(k - 1) * a.n + j] = make_float4(gm[0], gm[1], gm[2], gm[3]);
             T = T * Bk[k - 1];
         }
         // group 1: interpolation entries 0 and 1, and the env texel

@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MIRRES_LIB") or os.path.join(_HERE, "libmirres.so")
 
 MRS_OK, MRS_EINVAL, MRS_ENOMEM, MRS_EHIP, MRS_EOVERFLOW, MRS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-MAT_VERTEX, MAT_TEXTURE = 0, 1
+MAT_VERTEX, MAT_TEXTURE, MAT_FIELD = 0, 1, 2
+FIELD_KEYS = ("table", "w1", "b1", "w2", "b2")
 TAPE_AUTO, TAPE_ON, TAPE_OFF = 0, 1, 2
 
 
@@ -33,11 +34,22 @@ class MirresError(RuntimeError):
         self.code = code
 
 
+class _Field(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("n_min", C.c_int32), ("n_max", C.c_int32),
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("table", C.c_void_p), ("w1", C.c_void_p),
+                ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p)]
+
+
+class _FieldGrads(C.Structure):
+    _fields_ = [("table", C.c_void_p), ("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p),
+                ("b2", C.c_void_p)]
+
+
 class _Scene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("nv", C.c_int32), ("faces", C.c_void_p), ("nf", C.c_int32),
                 ("uv", C.c_void_p), ("bvh", C.c_void_p), ("mat_mode", C.c_int32), ("vmat", C.c_void_p),
                 ("albedo", C.c_void_p), ("rough", C.c_void_p), ("metal", C.c_void_p), ("tw", C.c_int32),
-                ("th", C.c_int32), ("env", C.c_void_p), ("ew", C.c_int32), ("eh", C.c_int32)]
+                ("th", C.c_int32), ("env", C.c_void_p), ("ew", C.c_int32), ("eh", C.c_int32), ("field", _Field)]
 
 
 class _View(C.Structure):
@@ -54,7 +66,13 @@ class _Options(C.Structure):
 
 class _Grads(C.Structure):
     _fields_ = [("vmat", C.c_void_p), ("albedo", C.c_void_p), ("rough", C.c_void_p), ("metal", C.c_void_p),
-                ("env", C.c_void_p)]
+                ("env", C.c_void_p), ("field", _FieldGrads)]
+
+
+def _grads_struct(grads: Dict[str, Optional[torch.Tensor]]) -> _Grads:
+    fg = _FieldGrads(*[_ptr(grads.get(k)) for k in FIELD_KEYS])
+    return _Grads(_ptr(grads.get("vmat")), _ptr(grads.get("albedo")), _ptr(grads.get("rough")),
+                  _ptr(grads.get("metal")), _ptr(grads.get("env")), fg)
 
 
 # BVH builders (MRS_BVH_*).  Scenes built here default to PLOC: on the
@@ -67,8 +85,8 @@ DEFAULT_BUILDER = int(os.environ.get("MIRRES_BVH_BUILDER", BVH_PLOC))
 EXPORTS = ["mrs_build_bvh", "mrs_build_bvh_with", "mrs_bvh_refit", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
            "mrs_plan_create", "mrs_plan_forward", "mrs_plan_backward", "mrs_plan_info", "mrs_plan_destroy",
            "mrs_tape_bytes", "mrs_tape_destroy", "mrs_gbuffer", "mrs_denoise_work_bytes", "mrs_denoise",
-           "mrs_denoise_backward", "mrs_profile_begin", "mrs_profile_end", "mrs_release_workspace",
-           "mrs_last_error"]
+           "mrs_denoise_backward", "mrs_field_eval", "mrs_field_backward", "mrs_profile_begin", "mrs_profile_end",
+           "mrs_release_workspace", "mrs_last_error"]
 
 
 class _KernelTime(C.Structure):
@@ -95,6 +113,10 @@ def _load():
     lib.mrs_denoise.argtypes = [p, i32, p, p, p, p, p, p, p]
     lib.mrs_denoise_backward.restype = i32
     lib.mrs_denoise_backward.argtypes = [p, i32, p, p, p, p, p, p, p]
+    lib.mrs_field_eval.restype = i32
+    lib.mrs_field_eval.argtypes = [C.POINTER(_Field), p, i64, p, p]
+    lib.mrs_field_backward.restype = i32
+    lib.mrs_field_backward.argtypes = [C.POINTER(_Field), p, p, i64, C.POINTER(_FieldGrads), p]
     lib.mrs_bvh_destroy.argtypes = [p]
     lib.mrs_bvh_info.restype = i32
     lib.mrs_bvh_info.argtypes = [p, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
@@ -248,11 +270,71 @@ class Tape:
             self._h = None
 
 
+class Field:
+    """Material field F_m (hash-grid encoding + 2-layer MLP, include/mirres.h
+    mrs_field) as GPU float32 tensors: table [L, T, 2], w1 [32, 2L], b1 [32],
+    w2 [4, 32], b2 [4], over the box [lo, hi]."""
+
+    def __init__(self, table, w1, b1, w2, b2, lo, hi, n_min: int = 16, n_max: int = 2048, device="cuda"):
+        dev = torch.device(device)
+        t = lambda x: torch.as_tensor(x).to(device=dev, dtype=torch.float32).contiguous()
+        self.table, self.w1, self.b1, self.w2, self.b2 = t(table), t(w1), t(b1), t(w2), t(b2)
+        self.lo = [float(v) for v in torch.as_tensor(lo).reshape(3).tolist()]
+        self.hi = [float(v) for v in torch.as_tensor(hi).reshape(3).tolist()]
+        self.n_min, self.n_max = int(n_min), int(n_max)
+        T = int(self.table.shape[1])
+        if T & (T - 1) or self.table.dim() != 3 or self.table.shape[2] != 2:
+            raise ValueError("field table must be [L, 2^k, 2]")
+
+    @classmethod
+    def from_synth(cls, f, device="cuda") -> "Field":
+        return cls(f.table, f.w1, f.b1, f.w2, f.b2, f.lo, f.hi, f.n_min, f.n_max, device=device)
+
+    def with_params(self, **kw) -> "Field":
+        f = object.__new__(Field)
+        f.__dict__.update(self.__dict__)
+        for k, v in kw.items():
+            if v is not None:
+                setattr(f, k, _dev(v))
+        return f
+
+    def zeros_like_params(self) -> Dict[str, torch.Tensor]:
+        return {k: torch.zeros_like(getattr(self, k)) for k in FIELD_KEYS}
+
+    def struct(self) -> _Field:
+        L, T = int(self.table.shape[0]), int(self.table.shape[1])
+        return _Field(L, T.bit_length() - 1, self.n_min, self.n_max, (C.c_float * 3)(*self.lo),
+                      (C.c_float * 3)(*self.hi), _ptr(self.table), _ptr(self.w1), _ptr(self.b1), _ptr(self.w2),
+                      _ptr(self.b2))
+
+    def eval(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        """m [n, 4] = (albedo rgb, roughness) at the points x [n, 3]."""
+        x = _dev(x).reshape(-1, 3)
+        m = torch.empty((x.shape[0], 4), dtype=torch.float32, device=x.device)
+        fs = self.struct()
+        _check(_lib.mrs_field_eval(C.byref(fs), x.data_ptr(), x.shape[0], m.data_ptr(), _stream(stream)))
+        return m
+
+    def backward(self, x: torch.Tensor, grad_m: torch.Tensor, grads: Optional[Dict[str, torch.Tensor]] = None,
+                 stream=None) -> Dict[str, torch.Tensor]:
+        """Accumulates the pull-back of grad_m [n, 4] into `grads` (zeros if None)."""
+        x = _dev(x).reshape(-1, 3)
+        gm = _dev(grad_m).reshape(-1, 4)
+        if grads is None:
+            grads = self.zeros_like_params()
+        fs = self.struct()
+        fg = _FieldGrads(*[_ptr(grads.get(k)) for k in FIELD_KEYS])
+        _check(_lib.mrs_field_backward(C.byref(fs), x.data_ptr(), gm.data_ptr(), x.shape[0], C.byref(fg),
+                                       _stream(stream)))
+        return grads
+
+
 class GpuScene:
     """Mesh, materials and environment map as GPU float32 tensors."""
 
     def __init__(self, pos, faces, env, vmat=None, uv=None, albedo=None, rough=None, metal=None,
-                 bvh: Optional[Bvh] = None, device="cuda", builder: Optional[int] = None):
+                 bvh: Optional[Bvh] = None, device="cuda", builder: Optional[int] = None,
+                 field: Optional[Field] = None):
         dev = torch.device(device)
 
         def t(x, dt=torch.float32):
@@ -268,13 +350,15 @@ class GpuScene:
         self.albedo = t(albedo)
         self.rough = t(rough)
         self.metal = t(metal)
-        self.mat_mode = MAT_VERTEX if self.vmat is not None else MAT_TEXTURE
+        self.field = field
+        self.mat_mode = MAT_FIELD if field is not None else (MAT_VERTEX if self.vmat is not None else MAT_TEXTURE)
         self.bvh = bvh if bvh is not None else Bvh(self.pos, self.faces, builder=builder)
 
     @classmethod
     def from_synth(cls, sc, device="cuda", builder: Optional[int] = None) -> "GpuScene":
+        field = Field.from_synth(sc.field, device=device) if sc.mat_mode == MAT_FIELD else None
         return cls(sc.pos, sc.faces, sc.env, vmat=sc.vmat if sc.mat_mode == 0 else None, uv=sc.uv,
-                   albedo=sc.albedo, rough=sc.rough, metal=sc.metal, device=device, builder=builder)
+                   albedo=sc.albedo, rough=sc.rough, metal=sc.metal, device=device, builder=builder, field=field)
 
     def with_params(self, vmat=None, albedo=None, rough=None, metal=None, env=None) -> "GpuScene":
         s = object.__new__(GpuScene)
@@ -290,7 +374,20 @@ class GpuScene:
             th, tw = self.rough.shape
         return _Scene(_ptr(self.pos), self.pos.shape[0], _ptr(self.faces), self.faces.shape[0], _ptr(self.uv),
                       self.bvh.handle, self.mat_mode, _ptr(self.vmat), _ptr(self.albedo), _ptr(self.rough),
-                      _ptr(self.metal), tw, th, _ptr(self.env), self.env.shape[1], self.env.shape[0])
+                      _ptr(self.metal), tw, th, _ptr(self.env), self.env.shape[1], self.env.shape[0],
+                      self.field.struct() if self.field is not None else _Field())
+
+    def zero_grads(self) -> Dict[str, torch.Tensor]:
+        """Zeroed gradient buffers for every parameter of the scene."""
+        g = {"env": torch.zeros_like(self.env)}
+        if self.mat_mode == MAT_VERTEX:
+            g["vmat"] = torch.zeros_like(self.vmat)
+        elif self.mat_mode == MAT_FIELD:
+            g.update(self.field.zeros_like_params())
+        else:
+            g.update(albedo=torch.zeros_like(self.albedo), rough=torch.zeros_like(self.rough),
+                     metal=torch.zeros_like(self.metal))
+        return g
 
 
 def views_struct(views: Sequence) -> Tuple[C.Array, int, List[int]]:
@@ -349,15 +446,8 @@ def render_backward(scene: GpuScene, views: Sequence, opts, grad_image: torch.Te
     vs, npix, _ = views_struct(views)
     gi = _dev(grad_image).reshape(npix, 3)
     if grads is None:
-        grads = {"env": torch.zeros_like(scene.env)}
-        if scene.mat_mode == MAT_VERTEX:
-            grads["vmat"] = torch.zeros_like(scene.vmat)
-        else:
-            grads["albedo"] = torch.zeros_like(scene.albedo)
-            grads["rough"] = torch.zeros_like(scene.rough)
-            grads["metal"] = torch.zeros_like(scene.metal)
-    g = _Grads(_ptr(grads.get("vmat")), _ptr(grads.get("albedo")), _ptr(grads.get("rough")),
-               _ptr(grads.get("metal")), _ptr(grads.get("env")))
+        grads = scene.zero_grads()
+    g = _grads_struct(grads)
     op = o.struct()
     sc = scene.struct()
     _check(_lib.mrs_render_backward(C.byref(sc), C.addressof(vs), len(views), C.byref(op), gi.data_ptr(),
@@ -396,14 +486,8 @@ class Plan:
         g = None
         if with_grad:
             self.grad_image = torch.zeros_like(self.image)
-            self.grads["env"] = torch.zeros_like(scene.env)
-            if scene.mat_mode == MAT_VERTEX:
-                self.grads["vmat"] = torch.zeros_like(scene.vmat)
-            else:
-                self.grads.update(albedo=torch.zeros_like(scene.albedo), rough=torch.zeros_like(scene.rough),
-                                  metal=torch.zeros_like(scene.metal))
-            g = _Grads(_ptr(self.grads.get("vmat")), _ptr(self.grads.get("albedo")), _ptr(self.grads.get("rough")),
-                       _ptr(self.grads.get("metal")), _ptr(self.grads.get("env")))
+            self.grads = scene.zero_grads()
+            g = _grads_struct(self.grads)
         op = self.opts.struct(self.dbg_rgb, self.dbg_hash)
         sc = scene.struct()
         h = C.c_void_p()

@@ -470,12 +470,18 @@ def plane_scene(albedo=(0.3, 0.5, 0.7), env_value: float = 2.0, env_hw=(8, 16)) 
 
 
 def random_field(lo, hi, rng: np.random.Generator, levels: int = 16, log2_table: int = 19, n_min: int = 16,
-                 n_max: int = 2048, table_scale: float = 0.5) -> Field:
-    """Seeded field parameters: table entries uniform in +-table_scale,
-    layers with fan-in scaled normal weights, output biases around a mid-grey
-    albedo and mid roughness."""
+                 n_max: int = 2048, table_scale: float = 0.5, decay: float = 0.0) -> Field:
+    """Seeded field parameters: table entries uniform in +-table_scale
+    (n_min / N_l)^decay at level l of resolution N_l (decay 1 keeps each
+    level's slope per unit length alike, the fine levels carrying less
+    amplitude, as in a trained field), layers with fan-in scaled normal
+    weights, output biases around a mid-grey albedo and mid roughness."""
     T = 1 << log2_table
     table = rng.uniform(-table_scale, table_scale, (levels, T, 2))
+    if decay:
+        g = np.log(n_max / n_min) / max(levels - 1, 1)
+        res = np.floor(n_min * np.exp(np.arange(levels) * g) + 1e-6)
+        table *= ((n_min / res) ** decay)[:, None, None]
     w1 = rng.normal(0.0, 1.0 / np.sqrt(2 * levels), (32, 2 * levels)) * 2.0
     b1 = rng.normal(0.0, 0.1, 32)
     w2 = rng.normal(0.0, 1.0 / np.sqrt(32), (4, 32)) * 2.0
@@ -485,13 +491,14 @@ def random_field(lo, hi, rng: np.random.Generator, levels: int = 16, log2_table:
                  n_min=n_min, n_max=n_max)
 
 
-def with_field(scene: Scene, rng: np.random.Generator, margin: float = 0.05, **kw) -> Scene:
+def with_field(scene: Scene, rng: np.random.Generator, margin: float = 0.05, decay: float = 1.0, **kw) -> Scene:
     """The same mesh and environment with a material field over the mesh's
     bounding box (enlarged by `margin` of its extent) instead of its
-    per-vertex or texture materials."""
+    per-vertex or texture materials; table amplitude falls as 1 / N_l
+    (decay 1) by default."""
     lo, hi = scene.pos.min(0), scene.pos.max(0)
     ext = np.maximum(hi - lo, 1e-3)
-    f = random_field(lo - margin * ext, hi + margin * ext, rng, **kw)
+    f = random_field(lo - margin * ext, hi + margin * ext, rng, decay=decay, **kw)
     return Scene(pos=scene.pos, faces=scene.faces, env=scene.env, mat_mode=MAT_FIELD, field=f)
 
 

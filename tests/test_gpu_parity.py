@@ -202,8 +202,11 @@ def test_white_furnace_gpu(mr):
 
 
 # --------------------------------------------------------------- a10 / a11
-def _grad_check(mr, orc_mod, w, r, pixels=None, seed=0, label=""):
-    """dL/dI seeded on `pixels` (all if None), zeroed where a decision flipped."""
+def _grad_check(mr, orc_mod, w, r, pixels=None, seed=0, label="", tape_rel=None):
+    """dL/dI seeded on `pixels` (all if None), zeroed where a decision flipped.
+    Tape and recompute agree within 1e-4 x RMS of the group, or, with
+    tape_rel, within tape_rel of each element plus 1e-6 of the largest (for
+    arrays whose entries sum thousands of float atomics in launch order)."""
     rng = np.random.default_rng(seed)
     npix = sum(v.w * v.h for v in w.views)
     gi = np.zeros((npix, 3), np.float32)
@@ -231,7 +234,10 @@ def _grad_check(mr, orc_mod, w, r, pixels=None, seed=0, label=""):
         print(f"[{label}] grad {k}: rms={rms:.3e} bad={bad.sum()}/{bad.size} "
               f"tape-vs-recompute={np.abs(a - c).max() / rms:.2e}", flush=True)
         assert bad.mean() <= 1e-3, k
-        assert np.abs(a - c).max() <= 1e-4 * rms, k
+        if tape_rel is None:
+            assert np.abs(a - c).max() <= 1e-4 * rms, k
+        else:
+            assert np.all(np.abs(a - c) <= tape_rel * np.abs(og[k]) + 1e-6 * np.abs(og[k]).max()), k
 
 
 def test_gradient_c1(mr, orc_mod):
