@@ -8,6 +8,11 @@ triangle displaced mesh with 2048^2 fp32 textures and a 512x256 HDR env
 ground-truth materials, then the adjoint replay that scatters dL/dtexel and
 dL/denv-texel.  value = path samples per second of that fwd+bwd step.
 
+--workload field runs the same step with the materials from the paper's
+neural material field F_m (16-level hash grid, 2^19 slots per level,
+resolutions 16..2048, 2-layer MLP with 32 hidden units) instead of textures,
+differentiating the field's table and weights.
+
 Also reported (one JSON line):
   roofline      the dominant kernel's algorithmic bytes per second (counts
                 from the FP64 oracle's own SAH BVH on a seeded subset of the
@@ -37,19 +42,29 @@ HBM_PEAK_GBPS = 8000.0
 # entries 8), pixel 12 B, adjoint gradient RMW 3x the material fetch, env
 # gradient RMW 24 B, vertex record 32 B written + read.
 NODE_B, TRI_B, HIT_B, CAND_B, PIX_B, ENVG_B, VREC_B = 32, 36, 36, 20, 12, 24, 64
+# material field, per point: hit or tape record 16 B, triangle 36 B, 16
+# levels x 8 corners x 8 B of table entries, output 16 B; the pull-back adds
+# the read-modify-write of the same 128 entries
+FIELD_B = 16 + 36 + 128 * 8 + 16
+FIELD_BWD_B = FIELD_B + 2 * 128 * 8
 
 
-def kernel_bytes(cnt, n, spp, tex):
+def kernel_bytes(cnt, n, spp, tex, field=False):
     """Per-sample algorithmic bytes attributed to each kernel class."""
-    tmat = 80 if tex else 60
+    tmat = 16 if field else (80 if tex else 60)
     per = {k: v / n for k, v in cnt.items()}
-    return {
+    kb = {
         "trace_closest": NODE_B * per["closest_nodes"] + TRI_B * per["closest_tris"],
         "trace_shadow": NODE_B * per["shadow_nodes"] + TRI_B * per["shadow_tris"],
         "shade": per["hits"] * (HIT_B + tmat) + per["candidates"] * CAND_B,
         "resolve": PIX_B / spp,
-        "adjoint": PIX_B / spp + per["hits"] * (HIT_B + 3 * tmat) + per["nee_visible"] * ENVG_B + per["hits"] * VREC_B,
+        "adjoint": PIX_B / spp + per["hits"] * (HIT_B + (2 if field else 3) * tmat) + per["nee_visible"] * ENVG_B
+                   + per["hits"] * VREC_B,
     }
+    if field:
+        kb["field_eval"] = 2 * per["hits"] * FIELD_B          # forward pass and the adjoint's replay
+        kb["field_backward"] = per["hits"] * FIELD_BWD_B
+    return kb
 
 
 def source_digest():
@@ -80,6 +95,11 @@ def make_workload(name):
     from paper_2406_16360_amd import synth
     if name == "c3":
         return synth.config3()
+    if name == "field":
+        w = synth.config3()
+        w.scene = synth.with_field(w.scene, np.random.default_rng(3003))
+        w.name = "c3_field_" + w.name[3:]
+        return w
     if name == "c2":
         return synth.config2()
     if name == "c1":
@@ -299,7 +319,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "bvh", "denoise"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "bvh", "denoise", "field"])
     ap.add_argument("--mode", default="fwdbwd", choices=["fwdbwd", "fwd"])
     ap.add_argument("--tape", default="on", choices=["auto", "on", "off"])
     ap.add_argument("--pool", type=int, default=0)
@@ -334,22 +354,21 @@ def main():
     opts.tape_mode = {"auto": mirres.TAPE_AUTO, "on": mirres.TAPE_ON, "off": mirres.TAPE_OFF}[args.tape]
     opts.pool, opts.block = args.pool, args.block
     tex = sc.mat_mode == mirres.MAT_TEXTURE
+    field = sc.mat_mode == mirres.MAT_FIELD
 
-    # target rendered from seeded ground-truth materials (a second texture set)
+    # target rendered from seeded ground-truth materials (a second texture set or field)
     rng = np.random.default_rng(9000)
     if tex:
         ga, gr_, gm = synth.noise_textures(sc.rough.shape[0], rng)
         gt = sc.with_params(albedo=torch.tensor(ga, device=dev), rough=torch.tensor(gr_, device=dev),
                             metal=torch.tensor(gm, device=dev))
+    elif field:
+        f2 = synth.with_field(w.scene, rng).field
+        gt = mirres.GpuScene(sc.pos, sc.faces, sc.env, bvh=sc.bvh, field=mirres.Field.from_synth(f2))
     else:
         gt = sc.with_params(vmat=sc.vmat.flip(0).contiguous())
     target = mirres.render(gt, w.views, opts).clone()
-    grads = {"env": torch.zeros_like(sc.env)}
-    if tex:
-        grads.update(albedo=torch.zeros_like(sc.albedo), rough=torch.zeros_like(sc.rough),
-                     metal=torch.zeros_like(sc.metal))
-    else:
-        grads["vmat"] = torch.zeros_like(sc.vmat)
+    grads = sc.zero_grads()
 
     def step():
         if args.mode == "fwd":
@@ -395,9 +414,12 @@ def main():
     roof = None
     extra = {}
     if cnt is not None:
-        kb = kernel_bytes(cnt, nsub, w.views[0].spp, tex)
+        kb = kernel_bytes(cnt, nsub, w.views[0].spp, tex, field)
         if args.mode == "fwd":
             kb.pop("adjoint")
+            kb.pop("field_backward", None)
+            if "field_eval" in kb:
+                kb["field_eval"] /= 2                          # no adjoint replay
         balg = sum(kb.values())
         roof, kern = roofline_from(prof, kb, S, args.steps, args.workload)
         extra = {"path_roofline": {"alg_bytes_per_sample": balg,

@@ -104,8 +104,7 @@ __device__ __forceinline__ int drow(int r, int half) { return 8 * (r >> 2) + 4 *
 // cell and its fractions come from u N in double: at N = 2048 one float ulp
 // of u moves the grid coordinate by about 1e-4 of a cell.
 __device__ __forceinline__ void field_corners(const double (&u)[3], int N, bool dense, uint32_t tmask,
-                                              uint32_t (&slot)[8], float (&w)[8]) {
-    uint32_t c[3];
+                                              uint32_t (&slot)[8], float (&w)[8], uint32_t (&c)[3]) {
     float t[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -145,9 +144,9 @@ __device__ __forceinline__ void field_encode(const FieldDev &f, const double (&u
         if (valid && l < f.L) {
             const int N = half ? f.res[lb] : f.res[la];
             const bool dense = (f.dense >> l) & 1u;
-            uint32_t slot[8];
+            uint32_t slot[8], cell[3];
             float w[8];
-            field_corners(u, N, dense, f.tmask, slot, w);
+            field_corners(u, N, dense, f.tmask, slot, w, cell);
             const float2 *tab = f.table + ((size_t)l << f.log2T);
             float2 v[8];
 #pragma unroll
@@ -241,14 +240,78 @@ __global__ __launch_bounds__(64) void k_field_eval(FieldDev f, Src src, float *_
 
 struct FieldGrads { float *table, *w1, *b1, *w2, *b2; };
 
-// Pull-back: g[i][4] = dL/dm_i; accumulates the parameter gradients.  A
-// persistent loop over tiles keeps the weight-gradient sums in registers
-// until the block's last tile.
+// Table scatter of one level per half-wave: each pending lane adds w_k d_j
+// into feature j of the slot of corner k (16 values).  Device-scope float
+// atomics are carried out past L2, one memory-side request per cache line an
+// instruction touches, so the values are not issued lane by lane:
+//   - a half-wave whose pending lanes all lie in one cell (neighbouring
+//     points of a tile at the coarse levels) sums its 16 values over the
+//     half (butterfly) and its first pending lane adds them;
+//   - otherwise every pending lane stages its 16 (offset, value) pairs in
+//     LDS, corner pairs along x first (their slots are adjacent on dense
+//     levels, and on hashed levels when the lower x is even, since the x
+//     prime is 1), and the wavefront issues them transposed: instruction j
+//     takes the 16 pairs of lanes 4j..4j+3, so it touches a few cache lines
+//     instead of 64.
+// Offsets count floats from the table gradient's base.  Every lane of the
+// wavefront calls it.
+constexpr int kScatterPairs = 16;
+__device__ __forceinline__ void scatter_level(float *gtab, uint32_t base, const uint32_t (&slot)[8],
+                                              const float (&w)[8], float d0, float d1, const uint32_t (&cell)[3],
+                                              bool pending, uint32_t *s_off, float *s_val, int *s_cnt) {
+    const int lane = __lane_id();
+    const uint64_t half_mask = lane < 32 ? 0x00000000FFFFFFFFull : 0xFFFFFFFF00000000ull;
+    const uint64_t pm = __ballot(pending);
+    if (pm == 0) return;
+    const uint64_t mine = pm & half_mask;
+    const int leader = mine ? __ffsll((unsigned long long)mine) - 1 : lane;
+    const uint32_t l0 = __shfl(cell[0], leader), l1 = __shfl(cell[1], leader), l2 = __shfl(cell[2], leader);
+    const bool differs = pending && (cell[0] != l0 || cell[1] != l1 || cell[2] != l2);
+    const bool agg = mine != 0 && (__ballot(differs) & half_mask) == 0;
+    float v[kScatterPairs];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[2 * k] = pending ? w[k] * d0 : 0.0f;
+        v[2 * k + 1] = pending ? w[k] * d1 : 0.0f;
+    }
+    if (__ballot(agg) != 0) {
+#pragma unroll
+        for (int e = 0; e < kScatterPairs; ++e) {
+            float t = agg ? v[e] : 0.0f;
+#pragma unroll
+            for (int o = 16; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+            if (agg) v[e] = t;
+        }
+    }
+    const int n = agg ? (lane == leader ? kScatterPairs : 0) : (pending ? kScatterPairs : 0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        s_off[lane * kScatterPairs + 2 * k] = base + 2 * slot[k];
+        s_off[lane * kScatterPairs + 2 * k + 1] = base + 2 * slot[k] + 1;
+        s_val[lane * kScatterPairs + 2 * k] = v[2 * k];
+        s_val[lane * kScatterPairs + 2 * k + 1] = v[2 * k + 1];
+    }
+    s_cnt[lane] = n;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScatterPairs; ++j) {
+        const int e = j * 64 + lane, src = e / kScatterPairs;
+        if ((e % kScatterPairs) < s_cnt[src]) atomicAdd(gtab + s_off[e], s_val[e]);
+    }
+    __syncthreads();
+}
+
+#ifndef MRS_FIELD_BWD_WAVES
+#define MRS_FIELD_BWD_WAVES 2
+#endif
 template <class Src>
-__global__ __launch_bounds__(64) void k_field_backward(FieldDev f, Src src, const float *__restrict__ g,
-                                                       FieldGrads out) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MRS_FIELD_BWD_WAVES)))
+void k_field_backward(FieldDev f, Src src, const float *__restrict__ g, FieldGrads out) {
     __shared__ float sT[kFieldTile * kFieldStride];
     __shared__ float4 sG[kFieldTile];
+    __shared__ uint32_t s_off[64 * kScatterPairs];
+    __shared__ float s_val[64 * kScatterPairs];
+    __shared__ int s_cnt[64];
     const int lane = threadIdx.x, half = lane >> 5, hid = lane & 31;
     const uint64_t ntiles = (src.count() + kFieldTile - 1) / kFieldTile;
     float w1c[16], w1r[16];
@@ -320,24 +383,19 @@ __global__ __launch_bounds__(64) void k_field_backward(FieldDev f, Src src, cons
             de = __builtin_amdgcn_mfma_f32_32x32x2f32(w1r[s], sT[hid * kFieldStride + 2 * s + half], de, 0, 0, 0);
         __syncthreads();
         // scatter dL/de of the lane's levels through the corner weights
-        if (valid && out.table) {
+        if (out.table) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int la = 4 * (q >> 1) + (q & 1), lb = la + 2;
                 const int l = half ? lb : la;
-                if (l < f.L) {
-                    const int N = half ? f.res[lb] : f.res[la];
-                    uint32_t slot[8];
-                    float w[8];
-                    field_corners(u, N, (f.dense >> l) & 1u, f.tmask, slot, w);
-                    float *tab = out.table + ((size_t)l << (f.log2T + 1));
-                    const float d0 = de[2 * q], d1 = de[2 * q + 1];
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        atomicAdd(tab + 2 * slot[k], w[k] * d0);
-                        atomicAdd(tab + 2 * slot[k] + 1, w[k] * d1);
-                    }
-                }
+                if (__ballot(valid && l < f.L) == 0) continue;
+                const int N = half ? f.res[lb] : f.res[la];
+                uint32_t slot[8], cell[3];
+                float w[8];
+                field_corners(u, N, (f.dense >> (l & 31)) & 1u, f.tmask, slot, w, cell);
+                const uint32_t base = (uint32_t)(l < f.L ? l : 0) << (f.log2T + 1);
+                scatter_level(out.table, base, slot, w, de[2 * q], de[2 * q + 1], cell, valid && l < f.L, s_off,
+                              s_val, s_cnt);
             }
         }
     }
