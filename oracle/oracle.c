@@ -37,6 +37,15 @@
  *                     path gradients against differences of the frozen
  *                     functional.  The hash primes are the published ones
  *                     (Mueller et al. 2022) and are pinned only on the x axis.
+ *   reservoir reuse - neighbour offsets uniform over the window (chi-square);
+ *                     on an unoccluded Lambertian plane under a constant
+ *                     environment with cosine-sampled candidates every merge
+ *                     (spatial, temporal) still gives exactly albedo x L per
+ *                     sample; with env candidates too the merged estimator's
+ *                     mean over seeds is albedo x L; with no neighbour and no
+ *                     history it reduces to plain RIS; texture and env
+ *                     gradients with reuse against central differences of
+ *                     the frozen functional.
  * Parity with numbers printed in the paper is unpinned: the paper prints no
  * per-pixel or per-gradient values for this path.
  */
@@ -982,15 +991,253 @@ static void camera_ray(const orc_view *vw, int x, int y, double u0, double u1, d
     normalize3(d);
 }
 
+/* Shading point of a surface hit (Sec. 3 "Rendering"): position from the
+ * barycentrics, geometric normal turned towards the viewer, shading frame and
+ * clamped material. */
+typedef struct {
+    int32_t prim; double b1, b2;
+    double p[3], n[3], wo[3], t[3], b[3], m[5];
+} shpt;
+
+static void shading_point(const orc_ctx *c, const hitrec *hr, const double d[3], int k, shpt *S) {
+    S->prim = hr->prim; S->b1 = hr->b1; S->b2 = hr->b2;
+    const double *v0 = c->v + 9 * (size_t)hr->prim, *v1 = v0 + 3, *v2 = v0 + 6;
+    double b0 = 1.0 - hr->b1 - hr->b2, e1[3], e2[3], ng[3];
+    for (int a = 0; a < 3; ++a) S->p[a] = b0 * v0[a] + hr->b1 * v1[a] + hr->b2 * v2[a];
+    sub3(v1, v0, e1); sub3(v2, v0, e2); cross3(e1, e2, ng); normalize3(ng);
+    if (dot3(ng, d) > 0.0) { ng[0] = -ng[0]; ng[1] = -ng[1]; ng[2] = -ng[2]; }
+    for (int a = 0; a < 3; ++a) { S->n[a] = ng[a]; S->wo[a] = -d[a]; }
+    orc_frame(S->n, S->t, S->b);
+    if (c->s.mat_mode == 2) {
+        dual md[5]; seed_t none = { PK_NONE, -1 };
+        material_field_d(c, S->p, k, none, md);
+        for (int ch = 0; ch < 5; ++ch) S->m[ch] = md[ch].v;
+    } else {
+        interp ip; material_interp(c, hr->prim, hr->b1, hr->b2, &ip);
+        material_plain(c, &ip, S->m);
+    }
+}
+
+/* RIS over Me env + Mb BRDF candidates with a streaming weighted reservoir
+ * (Sec. 4.1, Eq. restir; App. A "Spatial-temporal reuse"), candidate s drawn
+ * from Philox block (k, s).  sel = selected candidate (-1 none); W = its
+ * contribution weight w_sum / p_hat(y). */
+typedef struct {
+    int32_t sel, ytex;
+    double y[3], fy[3], Ly[3], wsum, phat, W;
+} risres;
+
+static void ris_vertex(const orc_ctx *c, const shpt *S, const orc_options *opt, uint32_t pixel, uint32_t sc,
+                       uint32_t vi, int k, risres *r, uint32_t *h, int64_t *cnt) {
+    int spec = opt->brdf == 1;
+    int Mb = opt->ris_m_brdf, Me = opt->ris_m - opt->ris_m_brdf;
+    double u[4];
+    r->sel = -1; r->ytex = -1; r->wsum = 0.0; r->phat = 0.0; r->W = 0.0;
+    for (int a = 0; a < 3; ++a) { r->y[a] = 0.0; r->fy[a] = 0.0; r->Ly[a] = 0.0; }
+    double co = dot3(S->n, S->wo);
+    if (!(co > 0.0)) return;
+    for (int s = 0; s < opt->ris_m; ++s) {
+        cnt[ORC_C_CANDIDATES]++;
+        uniforms4(opt->seed, pixel, sc, vi, (uint32_t)k, (uint32_t)s, u);
+        double w[3], qe = 0.0, qb = 0.0;
+        int32_t tex = -1;
+        int ok;
+        if (s < Me) {
+            ok = env_sample(c, u[0], u[1], w, &qe, &tex);
+            if (ok) qb = mix_pdf(S->n, S->wo, w, S->m, spec);
+        } else {
+            int lb = mix_sample(S->n, S->t, S->b, S->wo, S->m, spec, u[0], u[1], u[2], w);
+            ok = lb != 0;
+            if (ok) {
+                qb = mix_pdf(S->n, S->wo, w, S->m, spec);
+                qe = env_pdf_dir(c, w);
+                tex = env_texel_of(c, w);
+                *h ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
+            }
+        }
+        if (!ok) continue;
+        double ci = dot3(S->n, w);
+        if (!(ci > 0.0)) continue;
+        double f[3], L[3];
+        brdf_eval_plain(S->n, S->wo, w, S->m, spec, f);
+        for (int ch = 0; ch < 3; ++ch) L[ch] = env_channel(c, tex, ch);
+        double phat = (L[0] * f[0] + L[1] * f[1] + L[2] * f[2]) / 3.0 * ci;
+        double den = Me * qe + Mb * qb;
+        if (!(phat > 0.0) || !(den > 0.0)) continue;
+        double ws = phat / den;
+        r->wsum += ws;
+        if (u[3] < ws / r->wsum) {
+            r->sel = s; r->phat = phat; r->ytex = tex;
+            for (int a = 0; a < 3; ++a) { r->y[a] = w[a]; r->fy[a] = f[a]; r->Ly[a] = L[a]; }
+        }
+    }
+    if (r->sel >= 0) r->W = r->wsum / r->phat;
+}
+
+/* ------------------------------------------------------------------ */
+/* reservoir reuse at primary vertices (Sec. 4.1 end; App. A            */
+/* "Spatial-temporal reuse"), in the readings the design document       */
+/* lists: per frame, the initial RIS reservoir r0 of every sample is     */
+/* merged with the previous frame's final reservoir of the same sample   */
+/* (temporal, its confidence capped at m_cap * M), then with the        */
+/* temporally merged reservoirs of `spatial` neighbours (same view and   */
+/* sample index, offsets uniform in a (2R+1)^2 window without the       */
+/* centre, from Philox block (1, 0xFFE0 + j) by integer arithmetic).     */
+/* Merging is the confidence-weighted combine: input i with sample y_i,  */
+/* contribution weight W_i and confidence M_i gets resampling weight     */
+/* w_i = p_hat_q(y_i) W_i M_i at the merging vertex q; the pick follows  */
+/* the streaming reservoir rule, and W = sum w / (sum M p_hat_q(y)).    */
+/* ------------------------------------------------------------------ */
+typedef struct { double y[3], W, M; } resv;
+
+/* the RIS target at a shading point: mean over channels of L(y) f(y) cos */
+static double phat_at(const orc_ctx *c, const shpt *S, int spec, const double y[3]) {
+    double ci = dot3(S->n, y);
+    if (!(ci > 0.0)) return 0.0;
+    double f[3], L[3];
+    brdf_eval_plain(S->n, S->wo, y, S->m, spec, f);
+    int32_t tex = env_texel_of(c, y);
+    for (int ch = 0; ch < 3; ++ch) L[ch] = env_channel(c, tex, ch);
+    return (L[0] * f[0] + L[1] * f[1] + L[2] * f[2]) / 3.0 * ci;
+}
+
+static int merge_reservoirs(const orc_ctx *c, const shpt *S, int spec, const resv *in, const double *u, int n,
+                            resv *out) {
+    double wsum = 0.0, Msum = 0.0;
+    int sel = -1;
+    for (int i = 0; i < n; ++i) {
+        if (!(in[i].M > 0.0)) continue;
+        Msum += in[i].M;
+        if (!(in[i].W > 0.0)) continue;
+        double w = phat_at(c, S, spec, in[i].y) * in[i].W * in[i].M;
+        if (!(w > 0.0)) continue;
+        wsum += w;
+        if (u[i] < w / wsum) sel = i;
+    }
+    out->M = Msum;
+    out->W = 0.0;
+    for (int a = 0; a < 3; ++a) out->y[a] = 0.0;
+    if (sel >= 0) {
+        for (int a = 0; a < 3; ++a) out->y[a] = in[sel].y[a];
+        out->W = wsum / (Msum * phat_at(c, S, spec, out->y));
+    }
+    return sel;
+}
+
+static uint32_t ev_merge(uint32_t stage, uint32_t sel) { return fnv_word(fnv_word(FNV_BASIS, 0x40000u | stage), sel); }
+
+static int64_t sample_index(const orc_view *views, int32_t vi, int32_t pixel, int32_t sidx) {
+    int64_t base = 0;
+    for (int v = 0; v < vi; ++v) base += (int64_t)views[v].w * views[v].h * views[v].spp;
+    return base + (int64_t)pixel * views[vi].spp + sidx;
+}
+
+/* primary vertex of sample (vi, pixel, sidx) and its initial reservoir; 0
+ * when the primary ray misses (no reservoir) */
+static int primary_vertex(const orc_ctx *c, const orc_view *views, int32_t vi, int32_t pixel, int32_t sidx,
+                          const orc_options *opt, shpt *S, resv *r0, uint32_t *h, int64_t *cnt) {
+    const orc_view *vw = &views[vi];
+    uint32_t sc = vw->sample_offset + (uint32_t)sidx;
+    double u[4], o[3], d[3];
+    uniforms4(opt->seed, (uint32_t)pixel, sc, (uint32_t)vi, 0, 0, u);
+    camera_ray(vw, pixel % vw->w, pixel / vw->w, u[0], u[1], o, d);
+    cnt[ORC_C_CLOSEST_RAYS]++;
+    hitrec hr = trace_closest(c, o, d, 0, &cnt[ORC_C_CLOSEST_NODES], &cnt[ORC_C_CLOSEST_TRIS]);
+    if (hr.prim < 0) return 0;
+    shading_point(c, &hr, d, 0, S);
+    risres rr;
+    ris_vertex(c, S, opt, (uint32_t)pixel, sc, (uint32_t)vi, 1, &rr, h, cnt);
+    for (int a = 0; a < 3; ++a) r0->y[a] = rr.y[a];
+    r0->W = rr.W;
+    r0->M = dot3(S->n, S->wo) > 0.0 ? (double)opt->ris_m : 0.0;
+    return 1;
+}
+
+/* temporal merge of a sample's initial reservoir with the previous frame's */
+static void temporal_merge(const orc_ctx *c, const orc_view *views, int32_t vi, int32_t pixel, int32_t sidx,
+                           const orc_options *opt, const shpt *S, const resv *r0, resv *r1, uint32_t *h) {
+    const orc_reuse *ru = opt->reuse;
+    *r1 = *r0;
+    if (!ru->temporal || !ru->prev) return;
+    const float *pr = ru->prev + 8 * sample_index(views, vi, pixel, sidx);
+    resv in[2];
+    in[0] = *r0;
+    for (int a = 0; a < 3; ++a) in[1].y[a] = pr[a];
+    in[1].W = pr[3];
+    in[1].M = fmin((double)pr[4], (double)ru->m_cap * opt->ris_m);
+    double u[4], uu[2];
+    uniforms4(opt->seed, (uint32_t)pixel, views[vi].sample_offset + (uint32_t)sidx, (uint32_t)vi, 1, 0xFFD0u, u);
+    uu[0] = 0.0; uu[1] = u[0];
+    int sel = merge_reservoirs(c, S, opt->brdf == 1, in, uu, 2, r1);
+    if (h) *h ^= ev_merge(1u, (uint32_t)sel);
+}
+
+/* final reservoir of sample (vi, pixel, sidx) at its primary vertex S,
+ * given its initial reservoir r0 */
+static void reuse_reservoir(const orc_ctx *c, const orc_view *views, int32_t vi, int32_t pixel, int32_t sidx,
+                            const orc_options *opt, const shpt *S, const resv *r0, resv *r2, uint32_t *h,
+                            int64_t *cnt) {
+    const orc_reuse *ru = opt->reuse;
+    const orc_view *vw = &views[vi];
+    uint32_t sc = vw->sample_offset + (uint32_t)sidx;
+    resv in[1 + ORC_REUSE_MAXK];
+    double uu[1 + ORC_REUSE_MAXK];
+    temporal_merge(c, views, vi, pixel, sidx, opt, S, r0, &in[0], h);
+    uu[0] = 0.0;
+    int n = 1;
+    const int x = pixel % vw->w, y = pixel / vw->w, R = ru->radius, side = 2 * R + 1;
+    for (int j = 0; j < ru->spatial; ++j) {
+        uint32_t ctr[4] = { (uint32_t)pixel, sc, (uint32_t)vi, (1u << 16) | (0xFFE0u + (uint32_t)j) };
+        uint32_t key[2] = { (uint32_t)opt->seed, (uint32_t)(opt->seed >> 32) };
+        uint32_t r[4];
+        orc_philox(ctr, key, r);
+        int dx = (int)(((uint64_t)r[0] * (uint64_t)side) >> 32) - R;
+        int dy = (int)(((uint64_t)r[1] * (uint64_t)side) >> 32) - R;
+        int xn = x + dx, yn = y + dy;
+        if ((dx == 0 && dy == 0) || xn < 0 || yn < 0 || xn >= vw->w || yn >= vw->h) continue;
+        int32_t pn = yn * vw->w + xn;
+        shpt Sn;
+        resv r0n;
+        uint32_t hn = 0;
+        if (!primary_vertex(c, views, vi, pn, sidx, opt, &Sn, &r0n, &hn, cnt)) continue;
+        temporal_merge(c, views, vi, pn, sidx, opt, &Sn, &r0n, &in[n], NULL);
+        uu[n] = (double)(r[2] >> 8) * (1.0 / 16777216.0);
+        ++n;
+    }
+    int sel = merge_reservoirs(c, S, opt->brdf == 1, in, uu, n, r2);
+    *h ^= ev_merge(2u, (uint32_t)sel);
+}
+
+/* neighbour offset j of a sample (test hook): 1 if it lies in the window */
+int32_t orc_reuse_offset(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t view, int32_t j, int32_t radius,
+                         int32_t *dx, int32_t *dy) {
+    if (radius < 1 || j < 0 || j >= ORC_REUSE_MAXK || !dx || !dy) return -1;
+    uint32_t ctr[4] = { pixel, sample, view, (1u << 16) | (0xFFE0u + (uint32_t)j) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t r[4];
+    orc_philox(ctr, key, r);
+    const uint64_t side = 2 * (uint64_t)radius + 1;
+    *dx = (int32_t)(((uint64_t)r[0] * side) >> 32) - radius;
+    *dy = (int32_t)(((uint64_t)r[1] * side) >> 32) - radius;
+    return 0;
+}
+
+static int reuse_on(const orc_options *opt) {
+    return opt->reuse && (opt->reuse->spatial > 0 || opt->reuse->temporal);
+}
+
 /* Path tracing with RIS next-event estimation at every surface vertex
- * (Sec. 4.1, Eq. restir; Sec. 4.2, Eq. sec_bouce).  Fills rgb, hash and the
- * path record used for differentiation. */
+ * (Sec. 4.1, Eq. restir; Sec. 4.2, Eq. sec_bouce), and with reservoir reuse
+ * at the primary vertex when enabled.  Fills rgb, hash and the path record
+ * used for differentiation (the reused sample and its weight are held fixed
+ * there like every other sampling decision).  res_out (nullable) receives the
+ * primary vertex's final reservoir (y, W, M). */
 static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int32_t pixel, int32_t sidx,
-                       const orc_options *opt, double rgb[3], uint32_t *hash, pathrec *rec, int64_t *cnt) {
+                       const orc_options *opt, double rgb[3], uint32_t *hash, pathrec *rec, int64_t *cnt,
+                       double *res_out) {
     const orc_view *vw = &views[vi];
     uint32_t S = vw->sample_offset + (uint32_t)sidx;
     int spec = opt->brdf == 1;
-    int Mb = opt->ris_m_brdf, Me = opt->ris_m - opt->ris_m_brdf;
     double u[4];
     uniforms4(opt->seed, (uint32_t)pixel, S, (uint32_t)vi, 0, 0, u);
     double o[3], d[3];
@@ -999,6 +1246,7 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
     rgb[0] = rgb[1] = rgb[2] = 0.0;
     uint32_t h = 0;
     rec->nv = 0; rec->miss_tex = -1;
+    if (res_out) for (int a = 0; a < 8; ++a) res_out[a] = 0.0;
     for (int a = 0; a < 3; ++a) rec->d[a] = d[a];
     for (int k = 1; k <= opt->bounces; ++k) {
         cnt[ORC_C_CLOSEST_RAYS]++;
@@ -1019,70 +1267,39 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
         vtx *V = &rec->v[rec->nv++];
         V->prim = hr.prim; V->b1 = hr.b1; V->b2 = hr.b2;
         V->nee = 0; V->W = 0.0; V->ytex = -1; V->q = 0.0; V->rr = 1.0;
-        /* position from barycentrics, geometric normal facing the viewer */
-        const double *v0 = c->v + 9 * (size_t)hr.prim, *v1 = v0 + 3, *v2 = v0 + 6;
-        double b0 = 1.0 - hr.b1 - hr.b2, e1[3], e2[3], ng[3];
-        for (int a = 0; a < 3; ++a) V->p[a] = b0 * v0[a] + hr.b1 * v1[a] + hr.b2 * v2[a];
-        sub3(v1, v0, e1); sub3(v2, v0, e2); cross3(e1, e2, ng); normalize3(ng);
-        if (dot3(ng, d) > 0.0) { ng[0] = -ng[0]; ng[1] = -ng[1]; ng[2] = -ng[2]; }
-        for (int a = 0; a < 3; ++a) { V->n[a] = ng[a]; V->wo[a] = -d[a]; }
-        double tf[3], bf[3];
-        orc_frame(V->n, tf, bf);
-        double m[5];
-        if (c->s.mat_mode == 2) {
-            dual md[5]; seed_t none = { PK_NONE, -1 };
-            material_field_d(c, V->p, rec->nv - 1, none, md);
-            for (int ch = 0; ch < 5; ++ch) m[ch] = md[ch].v;
-        } else {
-            interp ip; material_interp(c, hr.prim, hr.b1, hr.b2, &ip);
-            material_plain(c, &ip, m);
-        }
+        shpt Sp;
+        shading_point(c, &hr, d, rec->nv - 1, &Sp);
+        for (int a = 0; a < 3; ++a) { V->p[a] = Sp.p[a]; V->n[a] = Sp.n[a]; V->wo[a] = Sp.wo[a]; }
+        const double *m = Sp.m;
         double pn = fmax(fabs(V->p[0]), fmax(fabs(V->p[1]), fabs(V->p[2])));
         double eps = 1e-4 * fmax(1.0, pn);
         double org[3] = { V->p[0] + eps * V->n[0], V->p[1] + eps * V->n[1], V->p[2] + eps * V->n[2] };
         double co = dot3(V->n, V->wo);
-        /* --- RIS over Me env + Mb BRDF candidates, streaming WRS ---------- */
-        double wsum = 0.0, phat_y = 0.0, fy[3] = { 0, 0, 0 }, Ly[3] = { 0, 0, 0 };
-        int32_t sel = -1;
-        if (co > 0.0) {
-            for (int s = 0; s < opt->ris_m; ++s) {
-                cnt[ORC_C_CANDIDATES]++;
-                uniforms4(opt->seed, (uint32_t)pixel, S, (uint32_t)vi, (uint32_t)k, (uint32_t)s, u);
-                double w[3], qe = 0.0, qb = 0.0;
-                int32_t tex = -1;
-                int ok;
-                if (s < Me) {
-                    ok = env_sample(c, u[0], u[1], w, &qe, &tex);
-                    if (ok) qb = mix_pdf(V->n, V->wo, w, m, spec);
-                } else {
-                    int lb = mix_sample(V->n, tf, bf, V->wo, m, spec, u[0], u[1], u[2], w);
-                    ok = lb != 0;
-                    if (ok) {
-                        qb = mix_pdf(V->n, V->wo, w, m, spec);
-                        qe = env_pdf_dir(c, w);
-                        tex = env_texel_of(c, w);
-                        h ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
-                    }
-                }
-                if (!ok) continue;
-                double ci = dot3(V->n, w);
-                if (!(ci > 0.0)) continue;
-                double f[3], L[3];
-                brdf_eval_plain(V->n, V->wo, w, m, spec, f);
-                for (int ch = 0; ch < 3; ++ch) L[ch] = env_channel(c, tex, ch);
-                double phat = (L[0] * f[0] + L[1] * f[1] + L[2] * f[2]) / 3.0 * ci;
-                double den = Me * qe + Mb * qb;
-                if (!(phat > 0.0) || !(den > 0.0)) continue;
-                double ws = phat / den;
-                wsum += ws;
-                if (u[3] < ws / wsum) {
-                    sel = s; phat_y = phat; V->ytex = tex;
-                    for (int a = 0; a < 3; ++a) { V->y[a] = w[a]; fy[a] = f[a]; Ly[a] = L[a]; }
-                }
+        /* --- direct light: RIS (and reuse at the primary vertex) ---------- */
+        risres R;
+        ris_vertex(c, &Sp, opt, (uint32_t)pixel, S, (uint32_t)vi, k, &R, &h, cnt);
+        int32_t sel = R.sel;
+        double W = R.W;
+        if (k == 1 && reuse_on(opt)) {
+            resv r0, r2;
+            for (int a = 0; a < 3; ++a) r0.y[a] = R.y[a];
+            r0.W = R.W;
+            r0.M = co > 0.0 ? (double)opt->ris_m : 0.0;
+            reuse_reservoir(c, views, vi, pixel, sidx, opt, &Sp, &r0, &r2, &h, cnt);
+            if (res_out) { for (int a = 0; a < 3; ++a) res_out[a] = r2.y[a]; res_out[3] = r2.W; res_out[4] = r2.M; }
+            sel = r2.W > 0.0 ? 0 : -1;
+            W = r2.W;
+            if (sel >= 0) {
+                for (int a = 0; a < 3; ++a) R.y[a] = r2.y[a];
+                brdf_eval_plain(Sp.n, Sp.wo, R.y, Sp.m, spec, R.fy);
+                R.ytex = env_texel_of(c, R.y);
+                for (int ch = 0; ch < 3; ++ch) R.Ly[ch] = env_channel(c, R.ytex, ch);
             }
         }
         if (sel >= 0) {
-            V->W = wsum / phat_y;
+            for (int a = 0; a < 3; ++a) V->y[a] = R.y[a];
+            V->ytex = R.ytex;
+            V->W = W;
             cnt[ORC_C_SHADOW_RAYS]++;
             int occl = trace_any(c, org, V->y, 0, &cnt[ORC_C_SHADOW_NODES], &cnt[ORC_C_SHADOW_TRIS]);
             h ^= ev_nee((uint32_t)k, occl ? 0u : 1u);
@@ -1090,14 +1307,14 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
                 cnt[ORC_C_NEE_VISIBLE]++;
                 V->nee = 1;
                 double cy = dot3(V->n, V->y);
-                for (int ch = 0; ch < 3; ++ch) rgb[ch] += T[ch] * Ly[ch] * fy[ch] * cy * V->W;
+                for (int ch = 0; ch < 3; ++ch) rgb[ch] += T[ch] * R.Ly[ch] * R.fy[ch] * cy * V->W;
             }
         }
         if (k == opt->bounces) { h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 0u); break; }
         /* --- continuation (Eq. mc_indir): BRDF mixture sample ------------- */
         uniforms4(opt->seed, (uint32_t)pixel, S, (uint32_t)vi, (uint32_t)k, 0xFFFFu, u);
         double wi[3];
-        int lobe = co > 0.0 ? mix_sample(V->n, tf, bf, V->wo, m, spec, u[0], u[1], u[2], wi) : 0;
+        int lobe = co > 0.0 ? mix_sample(V->n, Sp.t, Sp.b, V->wo, m, spec, u[0], u[1], u[2], wi) : 0;
         double q = lobe ? mix_pdf(V->n, V->wo, wi, m, spec) : 0.0;
         if (!lobe || !(q > 0.0)) { h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 2u); break; }
         double f[3];
@@ -1167,6 +1384,8 @@ static int check_args(const orc_ctx *c, const orc_view *views, int32_t nviews, c
     if (!c || !views || nviews <= 0 || !opt || (n > 0 && !items)) return -1;
     if (opt->bounces < 1 || opt->bounces > ORC_MAXB || opt->ris_m < 1 || opt->ris_m_brdf < 0 ||
         opt->ris_m_brdf > opt->ris_m) return -1;
+    if (opt->reuse && (opt->reuse->spatial < 0 || opt->reuse->spatial > ORC_REUSE_MAXK || opt->reuse->radius < 1 ||
+                       opt->reuse->radius > 64 || opt->reuse->m_cap < 1)) return -1;
     for (int64_t i = 0; i < n; ++i) {
         int32_t v = items[3 * i], p = items[3 * i + 1], s = items[3 * i + 2];
         if (v < 0 || v >= nviews) return -1;
@@ -1188,7 +1407,8 @@ int32_t orc_render(const orc_ctx *c, const orc_view *views, int32_t nviews, cons
 #pragma omp for schedule(dynamic, 64)
         for (int64_t i = 0; i < n; ++i) {
             uint32_t hh;
-            trace_path(c, views, items[3 * i], items[3 * i + 1], items[3 * i + 2], opt, rgb + 3 * i, &hh, rec, cnt);
+            trace_path(c, views, items[3 * i], items[3 * i + 1], items[3 * i + 2], opt, rgb + 3 * i, &hh, rec, cnt,
+                       (opt->reuse && opt->reuse->out) ? opt->reuse->out + 8 * i : NULL);
             if (hash) hash[i] = hh;
         }
         free(rec);
@@ -1252,7 +1472,7 @@ static int32_t grad_impl(const orc_ctx *c, const orc_view *views, int32_t nviews
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = 0; i < n; ++i) {
             double rgb[3]; uint32_t hh;
-            trace_path(c, views, items[3 * i], items[3 * i + 1], items[3 * i + 2], opt, rgb, &hh, rec, cnt);
+            trace_path(c, views, items[3 * i], items[3 * i + 1], items[3 * i + 2], opt, rgb, &hh, rec, cnt, NULL);
             int np = path_params(c, rec, opt, ps, 64 * ORC_MAXB);
             memset(gfield, 0, sizeof(gfield));
             for (int j = 0; j < np; ++j) {
@@ -1301,7 +1521,7 @@ int32_t orc_frozen(const orc_ctx *rc, const orc_ctx *ec, const orc_view *views, 
     int64_t cnt[ORC_NCOUNT] = { 0 };
     pathrec *rec = (pathrec *)malloc(sizeof(pathrec));
     double tmp[3]; uint32_t hh;
-    trace_path(rc, views, item[0], item[1], item[2], opt, tmp, &hh, rec, cnt);
+    trace_path(rc, views, item[0], item[1], item[2], opt, tmp, &hh, rec, cnt, NULL);
     seed_t none = { PK_NONE, -1 };
     dual C[3];
     frozen_eval(ec, rec, opt, none, C);

@@ -91,6 +91,21 @@ typedef struct {
     uint32_t sample_offset;
 } orc_view;
 
+/* Reservoir reuse at primary vertices (Sec. 4.1 end; App. A "Spatial-
+ * temporal reuse"; the readings are listed in oracle.c).  prev / out hold
+ * one 8-float record per sample, (y.x, y.y, y.z, W, M, 0, 0, 0): prev is
+ * indexed by the global sample index (views in order, pixel-major, spp
+ * minor), out by item. */
+#define ORC_REUSE_MAXK 16
+typedef struct {
+    int32_t spatial;       /* neighbours merged, in [0, ORC_REUSE_MAXK] */
+    int32_t radius;        /* window half-size R in pixels, in [1, 64] */
+    int32_t temporal;      /* 1: merge prev of the same sample first */
+    int32_t m_cap;         /* temporal confidence cap, in multiples of ris_m (>= 1) */
+    const float *prev;     /* nullable [S][8] */
+    double  *out;          /* nullable [n][8] */
+} orc_reuse;
+
 typedef struct {
     int32_t  bounces;      /* B >= 1 surface vertices with next-event estimation */
     int32_t  ris_m;        /* M >= 1 candidates per vertex */
@@ -100,6 +115,7 @@ typedef struct {
     int32_t  brdf;         /* 0: Lambert only, 1: Lambert + GGX */
     int32_t  background;   /* 0: env radiance on primary miss, 1: black */
     int32_t  grad_mode;    /* 0: full path, 1: primary vertex only */
+    const orc_reuse *reuse; /* nullable: no reuse */
 } orc_options;
 
 enum { ORC_C_CLOSEST_RAYS = 0, ORC_C_CLOSEST_NODES, ORC_C_CLOSEST_TRIS,
@@ -161,6 +177,11 @@ int32_t orc_frozen(const orc_ctx *rec_ctx, const orc_ctx *eval_ctx,
 int32_t orc_trace(const orc_ctx *ctx, const double *o, const double *d, int64_t n,
                   int32_t any_hit, int32_t brute, int32_t *prim, double *t,
                   double *b1, double *b2);
+
+/* Reuse neighbour offset j of a sample (test hook): the Philox block
+ * (1, 0xFFE0 + j) mapped by integer arithmetic to [-R, R]^2. */
+int32_t orc_reuse_offset(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t view, int32_t j,
+                         int32_t radius, int32_t *dx, int32_t *dy);
 
 /* Environment helpers (test hooks). */
 int32_t orc_env_sample(const orc_ctx *ctx, double u0, double u1, double dir[3],

@@ -38,10 +38,15 @@ class _View(C.Structure):
                 ("spp", C.c_int32), ("sample_offset", C.c_uint32)]
 
 
+class _Reuse(C.Structure):
+    _fields_ = [("spatial", C.c_int32), ("radius", C.c_int32), ("temporal", C.c_int32), ("m_cap", C.c_int32),
+                ("prev", C.c_void_p), ("out", C.c_void_p)]
+
+
 class _Options(C.Structure):
     _fields_ = [("bounces", C.c_int32), ("ris_m", C.c_int32), ("ris_m_brdf", C.c_int32),
                 ("rr_start", C.c_int32), ("seed", C.c_uint64), ("brdf", C.c_int32),
-                ("background", C.c_int32), ("grad_mode", C.c_int32)]
+                ("background", C.c_int32), ("grad_mode", C.c_int32), ("reuse", C.c_void_p)]
 
 
 _lib = None
@@ -71,6 +76,9 @@ def lib():
         _lib.orc_field_vjp.argtypes = [C.POINTER(_Field), p, p, i64, p, p, p, p, p]
         _lib.orc_field_levels.restype = i32
         _lib.orc_field_levels.argtypes = [C.POINTER(_Field), p]
+        _lib.orc_reuse_offset.restype = i32
+        _lib.orc_reuse_offset.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, i32, i32,
+                                          C.POINTER(i32), C.POINTER(i32)]
         _lib.orc_frozen.restype = i32
         _lib.orc_frozen.argtypes = [p, p, p, i32, C.POINTER(_Options), p, p]
         _lib.orc_trace.restype = i32
@@ -106,6 +114,13 @@ def _d(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def reuse_offset(seed: int, pixel: int, sample: int, view: int, j: int, radius: int):
+    dx, dy = C.c_int32(), C.c_int32()
+    if lib().orc_reuse_offset(seed, pixel, sample, view, j, radius, C.byref(dx), C.byref(dy)) != 0:
+        raise ValueError("oracle.reuse_offset: invalid arguments")
+    return dx.value, dy.value
+
+
 def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
     c = np.asarray(ctr, np.uint32)
     k = np.asarray(key, np.uint32)
@@ -124,9 +139,19 @@ def views_struct(views) -> C.Array:
     return arr
 
 
-def options_struct(o) -> _Options:
+def reuse_struct(o, prev: Optional[np.ndarray] = None, out: Optional[np.ndarray] = None) -> Optional[_Reuse]:
+    """Reservoir-reuse settings of options `o` (None when reuse is off)."""
+    sp, tm = int(getattr(o, "reuse_spatial", 0)), int(getattr(o, "reuse_temporal", 0))
+    if sp <= 0 and not tm:
+        return None
+    return _Reuse(sp, int(getattr(o, "reuse_radius", 16)), tm, int(getattr(o, "reuse_m_cap", 20)), _ptr(prev),
+                  _ptr(out))
+
+
+def options_struct(o, reuse: Optional[_Reuse] = None) -> _Options:
     return _Options(int(o.bounces), int(o.ris_m), int(o.ris_m_brdf), int(o.rr_start), int(o.seed),
-                    int(o.brdf), int(o.background), int(o.grad_mode))
+                    int(o.brdf), int(o.background), int(o.grad_mode),
+                    C.addressof(reuse) if reuse is not None else None)
 
 
 class FieldRef:
@@ -199,7 +224,11 @@ class Oracle:
         self.close()
 
     # ---------------------------------------------------------------- render
-    def render(self, views, opts, items: np.ndarray, nthreads: int = 0, counters: bool = False):
+    def render(self, views, opts, items: np.ndarray, nthreads: int = 0, counters: bool = False,
+               prev: Optional[np.ndarray] = None, reservoirs: bool = False):
+        """Per-item radiance and decision hashes.  With reservoir reuse in
+        `opts`, prev [S, 8] is the previous frame's records by global sample
+        index, and reservoirs=True also returns each item's final record."""
         items = np.ascontiguousarray(items, np.int32).reshape(-1, 3)
         n = items.shape[0]
         rgb = np.zeros((n, 3))
@@ -207,23 +236,32 @@ class Oracle:
         cnt = np.zeros(NCOUNT, np.int64)
         nt = nthreads or os.cpu_count() or 1
         vs = views_struct(views)
-        op = options_struct(opts)
+        prev = None if prev is None else np.ascontiguousarray(prev, np.float32).reshape(-1, 8)
+        res = np.zeros((n, 8)) if reservoirs else None
+        ru = reuse_struct(opts, prev, res)
+        op = options_struct(opts, ru)
         rc = lib().orc_render(self._h, C.addressof(vs), len(views), C.byref(op), _ptr(items), n,
                               _ptr(rgb), _ptr(hsh), _ptr(cnt), nt)
         if rc != 0:
             raise ValueError("oracle.render: invalid arguments")
+        out = [rgb, hsh]
         if counters:
-            return rgb, hsh, dict(zip(COUNTER_NAMES, cnt.tolist()))
-        return rgb, hsh
+            out.append(dict(zip(COUNTER_NAMES, cnt.tolist())))
+        if reservoirs:
+            out.append(res)
+        return tuple(out)
 
-    def grad(self, views, opts, items: np.ndarray, dldc: np.ndarray, nthreads: int = 0) -> Dict[str, np.ndarray]:
+    def grad(self, views, opts, items: np.ndarray, dldc: np.ndarray, nthreads: int = 0,
+             prev: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
         items = np.ascontiguousarray(items, np.int32).reshape(-1, 3)
         dldc = _d(dldc).reshape(-1, 3)
         assert dldc.shape[0] == items.shape[0]
         sc = self.scene
         g = {"env": np.zeros(sc.env.shape)}
         vs = views_struct(views)
-        op = options_struct(opts)
+        prev = None if prev is None else np.ascontiguousarray(prev, np.float32).reshape(-1, 8)
+        ru = reuse_struct(opts, prev)
+        op = options_struct(opts, ru)
         nt = nthreads or os.cpu_count() or 1
         if sc.mat_mode == 2:
             for k, a in zip(("table", "w1", "b1", "w2", "b2"), self.field._keep):
@@ -247,11 +285,13 @@ class Oracle:
             raise ValueError("oracle.grad: invalid arguments")
         return g
 
-    def frozen(self, eval_oracle: "Oracle", views, opts, item) -> np.ndarray:
+    def frozen(self, eval_oracle: "Oracle", views, opts, item, prev: Optional[np.ndarray] = None) -> np.ndarray:
         it = np.ascontiguousarray(item, np.int32).reshape(3)
         out = np.zeros(3)
         vs = views_struct(views)
-        op = options_struct(opts)
+        prev = None if prev is None else np.ascontiguousarray(prev, np.float32).reshape(-1, 8)
+        ru = reuse_struct(opts, prev)
+        op = options_struct(opts, ru)
         rc = lib().orc_frozen(self._h, eval_oracle._h, C.addressof(vs), len(views), C.byref(op), _ptr(it),
                               _ptr(out))
         if rc != 0:

@@ -95,6 +95,10 @@ class Options:
     brdf: int = 1          # 0 Lambert, 1 Lambert + GGX
     background: int = 0    # 0 env, 1 black
     grad_mode: int = 0     # 0 full path, 1 primary vertex only
+    reuse_spatial: int = 0   # reservoir reuse at primary vertices: neighbours merged (0 = none)
+    reuse_radius: int = 16   # neighbour window half-size in pixels
+    reuse_temporal: int = 0  # 1: merge the previous frame's reservoir first
+    reuse_m_cap: int = 20    # temporal confidence cap, in multiples of ris_m
 
 
 @dataclasses.dataclass
