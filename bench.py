@@ -8,6 +8,10 @@ triangle displaced mesh with 2048^2 fp32 textures and a 512x256 HDR env
 ground-truth materials, then the adjoint replay that scatters dL/dtexel and
 dL/denv-texel.  value = path samples per second of that fwd+bwd step.
 
+--workload reuse runs the same step as a sequence of frames with spatial and
+temporal reservoir reuse at the primary vertices (5 neighbours in a 61 x 61
+pixel window, history capped at 20 M); each step's reservoirs feed the next.
+
 --workload field runs the same step with the materials from the paper's
 neural material field F_m (16-level hash grid, 2^19 slots per level,
 resolutions 16..2048, 2-layer MLP with 32 hidden units) instead of textures,
@@ -49,10 +53,11 @@ FIELD_B = 16 + 36 + 128 * 8 + 16
 FIELD_BWD_B = FIELD_B + 2 * 128 * 8
 
 
-def kernel_bytes(cnt, n, spp, tex, field=False):
+def kernel_bytes(cnt, n, spp, tex, field=False, reuse_k=0, ris_m=32):
     """Per-sample algorithmic bytes attributed to each kernel class."""
     tmat = 16 if field else (80 if tex else 60)
     per = {k: v / n for k, v in cnt.items()}
+    primary = 1.0 - per["primary_miss"]
     kb = {
         "trace_closest": NODE_B * per["closest_nodes"] + TRI_B * per["closest_tris"],
         "trace_shadow": NODE_B * per["shadow_nodes"] + TRI_B * per["shadow_tris"],
@@ -64,6 +69,12 @@ def kernel_bytes(cnt, n, spp, tex, field=False):
     if field:
         kb["field_eval"] = 2 * per["hits"] * FIELD_B          # forward pass and the adjoint's replay
         kb["field_backward"] = per["hits"] * FIELD_BWD_B
+    if reuse_k:
+        # one more camera ray per sample, the initial RIS at its primary vertex,
+        # and the merges: (2 + k) 32-byte records read, 3 written, the
+        # primary hit and material re-read per pass
+        ray = kb["trace_closest"] / max(per["closest_rays"], 1e-9)
+        kb["reuse"] = (ray + 16 + primary * (3 * (HIT_B + tmat) + ris_m * CAND_B + (2 + reuse_k) * 32 + 3 * 32))
     return kb
 
 
@@ -95,6 +106,11 @@ def make_workload(name):
     from paper_2406_16360_amd import synth
     if name == "c3":
         return synth.config3()
+    if name == "reuse":
+        w = synth.config3()
+        w.opts.reuse_spatial, w.opts.reuse_radius, w.opts.reuse_temporal, w.opts.reuse_m_cap = 5, 30, 1, 20
+        w.name = "c3_reuse_" + w.name[3:]
+        return w
     if name == "field":
         w = synth.config3()
         w.scene = synth.with_field(w.scene, np.random.default_rng(3003))
@@ -109,7 +125,8 @@ def make_workload(name):
 
 def cpu_baseline(w, seconds, nthreads):
     """The FP64 oracle on a bounded seeded subset of the same samples (render
-    + gradient), plus its traversal counters for the roofline model."""
+    + gradient), plus its traversal counters for the roofline model and the
+    number of samples they cover."""
     from oracle.oracle import Oracle
     from paper_2406_16360_amd import synth
     orc = Oracle(w.scene)
@@ -125,7 +142,15 @@ def cpu_baseline(w, seconds, nthreads):
     _, _, cnt = orc.render(w.views, w.opts, items, nthreads=nthreads, counters=True)
     orc.grad(w.views, w.opts, items, dl, nthreads=nthreads)
     dt = time.perf_counter() - t0
-    return n / dt, n, dt, cnt
+    if getattr(w.opts, "reuse_spatial", 0) or getattr(w.opts, "reuse_temporal", 0):
+        # the per-kernel byte model takes the path's own traversal counts: the
+        # oracle's reuse re-traces each neighbour's camera ray per sample
+        import copy
+        plain = copy.deepcopy(w.opts)
+        plain.reuse_spatial, plain.reuse_temporal = 0, 0
+        _, _, cnt = orc.render(w.views, plain, probe, nthreads=nthreads, counters=True)
+        return n / dt, n, dt, cnt, len(probe)
+    return n / dt, n, dt, cnt, n
 
 
 def roofline_from(prof, kb, S, steps, workload):
@@ -319,7 +344,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "bvh", "denoise", "field"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "bvh", "denoise", "field", "reuse"])
     ap.add_argument("--mode", default="fwdbwd", choices=["fwdbwd", "fwd"])
     ap.add_argument("--tape", default="on", choices=["auto", "on", "off"])
     ap.add_argument("--pool", type=int, default=0)
@@ -367,14 +392,23 @@ def main():
         gt = mirres.GpuScene(sc.pos, sc.faces, sc.env, bvh=sc.bvh, field=mirres.Field.from_synth(f2))
     else:
         gt = sc.with_params(vmat=sc.vmat.flip(0).contiguous())
-    target = mirres.render(gt, w.views, opts).clone()
+    reuse = opts.reuse_spatial > 0 or opts.reuse_temporal
+    res = [torch.zeros((w.samples, 8), device=dev), torch.zeros((w.samples, 8), device=dev)] if reuse else None
+    frame = [0]
+    target = mirres.render(gt, w.views, opts).clone() if not reuse else \
+        mirres.render(gt, w.views, opts, reservoir_out=res[1]).clone()
     grads = sc.zero_grads()
 
     def step():
+        kw = {}
+        if reuse:   # this frame's reservoirs become the next frame's history; a new seed per frame
+            frame[0] += 1
+            opts.seed = w.opts.seed + frame[0]
+            kw = dict(reservoir_prev=res[frame[0] % 2 ^ 1], reservoir_out=res[frame[0] % 2])
         if args.mode == "fwd":
-            mirres.render(sc, w.views, opts)
+            mirres.render(sc, w.views, opts, **kw)
             return
-        img, tape = mirres.render(sc, w.views, opts, keep_tape=True)
+        img, tape = mirres.render(sc, w.views, opts, keep_tape=True, **kw)
         dimg = 2.0 * (img - target)                    # d/dI of the L2 loss sum (I - I_ref)^2
         for g in grads.values():
             g.zero_()
@@ -406,7 +440,7 @@ def main():
     nsub = 0
     if not args.no_cpu_baseline:
         ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        v, nsub, dt, cnt = cpu_baseline(w, args.cpu_seconds, ncores)
+        v, nsub, dt, cnt, ncnt = cpu_baseline(w, args.cpu_seconds, ncores)
         cpu = {"value": v, "unit": "samples/s", "cores": ncores, "kind": "oracle",
                "sample": f"{nsub} seeded samples of {w.name} (render + gradient) in {dt:.1f}s"}
         if args.mode == "fwd":
@@ -414,7 +448,7 @@ def main():
     roof = None
     extra = {}
     if cnt is not None:
-        kb = kernel_bytes(cnt, nsub, w.views[0].spp, tex, field)
+        kb = kernel_bytes(cnt, ncnt, w.views[0].spp, tex, field, w.opts.reuse_spatial if reuse else 0, w.opts.ris_m)
         if args.mode == "fwd":
             kb.pop("adjoint")
             kb.pop("field_backward", None)
@@ -424,7 +458,7 @@ def main():
         roof, kern = roofline_from(prof, kb, S, args.steps, args.workload)
         extra = {"path_roofline": {"alg_bytes_per_sample": balg,
                                    "frac": value * balg / (HBM_PEAK_GBPS * 1e9),
-                                   "counts_per_sample": {k: v / nsub for k, v in cnt.items()}},
+                                   "counts_per_sample": {k: v / ncnt for k, v in cnt.items()}},
                  "kernels": kern}
     out = {"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",

@@ -156,6 +156,27 @@ typedef struct {
                                 else a multiple of 64 in [64, 256] */
     float   *debug_sample_rgb;   /* nullable device [S][3]: per-sample radiance, S = sum W*H*spp */
     uint32_t*debug_hash;         /* nullable device [S]: per-sample decision hash */
+    /* Reservoir reuse at primary vertices (Sec. 4.1 end; Appendix A
+     * "Spatial-temporal reuse"), on when reuse_spatial > 0 or
+     * reuse_temporal = 1.  Per call (one frame): each sample's initial RIS
+     * reservoir at its primary vertex is merged with the previous frame's
+     * final reservoir of the same sample (temporal; its confidence capped at
+     * reuse_m_cap * ris_m), then with the temporally merged reservoirs of
+     * reuse_spatial neighbours (same view and sample index, offsets uniform
+     * in a (2 reuse_radius + 1)^2 pixel window without the centre).  Merging
+     * weights input i at the merging vertex q by p_hat_q(y_i) W_i M_i and
+     * gives W = sum w / (sum M p_hat_q(y)).  The primary vertex is shaded
+     * with the merged sample; gradients hold it and its weight fixed.
+     * Reservoir records are 8 floats per sample (y.x, y.y, y.z, W, M, 0, 0,
+     * 0), indexed like debug_sample_rgb.  mrs_render_backward without a tape
+     * recomputes the frame's reservoirs, so reservoir_prev must hold the same
+     * records then; reservoir_out is written by mrs_render only. */
+    int32_t  reuse_spatial;      /* neighbours merged, in [0, 16] */
+    int32_t  reuse_radius;       /* window half-size in pixels, in [1, 64] */
+    int32_t  reuse_temporal;     /* 1: merge reservoir_prev first */
+    int32_t  reuse_m_cap;        /* temporal confidence cap in multiples of ris_m, >= 1 */
+    const float *reservoir_prev; /* nullable device [S][8]: the previous frame's final reservoirs */
+    float   *reservoir_out;      /* nullable device [S][8]: this frame's final reservoirs (must not alias prev) */
 } mrs_options;
 
 /* Gradient outputs (device, ACCUMULATED with +=; the caller zeroes them).

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "device.h"
+#include "reuse.h"
 #include "runtime.h"
 #include "wavefront.h"
 
@@ -53,10 +54,10 @@ namespace {
 // while a launch sequence is being captured into a graph)
 // ============================================================================
 enum KernelId { KID_ENV = 0, KID_SCHED, KID_GENERATE, KID_CLOSEST, KID_SHADE, KID_SHADOW, KID_RESOLVE, KID_ADJOINT,
-                KID_TRACE, KID_FIELD, KID_FIELD_BWD, KID_PLAN_FWD, KID_PLAN_BWD, KID_COUNT };
+                KID_TRACE, KID_FIELD, KID_FIELD_BWD, KID_REUSE, KID_PLAN_FWD, KID_PLAN_BWD, KID_COUNT };
 const char *const kKernelNames[KID_COUNT] = {"env_tables", "schedule", "generate", "trace_closest", "shade",
                                              "trace_shadow", "resolve", "adjoint", "trace_batch", "field_eval",
-                                             "field_backward", "plan_forward_graph", "plan_backward_graph"};
+                                             "field_backward", "reuse", "plan_forward_graph", "plan_backward_graph"};
 struct Profiler {
     std::mutex mu;
     bool on = false;
@@ -112,9 +113,11 @@ struct Res {
     DevBuf ct_hit, ct_y, ct_rr;                                // chunk tape (recompute mode)
     DevBuf grec;                                               // adjoint gradient records
     DevBuf fm, fvtx, gvtx;                                     // field mode: pool materials, vertex materials and gradients
+    DevBuf rprim, rfmat, rr0, rr1;                             // reuse: primary hits, their field output, reservoirs
     void release_all() {
         for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &views, &qa_o, &qa_d, &qa_t, &qb_o,
-                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec, &fm, &fvtx, &gvtx})
+                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec, &fm, &fvtx, &gvtx,
+                          &rprim, &rfmat, &rr0, &rr1})
             b->release();
     }
 };
@@ -154,8 +157,17 @@ bool field_wanted(const mrs_grads *gr) {
     return gr->field.table || gr->field.w1 || gr->field.b1 || gr->field.w2 || gr->field.b2;
 }
 
+// reservoir reuse settings of a job (all zero: no reuse)
+struct Reuse {
+    int on = 0, spatial = 0, radius = 1, temporal = 0;
+    float mcap = 0.0f;            // temporal confidence cap, m_cap * M
+    const float *prev = nullptr;  // [S][8]
+    float *out = nullptr;         // [S][8]
+};
+
 struct Job {
     FieldDev fd{};                // field mode: the field's device view
+    Reuse reuse;
     std::vector<ViewDev> vd;
     uint64_t S = 0, pixels = 0;
     SceneDev sd{};
@@ -218,6 +230,21 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
     if (op->tape_mode < MRS_TAPE_AUTO || op->tape_mode > MRS_TAPE_OFF) return fail(MRS_EINVAL, "unknown tape_mode %d", op->tape_mode);
     if (op->pool < 0) return fail(MRS_EINVAL, "pool must be >= 0");
     if (op->block != 0 && (op->block < 64 || op->block > 256 || op->block % 64)) return fail(MRS_EINVAL, "block must be 0 or a multiple of 64 in [64, 256]");
+    if (op->reuse_spatial != 0 || op->reuse_temporal != 0) {
+        if (op->reuse_spatial < 0 || op->reuse_spatial > kReuseMaxK) return fail(MRS_EINVAL, "reuse_spatial must be in [0, %d]", kReuseMaxK);
+        if (op->reuse_radius < 1 || op->reuse_radius > 64) return fail(MRS_EINVAL, "reuse_radius must be in [1, 64]");
+        if (op->reuse_temporal != 0 && op->reuse_temporal != 1) return fail(MRS_EINVAL, "reuse_temporal must be 0 or 1");
+        if (op->reuse_m_cap < 1) return fail(MRS_EINVAL, "reuse_m_cap must be >= 1");
+        job.reuse.on = 1;
+        job.reuse.spatial = op->reuse_spatial;
+        job.reuse.radius = op->reuse_radius;
+        job.reuse.temporal = op->reuse_temporal;
+        job.reuse.mcap = (float)op->reuse_m_cap * (float)op->ris_m;
+        job.reuse.prev = op->reservoir_prev;
+        job.reuse.out = op->reservoir_out;
+    } else if (op->reservoir_out) {
+        return fail(MRS_EINVAL, "reservoir_out needs reservoir reuse (reuse_spatial > 0 or reuse_temporal = 1)");
+    }
     job.vd.resize(n_views);
     uint64_t S = 0, P = 0;
     for (int i = 0; i < n_views; ++i) {
@@ -260,6 +287,9 @@ uint64_t signature(const Job &job) {
     };
     for (const ViewDev &v : job.vd) mix(&v, sizeof(ViewDev));
     mix(&job.op, sizeof(Opts));
+    const int ru[4] = {job.reuse.on, job.reuse.spatial, job.reuse.radius, job.reuse.temporal};
+    mix(ru, sizeof(ru));
+    mix(&job.reuse.mcap, sizeof(float));
     return h;
 }
 
@@ -398,6 +428,7 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
             ShadeArgs sa{job.sd, job.vt, job.op, qa, qb, r.hits.as<float4>(), ctr, it, r.so.as<float4>(),
                          r.sd.as<float4>(), r.sc.as<float4>(), r.out.as<float4>(), ch.c0, hash, tape, use_tape};
             sa.s.fm = r.fm.as<float4>();
+            if (job.reuse.on) { sa.resv = r.rr0.as<ResvRec>(); sa.resv_base = 0; }
             if (job.sd.env.H <= kEnvLdsRows) k_shade<true><<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
             else k_shade<false><<<nblocks(P, kShadeBlock), kShadeBlock, 0, s>>>(sa);
         }
@@ -410,6 +441,37 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
         std::swap(qa, qb);
     }
     HIPTRY(hipGetLastError(), "wavefront launch");
+    return MRS_OK;
+}
+
+// reservoir reuse buffers: primary hits, two record arrays (and the field's
+// output at the primary hits in field mode), one entry per sample
+mrs_status reserve_reuse(const Job &job, Res &r) {
+    if (!job.reuse.on) return MRS_OK;
+    TRY(r.rprim.reserve(sizeof(float4) * job.S));
+    TRY(r.rr0.reserve(sizeof(ResvRec) * job.S));
+    TRY(r.rr1.reserve(sizeof(ResvRec) * job.S));
+    if (job.sd.mat_mode == MRS_MAT_FIELD) TRY(r.rfmat.reserve(sizeof(float4) * job.S));
+    return MRS_OK;
+}
+
+// the final reservoirs of every primary vertex of the frame (into rr0);
+// needs the env tables of the call
+mrs_status run_reuse(const Job &job, Res &r, hipStream_t s) {
+    TRY(reserve_reuse(job, r));
+    PROF(KID_REUSE, s);
+    ReuseArgs ra{job.sd, job.vt, job.op, job.S, r.rprim.as<float4>(), r.rfmat.as<float4>(), r.rr0.as<ResvRec>(),
+                 r.rr1.as<ResvRec>(), job.reuse.prev, job.reuse.out, job.reuse.spatial, job.reuse.radius,
+                 job.reuse.temporal, job.reuse.mcap};
+    k_reuse_primary<<<nblocks(job.S, 256), 256, kLdsStackBytes * 256, s>>>(ra);
+    if (job.sd.mat_mode == MRS_MAT_FIELD) {
+        PointsPrimary src{r.rprim.as<float4>(), job.sd.tris, job.S};
+        k_field_eval<PointsPrimary><<<nblocks(job.S, kFieldTile), 64, 0, s>>>(job.fd, src, r.rfmat.as<float>());
+    }
+    k_reuse_init<<<nblocks(job.S, 256), 256, 0, s>>>(ra);
+    k_reuse_temporal<<<nblocks(job.S, 256), 256, 0, s>>>(ra);
+    k_reuse_spatial<<<nblocks(job.S, 256), 256, 0, s>>>(ra);
+    HIPTRY(hipGetLastError(), "reuse launch");
     return MRS_OK;
 }
 
@@ -522,6 +584,7 @@ mrs_status enqueue_forward(const Job &job, const std::vector<Chunk> &chunks, con
                            const mrs_tape *tape, float *image, float *dbg_rgb, uint32_t *dbg_hash, hipStream_t s) {
     Job j = job;
     TRY(env_tables(sc, j, r, s));
+    if (j.reuse.on) TRY(run_reuse(j, r, s));
     Tape tp = tape ? tape_view(tape) : Tape{};
     for (const Chunk &ch : chunks) {
         // the hash buffer is indexed from the chunk start like the output
@@ -545,6 +608,12 @@ mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, co
     if (tape) {
         TRY(adjoint(j, tape_view(tape), 0, j.S, dimg, grads, gl, rec, r, s));
     } else {
+        // the re-render needs this frame's reservoirs: the same inputs give the same ones
+        if (j.reuse.on) {
+            Job jr = j;
+            jr.reuse.out = nullptr;
+            TRY(run_reuse(jr, r, s));
+        }
         uint64_t cap = max_chunk(chunks);
         size_t n = (size_t)cap * j.op.B;
         TRY(r.ct_hit.reserve(sizeof(float4) * n));
@@ -864,6 +933,7 @@ extern "C" mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *vi
         for (const Chunk &c : *cs)
             n_iter = std::max(n_iter, iterations(job, c.c1 - c.c0, (uint32_t)std::min<uint64_t>(job.pool, c.c1 - c.c0)));
     PTRY(reserve_pool(p->res, P, outmax, n_iter, scene->mat_mode == MRS_MAT_FIELD));
+    PTRY(reserve_reuse(job, p->res));
     if (p->has_grads) {
         if (size_t words = grad_rec(scene, grads).words) PTRY(p->res.grec.reserve(4 * words));
         if (scene->mat_mode == MRS_MAT_FIELD) PTRY(reserve_field_vertices(job, job.S, p->res));

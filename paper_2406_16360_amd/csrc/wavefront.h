@@ -413,12 +413,87 @@ __global__ __launch_bounds__(256) void k_trace_closest(TraceArgs a) {
         });
 }
 
+// ---------------------------------------------------------------------------
+// RIS at a surface vertex (Sec. 4.1, Eq. restir): Me = M - Mb env candidates
+// and Mb BRDF-mixture candidates, candidate s from Philox block (k, s),
+// balance-heuristic weights p_hat / (Me q_env + Mb q_brdf), streaming
+// weighted reservoir (App. A "Spatial-temporal reuse").
+// ---------------------------------------------------------------------------
+struct RisOut {
+    float wsum, phat, cos_y, W;   // W < 0: take wsum / phat
+    V3 y, fy, Ly;
+    int sel, ytex;
+    uint32_t hev;                 // decision-hash events of the BRDF candidates (or of the reuse)
+};
+
+template <class MV>
+__device__ __forceinline__ void ris_select(const EnvTables &env, const MV &marg, const Rng &rng, int k, int M, int Mb,
+                                           const Lobe &L, const Frame &F, bool front, bool want_hash, RisOut &o) {
+    const int Me = M - Mb;
+    o.hev = 0;
+    o.wsum = 0.0f; o.phat = 0.0f; o.cos_y = 0.0f; o.W = -1.0f;
+    o.y = V3{0, 0, 0}; o.fy = V3{0, 0, 0}; o.Ly = V3{0, 0, 0};
+    o.sel = -1; o.ytex = -1;
+    if (!front) return;
+    for (int s = 0; s < M; ++s) {
+        float4 u = rng.draw((uint32_t)k, (uint32_t)s);
+        V3 dir, wl;
+        int tex;
+        float4 lp;
+        float qe, qb;
+        if (s < Me) {
+            if (!env_sample(env, marg, u.x, u.y, dir, tex, lp, qe)) continue;
+            wl = to_local(F, dir);
+        } else {
+            int lb = mix_sample(L, u.x, u.y, u.z, wl);
+            if (!lb) continue;
+            dir = to_world(F, wl);
+            tex = env_texel_of(env, dir);
+            if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
+            lp = env.lp[tex];
+            qe = env_pdf_dir(env, dir, tex, lp);
+        }
+        if (!(wl.z > 0.0f)) continue;
+        V3 f = brdf_eval_pdf(L, wl, qb);
+        float phat = (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
+        float den = (float)Me * qe + (float)Mb * qb;
+        if (!(phat > 0.0f) || !(den > 0.0f)) continue;
+        float w = phat / den;
+        o.wsum += w;
+        if (u.w < w / o.wsum) {
+            o.sel = s; o.y = dir; o.fy = f; o.Ly = V3{lp.x, lp.y, lp.z}; o.phat = phat; o.ytex = tex; o.cos_y = wl.z;
+        }
+    }
+}
+
+// A reservoir record: (y, W) and (M, decision-hash events of its own
+// sample, -, -).  M = 0: no reservoir (primary miss or back-facing).
+struct ResvRec { float4 yw; float4 mh; };
+
+// the primary vertex's reused sample as an RIS result (sel 0, or -1 if empty)
+__device__ __forceinline__ void reused_sample(const EnvTables &env, const Lobe &L, const Frame &F, const ResvRec &r,
+                                              RisOut &o) {
+    o.hev = __float_as_uint(r.mh.y);
+    o.wsum = 0.0f; o.phat = 0.0f; o.cos_y = 0.0f; o.W = 0.0f;
+    o.y = V3{0, 0, 0}; o.fy = V3{0, 0, 0}; o.Ly = V3{0, 0, 0};
+    o.sel = -1; o.ytex = -1;
+    if (!(r.yw.w > 0.0f)) return;
+    const V3 y = xyz(r.yw);
+    const V3 wl = to_local(F, y);
+    if (!(wl.z > 0.0f)) return;
+    const int tex = env_texel_of(env, y);
+    const float4 lp = env.lp[tex];
+    o.sel = 0; o.y = y; o.fy = brdf_eval(L, wl); o.Ly = V3{lp.x, lp.y, lp.z};
+    o.ytex = tex; o.cos_y = wl.z; o.W = r.yw.w;
+}
+
 struct ShadeArgs {
     SceneDev s; ViewTable vt; Opts op;
     Queue q, qn; float4 *hits; IterCtr *ctr; int it;
     float4 *so, *sd, *sc;          // shadow queue: origin (w = sample), dir (w = k), contribution
     float4 *out; uint64_t out_base; uint32_t *hash;
     Tape tape; int use_tape;
+    const ResvRec *resv; uint64_t resv_base;   // reuse: final reservoirs of the primary vertices (null: plain RIS)
 };
 
 constexpr int kShadeBlock = 256;
@@ -506,46 +581,18 @@ __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS
             V3 wo = to_local(S.F, d * -1.0f);
             Lobe L = make_lobe(m, wo, a.op.spec);
             V3 org = spawn(S.p, S.n);
-            const int Me = a.op.M - a.op.Mb, Mb = a.op.Mb;
-            // ---- RIS over Me env + Mb BRDF candidates, streaming WRS ----
-            uint32_t hcand = 0;   // hash events of the BRDF candidates
-            float wsum = 0.0f, phat_y = 0.0f, cos_y = 0.0f;
-            V3 y = V3{0, 0, 0}, fy = V3{0, 0, 0}, Ly = V3{0, 0, 0};
-            int sel = -1, ytex = -1;
-            if (wo.z > 0.0f) {
-                for (int s = 0; s < a.op.M; ++s) {
-                    float4 u = rng.draw((uint32_t)k, (uint32_t)s);
-                    V3 dir, wl;
-                    int tex;
-                    float4 lp;
-                    float qe, qb;
-                    if (s < Me) {
-                        if (!env_sample(a.s.env, marg, u.x, u.y, dir, tex, lp, qe)) continue;
-                        wl = to_local(S.F, dir);
-                    } else {
-                        int lb = mix_sample(L, u.x, u.y, u.z, wl);
-                        if (!lb) continue;
-                        dir = to_world(S.F, wl);
-                        tex = env_texel_of(a.s.env, dir);
-                        if (a.hash) hcand ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
-                        lp = a.s.env.lp[tex];
-                        qe = env_pdf_dir(a.s.env, dir, tex, lp);
-                    }
-                    if (!(wl.z > 0.0f)) continue;
-                    V3 f = brdf_eval_pdf(L, wl, qb);
-                    float phat = (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
-                    float den = (float)Me * qe + (float)Mb * qb;
-                    if (!(phat > 0.0f) || !(den > 0.0f)) continue;
-                    float w = phat / den;
-                    wsum += w;
-                    if (u.w < w / wsum) {
-                        sel = s; y = dir; fy = f; Ly = V3{lp.x, lp.y, lp.z}; phat_y = phat; ytex = tex; cos_y = wl.z;
-                    }
-                }
-            }
+            // ---- RIS over Me env + Mb BRDF candidates, streaming WRS, or the
+            // reused reservoir at the primary vertex ----
+            RisOut ro;
+            if (a.resv && k == 1) reused_sample(a.s.env, L, S.F, a.resv[g - a.resv_base], ro);
+            else ris_select(a.s.env, marg, rng, k, a.op.M, a.op.Mb, L, S.F, wo.z > 0.0f, a.hash != nullptr, ro);
+            const uint32_t hcand = ro.hev;
+            const float wsum = ro.wsum, phat_y = ro.phat, cos_y = ro.cos_y;
+            const V3 y = ro.y, fy = ro.fy, Ly = ro.Ly;
+            const int sel = ro.sel, ytex = ro.ytex;
             float Wy = 0.0f;
             if (sel >= 0) {
-                Wy = wsum / phat_y;
+                Wy = ro.W >= 0.0f ? ro.W : wsum / phat_y;
                 emit = true;
                 V3 cc = T * Ly * fy * (cos_y * Wy);
                 e_o = make_float4(org.x, org.y, org.z, __uint_as_float(g));

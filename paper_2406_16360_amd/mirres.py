@@ -61,7 +61,9 @@ class _Options(C.Structure):
     _fields_ = [("bounces", C.c_int32), ("ris_m", C.c_int32), ("ris_m_brdf", C.c_int32), ("rr_start", C.c_int32),
                 ("seed", C.c_uint64), ("brdf", C.c_int32), ("background", C.c_int32), ("grad_mode", C.c_int32),
                 ("tape_mode", C.c_int32), ("tape_budget", C.c_int64), ("pool", C.c_int32), ("block", C.c_int32),
-                ("debug_sample_rgb", C.c_void_p), ("debug_hash", C.c_void_p)]
+                ("debug_sample_rgb", C.c_void_p), ("debug_hash", C.c_void_p), ("reuse_spatial", C.c_int32),
+                ("reuse_radius", C.c_int32), ("reuse_temporal", C.c_int32), ("reuse_m_cap", C.c_int32),
+                ("reservoir_prev", C.c_void_p), ("reservoir_out", C.c_void_p)]
 
 
 class _Grads(C.Structure):
@@ -192,6 +194,10 @@ class RenderOptions:
     tape_budget: int = 0
     pool: int = 0
     block: int = 0
+    reuse_spatial: int = 0
+    reuse_radius: int = 16
+    reuse_temporal: int = 0
+    reuse_m_cap: int = 20
 
     @classmethod
     def from_any(cls, o) -> "RenderOptions":
@@ -200,10 +206,11 @@ class RenderOptions:
         names = [f.name for f in dataclasses.fields(cls)]
         return cls(**{n: getattr(o, n) for n in names if hasattr(o, n)})
 
-    def struct(self, debug_rgb=None, debug_hash=None) -> _Options:
+    def struct(self, debug_rgb=None, debug_hash=None, reservoir_prev=None, reservoir_out=None) -> _Options:
         return _Options(self.bounces, self.ris_m, self.ris_m_brdf, self.rr_start, self.seed & (2 ** 64 - 1), self.brdf,
                         self.background, self.grad_mode, self.tape_mode, self.tape_budget, self.pool, self.block,
-                        _ptr(debug_rgb), _ptr(debug_hash))
+                        _ptr(debug_rgb), _ptr(debug_hash), self.reuse_spatial, self.reuse_radius,
+                        self.reuse_temporal, self.reuse_m_cap, _ptr(reservoir_prev), _ptr(reservoir_out))
 
 
 class Bvh:
@@ -412,9 +419,12 @@ def total_samples(views: Sequence) -> int:
 
 
 def render(scene: GpuScene, views: Sequence, opts, keep_tape: bool = False, debug: bool = False,
-           out: Optional[torch.Tensor] = None, stream=None):
+           out: Optional[torch.Tensor] = None, stream=None, reservoir_prev: Optional[torch.Tensor] = None,
+           reservoir_out: Optional[torch.Tensor] = None):
     """Renders packed images [sum W*H, 3].  With keep_tape returns (image,
-    tape or None); with debug also per-sample radiance and decision hashes."""
+    tape or None); with debug also per-sample radiance and decision hashes.
+    With reservoir reuse in opts, reservoir_prev / reservoir_out [S, 8] are
+    the previous and this frame's final primary-vertex reservoirs."""
     o = RenderOptions.from_any(opts)
     vs, npix, _ = views_struct(views)
     dev = scene.pos.device
@@ -424,7 +434,7 @@ def render(scene: GpuScene, views: Sequence, opts, keep_tape: bool = False, debu
         S = total_samples(views)
         dbg_rgb = torch.empty((S, 3), dtype=torch.float32, device=dev)
         dbg_hash = torch.empty((S,), dtype=torch.int32, device=dev)
-    op = o.struct(dbg_rgb, dbg_hash)
+    op = o.struct(dbg_rgb, dbg_hash, reservoir_prev, reservoir_out)
     sc = scene.struct()
     th = C.c_void_p()
     _check(_lib.mrs_render(C.byref(sc), C.addressof(vs), len(views), C.byref(op), img.data_ptr(),
@@ -439,16 +449,18 @@ def render(scene: GpuScene, views: Sequence, opts, keep_tape: bool = False, debu
 
 
 def render_backward(scene: GpuScene, views: Sequence, opts, grad_image: torch.Tensor, tape: Optional[Tape] = None,
-                    grads: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
+                    grads: Optional[Dict[str, torch.Tensor]] = None, stream=None,
+                    reservoir_prev: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
     """Accumulates d(sum grad_image . image)/d(materials, env) into `grads`
-    (allocated zero if None) and returns it."""
+    (allocated zero if None) and returns it.  With reservoir reuse and no
+    tape, reservoir_prev must be the one the forward call used."""
     o = RenderOptions.from_any(opts)
     vs, npix, _ = views_struct(views)
     gi = _dev(grad_image).reshape(npix, 3)
     if grads is None:
         grads = scene.zero_grads()
     g = _grads_struct(grads)
-    op = o.struct()
+    op = o.struct(reservoir_prev=reservoir_prev)
     sc = scene.struct()
     _check(_lib.mrs_render_backward(C.byref(sc), C.addressof(vs), len(views), C.byref(op), gi.data_ptr(),
                                     C.byref(g), tape.handle if tape is not None else None, _stream(stream)))
@@ -470,7 +482,8 @@ class Plan:
     their contents in place between passes (never rebind them)."""
 
     def __init__(self, scene: GpuScene, views: Sequence, opts, with_grad: bool = False, use_graph: bool = True,
-                 debug: bool = False):
+                 debug: bool = False, reservoir_prev: Optional[torch.Tensor] = None,
+                 reservoir_out: Optional[torch.Tensor] = None):
         self.scene, self.views = scene, list(views)
         self.opts = RenderOptions.from_any(opts)
         vs, npix, self.offsets = views_struct(self.views)
@@ -488,7 +501,8 @@ class Plan:
             self.grad_image = torch.zeros_like(self.image)
             self.grads = scene.zero_grads()
             g = _grads_struct(self.grads)
-        op = self.opts.struct(self.dbg_rgb, self.dbg_hash)
+        self.reservoir_prev, self.reservoir_out = reservoir_prev, reservoir_out   # bound: keep them alive
+        op = self.opts.struct(self.dbg_rgb, self.dbg_hash, reservoir_prev, reservoir_out)
         sc = scene.struct()
         h = C.c_void_p()
         _check(_lib.mrs_plan_create(C.byref(sc), C.addressof(vs), len(self.views), C.byref(op),
