@@ -181,3 +181,24 @@ def test_reuse_rejects_bad_options(mr):
             mr.render(sc, w.views, o)
     with pytest.raises(mr.MirresError):        # an output without reuse
         mr.render(sc, w.views, w.opts, reservoir_out=torch.zeros((w.samples, 8), device="cuda"))
+
+
+def test_reuse_plan_graph_matches_eager(mr):
+    """A graph-replayed plan with reuse gives the eager frames bit for bit;
+    between frames this frame's reservoirs are copied into the bound history."""
+    w = synth.config1()
+    w.opts.reuse_spatial, w.opts.reuse_radius, w.opts.reuse_temporal = 4, 6, 1
+    sc = mr.GpuScene.from_synth(w.scene)
+    prev = torch.zeros((w.samples, 8), device="cuda")
+    out = torch.zeros_like(prev)
+    plan = mr.Plan(sc, w.views, w.opts, use_graph=True, reservoir_prev=prev, reservoir_out=out)
+    e_prev = torch.zeros_like(prev)
+    for frame in range(3):
+        img = plan.forward().clone()
+        e_out = torch.zeros_like(prev)
+        e_img = mr.render(sc, w.views, w.opts, reservoir_prev=e_prev, reservoir_out=e_out)
+        torch.cuda.synchronize()
+        assert torch.equal(img, e_img), frame
+        assert torch.equal(out, e_out), frame
+        prev.copy_(out)
+        e_prev = e_out
