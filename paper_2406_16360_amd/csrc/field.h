@@ -204,6 +204,7 @@ struct PointsArray {
     const float *x;
     uint64_t n;
     __device__ __forceinline__ uint64_t count() const { return n; }
+    __device__ __forceinline__ uint64_t gindex(uint64_t i) const { return i; }
     __device__ __forceinline__ bool get(uint64_t i, V3 &p) const {
         if (i >= n) return false;
         p = V3{x[3 * i], x[3 * i + 1], x[3 * i + 2]};
@@ -239,6 +240,48 @@ __global__ __launch_bounds__(64) void k_field_eval(FieldDev f, Src src, float *_
 }
 
 struct FieldGrads { float *table, *w1, *b1, *w2, *b2; };
+
+// 30-bit Morton code of u in [0, 1]^3 (10 bits per axis)
+__device__ __forceinline__ uint32_t morton_spread10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Sort keys of the pull-back's points: the Morton code of the point in the
+// field's box for points that carry a gradient, all ones for the others
+// (they sort last and are skipped).  Walking the points in this order makes
+// a tile's 32 points a compact cluster, so its table atomics aggregate and
+// share cache lines also for the spatially random bounce vertices.
+template <class Src>
+__global__ __launch_bounds__(256) void k_field_keys(FieldDev f, Src src, const float *__restrict__ g,
+                                                    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= src.count()) return;
+    uint32_t key = 0xFFFFFFFFu;
+    V3 x;
+    if ((g[4 * i] != 0.0f || g[4 * i + 1] != 0.0f || g[4 * i + 2] != 0.0f || g[4 * i + 3] != 0.0f) && src.get(i, x)) {
+        double u[3];
+        field_unit(f, x, u);
+        const uint32_t q0 = (uint32_t)min(1023.0, u[0] * 1024.0), q1 = (uint32_t)min(1023.0, u[1] * 1024.0),
+                       q2 = (uint32_t)min(1023.0, u[2] * 1024.0);
+        key = morton_spread10(q0) | (morton_spread10(q1) << 1) | (morton_spread10(q2) << 2);
+    }
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+}
+
+// the points of Src in the order of a permutation (from the key sort)
+template <class Src>
+struct PointsPerm {
+    Src base; const uint32_t *perm;
+    __host__ __device__ __forceinline__ uint64_t count() const { return base.count(); }
+    __device__ __forceinline__ uint64_t gindex(uint64_t i) const { return perm[i]; }
+    __device__ __forceinline__ bool get(uint64_t i, V3 &p) const { return i < count() && base.get(perm[i], p); }
+};
 
 // Table scatter of one level per half-wave: each pending lane adds w_k d_j
 // into feature j of the slot of corner k (16 values).  Device-scope float
@@ -329,8 +372,9 @@ void k_field_backward(FieldDev f, Src src, const float *__restrict__ g, FieldGra
         bool valid = src.get(i, x);
         float gi[kFieldOut] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (valid) {
+            const uint64_t ig = src.gindex(i);
 #pragma unroll
-            for (int o = 0; o < kFieldOut; ++o) gi[o] = g[4 * i + o];
+            for (int o = 0; o < kFieldOut; ++o) gi[o] = g[4 * ig + o];
             valid = gi[0] != 0.0f || gi[1] != 0.0f || gi[2] != 0.0f || gi[3] != 0.0f;
         }
         double u[3];

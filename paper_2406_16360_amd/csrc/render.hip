@@ -114,10 +114,11 @@ struct Res {
     DevBuf grec;                                               // adjoint gradient records
     DevBuf fm, fvtx, gvtx;                                     // field mode: pool materials, vertex materials and gradients
     DevBuf rprim, rfmat, rr0, rr1;                             // reuse: primary hits, their field output, reservoirs
+    DevBuf fkey, fkey2, fval, fval2, fsort;                    // field mode: pull-back order (keys, values, sort scratch)
     void release_all() {
         for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &views, &qa_o, &qa_d, &qa_t, &qb_o,
                           &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec, &fm, &fvtx, &gvtx,
-                          &rprim, &rfmat, &rr0, &rr1})
+                          &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort})
             b->release();
     }
 };
@@ -463,14 +464,7 @@ mrs_status run_reuse(const Job &job, Res &r, hipStream_t s) {
     ReuseArgs ra{job.sd, job.vt, job.op, job.S, r.rprim.as<float4>(), r.rfmat.as<float4>(), r.rr0.as<ResvRec>(),
                  r.rr1.as<ResvRec>(), job.reuse.prev, job.reuse.out, job.reuse.spatial, job.reuse.radius,
                  job.reuse.temporal, job.reuse.mcap};
-    k_reuse_primary<<<nblocks(job.S, 256), 256, kLdsStackBytes * 256, s>>>(ra);
-    if (job.sd.mat_mode == MRS_MAT_FIELD) {
-        PointsPrimary src{r.rprim.as<float4>(), job.sd.tris, job.S};
-        k_field_eval<PointsPrimary><<<nblocks(job.S, kFieldTile), 64, 0, s>>>(job.fd, src, r.rfmat.as<float>());
-    }
-    k_reuse_init<<<nblocks(job.S, 256), 256, 0, s>>>(ra);
-    k_reuse_temporal<<<nblocks(job.S, 256), 256, 0, s>>>(ra);
-    k_reuse_spatial<<<nblocks(job.S, 256), 256, 0, s>>>(ra);
+    launch_reuse(ra, job.fd, r.rfmat.as<float>(), s);
     HIPTRY(hipGetLastError(), "reuse launch");
     return MRS_OK;
 }
@@ -489,6 +483,8 @@ mrs_status reserve_field_vertices(const Job &job, uint64_t samples, Res &r) {
     size_t n = (size_t)std::min<uint64_t>(kAdjChunk, samples) * job.op.B;
     TRY(r.fvtx.reserve(sizeof(float4) * n));
     TRY(r.gvtx.reserve(sizeof(float4) * n));
+    for (DevBuf *b : {&r.fkey, &r.fkey2, &r.fval, &r.fval2}) TRY(b->reserve(sizeof(uint32_t) * n));
+    TRY(r.fsort.reserve(std::max<size_t>(sort_pairs_tmp_bytes(n), 16)));
     return MRS_OK;
 }
 
@@ -519,9 +515,17 @@ mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, con
         }
         if (field) {
             PROF(KID_FIELD_BWD, s);
+            // the vertices with a gradient in Morton order of their position, then the pull-back in that order
             PointsTape src{tp, job.sd.tris, a0, n, kgrad};
-            const uint64_t tiles = (src.count() + kFieldTile - 1) / kFieldTile;
-            k_field_backward<PointsTape><<<field_backward_blocks(tiles), 64, 0, s>>>(job.fd, src, r.gvtx.as<float>(), fg);
+            const uint64_t cnt = src.count();
+            k_field_keys<PointsTape><<<nblocks(cnt, 256), 256, 0, s>>>(job.fd, src, r.gvtx.as<float>(),
+                                                                       r.fkey.as<uint32_t>(), r.fval.as<uint32_t>());
+            TRY(sort_pairs_u32(r.fkey.as<uint32_t>(), r.fkey2.as<uint32_t>(), r.fval.as<uint32_t>(),
+                               r.fval2.as<uint32_t>(), cnt, r.fsort, s));
+            PointsPerm<PointsTape> ps{src, r.fval2.as<uint32_t>()};
+            const uint64_t tiles = (cnt + kFieldTile - 1) / kFieldTile;
+            k_field_backward<PointsPerm<PointsTape>><<<field_backward_blocks(tiles), 64, 0, s>>>(job.fd, ps,
+                                                                                                 r.gvtx.as<float>(), fg);
         }
     }
     HIPTRY(hipGetLastError(), "adjoint launch");

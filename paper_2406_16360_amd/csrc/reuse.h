@@ -112,7 +112,19 @@ __global__ void k_reuse_primary(ReuseArgs a) {
     a.prim[g] = make_float4(h.b1, h.b2, __int_as_float(h.leaf >= 0 ? h.leaf : -1), 0.0f);
 }
 
+// kMargLds: the env's marginal intervals and guide go to LDS first, as in
+// shading (H <= kEnvLdsRows), so an env candidate's row search reads LDS
+template <bool kMargLds>
 __global__ __launch_bounds__(256) void k_reuse_init(ReuseArgs a) {
+    __shared__ double2 s_mpair[kMargLds ? kEnvLdsRows : 1];
+    __shared__ int32_t s_gmarg[kMargLds ? kEnvLdsRows : 1];
+    if (kMargLds) {
+        for (int t = threadIdx.x; t < a.s.env.H; t += blockDim.x) {
+            s_mpair[t] = a.s.env.mpair[t];
+            s_gmarg[t] = a.s.env.gmarg[t];
+        }
+        __syncthreads();
+    }
     const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (g >= a.S) return;
     PrimVtx v;
@@ -120,7 +132,7 @@ __global__ __launch_bounds__(256) void k_reuse_init(ReuseArgs a) {
     r.yw = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     r.mh = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (prim_vertex(a, g, v)) {
-        const MargView marg{a.s.env.mpair, a.s.env.gmarg};
+        const MargView marg = kMargLds ? MargView{s_mpair, s_gmarg} : MargView{a.s.env.mpair, a.s.env.gmarg};
         const bool front = v.wo.z > 0.0f;
         RisOut ro;
         ris_select(a.s.env, marg, v.rng, 1, a.op.M, a.op.Mb, v.L, v.S.F, front, true, ro);
@@ -189,6 +201,7 @@ __global__ __launch_bounds__(256) void k_reuse_spatial(ReuseArgs a) {
 struct PointsPrimary {
     const float4 *prim; const TriRec *tris; uint64_t n;
     __host__ __device__ __forceinline__ uint64_t count() const { return n; }
+    __device__ __forceinline__ uint64_t gindex(uint64_t i) const { return i; }
     __device__ __forceinline__ bool get(uint64_t i, V3 &p) const {
         if (i >= n) return false;
         const float4 h = prim[i];
@@ -198,6 +211,21 @@ struct PointsPrimary {
         return true;
     }
 };
+
+// host: the reuse passes of one frame on stream s (fmat: the field pass's
+// output buffer in field mode)
+inline void launch_reuse(const ReuseArgs &ra, const FieldDev &fd, float *fmat, hipStream_t s) {
+    const unsigned nb = (unsigned)((ra.S + 255) / 256);
+    k_reuse_primary<<<nb, 256, kLdsStackBytes * 256, s>>>(ra);
+    if (ra.s.mat_mode == MRS_MAT_FIELD) {
+        PointsPrimary src{ra.prim, ra.s.tris, ra.S};
+        k_field_eval<PointsPrimary><<<(unsigned)((ra.S + kFieldTile - 1) / kFieldTile), 64, 0, s>>>(fd, src, fmat);
+    }
+    if (ra.s.env.H <= kEnvLdsRows) k_reuse_init<true><<<nb, 256, 0, s>>>(ra);
+    else k_reuse_init<false><<<nb, 256, 0, s>>>(ra);
+    k_reuse_temporal<<<nb, 256, 0, s>>>(ra);
+    k_reuse_spatial<<<nb, 256, 0, s>>>(ra);
+}
 
 }  // namespace
 }  // namespace mrs

@@ -195,6 +195,7 @@ __device__ __forceinline__ V3 hit_point(const TriRec *__restrict__ tris, int lea
 struct PointsHits {
     const float4 *hits; const TriRec *tris; const IterCtr *ctr; int it;
     __device__ __forceinline__ uint64_t count() const { return ctr[it].n_live; }
+    __device__ __forceinline__ uint64_t gindex(uint64_t i) const { return i; }
     __device__ __forceinline__ bool get(uint64_t i, V3 &p) const {
         if (i >= count()) return false;
         const float4 h = hits[i];
@@ -208,6 +209,7 @@ struct PointsHits {
 struct PointsTape {
     Tape tape; const TriRec *tris; uint64_t g0, n; int kmax;
     __host__ __device__ __forceinline__ uint64_t count() const { return (uint64_t)kmax * n; }
+    __device__ __forceinline__ uint64_t gindex(uint64_t i) const { return i; }
     __device__ __forceinline__ bool get(uint64_t i, V3 &p) const {
         if (i >= count()) return false;
         const int k = (int)(i / n) + 1;
