@@ -115,10 +115,11 @@ struct Res {
     DevBuf fm, fvtx, gvtx;                                     // field mode: pool materials, vertex materials and gradients
     DevBuf rprim, rfmat, rr0, rr1;                             // reuse: primary hits, their field output, reservoirs
     DevBuf fkey, fkey2, fval, fval2, fsort;                    // field mode: pull-back order (keys, values, sort scratch)
+    DevBuf tpack;                                              // texture mode: interleaved texel records
     void release_all() {
         for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &views, &qa_o, &qa_d, &qa_t, &qb_o,
                           &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec, &fm, &fvtx, &gvtx,
-                          &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort})
+                          &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort, &tpack})
             b->release();
     }
 };
@@ -364,6 +365,20 @@ mrs_status reserve_pool(Res &r, uint32_t P, uint64_t out_samples, int n_iter, bo
     return MRS_OK;
 }
 
+// texture mode: the texel records the material fetch reads, packed per call
+mrs_status reserve_tpack(const mrs_scene *sc, Res &r) {
+    if (sc->mat_mode != MRS_MAT_TEXTURE) return MRS_OK;
+    return r.tpack.reserve(2 * sizeof(float4) * (size_t)sc->tw * (size_t)sc->th);
+}
+mrs_status pack_texels(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
+    if (sc->mat_mode != MRS_MAT_TEXTURE) return MRS_OK;
+    TRY(reserve_tpack(sc, r));
+    const uint64_t n = (uint64_t)sc->tw * (uint64_t)sc->th;
+    k_pack_texels<<<nblocks(n, 256), 256, 0, s>>>(sc->albedo, sc->rough, sc->metal, n, r.tpack.as<float4>());
+    job.sd.tpack = r.tpack.as<float4>();
+    return MRS_OK;
+}
+
 // env tables: kernels only (the validity flag stays on the device), so the
 // sequence can be captured in a graph
 mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
@@ -588,6 +603,7 @@ mrs_status enqueue_forward(const Job &job, const std::vector<Chunk> &chunks, con
                            const mrs_tape *tape, float *image, float *dbg_rgb, uint32_t *dbg_hash, hipStream_t s) {
     Job j = job;
     TRY(env_tables(sc, j, r, s));
+    TRY(pack_texels(sc, j, r, s));
     if (j.reuse.on) TRY(run_reuse(j, r, s));
     Tape tp = tape ? tape_view(tape) : Tape{};
     for (const Chunk &ch : chunks) {
@@ -604,6 +620,7 @@ mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, co
                             const mrs_tape *tape, const float *dimg, const mrs_grads *grads, hipStream_t s) {
     Job j = job;
     TRY(env_tables(sc, j, r, s));
+    TRY(pack_texels(sc, j, r, s));
     const GradRec gl = grad_rec(sc, grads);
     if (gl.words) TRY(r.grec.reserve(4 * gl.words));
     if (sc->mat_mode == MRS_MAT_FIELD) TRY(reserve_field_vertices(j, j.S, r));
@@ -938,6 +955,7 @@ extern "C" mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *vi
             n_iter = std::max(n_iter, iterations(job, c.c1 - c.c0, (uint32_t)std::min<uint64_t>(job.pool, c.c1 - c.c0)));
     PTRY(reserve_pool(p->res, P, outmax, n_iter, scene->mat_mode == MRS_MAT_FIELD));
     PTRY(reserve_reuse(job, p->res));
+    PTRY(reserve_tpack(scene, p->res));
     if (p->has_grads) {
         if (size_t words = grad_rec(scene, grads).words) PTRY(p->res.grec.reserve(4 * words));
         if (scene->mat_mode == MRS_MAT_FIELD) PTRY(reserve_field_vertices(job, job.S, p->res));

@@ -49,6 +49,7 @@ struct SceneDev {
     const int32_t *faces;
     const float *uv, *vmat, *albedo, *rough, *metal;
     const float4 *fm;   // field mode: materials from the field pass (per pool entry in shade, per vertex in the adjoint)
+    const float4 *tpack; // texture mode: per texel (albedo rgb, roughness), (metallic, -, -, -), packed per call
     int mat_mode, tw, th;
     const BvhNode *nodes;
     const TriRec *tris;
@@ -156,6 +157,18 @@ __device__ __forceinline__ MatRaw fetch_material(const SceneDev &s, int prim, fl
     ip.idx[1] = j0 * s.tw + i1; ip.w[1] = fx * (1.0f - fy);
     ip.idx[2] = j1 * s.tw + i0; ip.w[2] = (1.0f - fx) * fy;
     ip.idx[3] = j1 * s.tw + i1; ip.w[3] = fx * fy;
+    if (s.tpack) {
+        // two 16-byte loads per texel from its 32-byte record instead of five scattered ones
+        const float4 t0 = s.tpack[2 * (size_t)ip.idx[0]], t1 = s.tpack[2 * (size_t)ip.idx[1]];
+        const float4 t2 = s.tpack[2 * (size_t)ip.idx[2]], t3 = s.tpack[2 * (size_t)ip.idx[3]];
+        const float m0 = s.tpack[2 * (size_t)ip.idx[0] + 1].x, m1 = s.tpack[2 * (size_t)ip.idx[1] + 1].x;
+        const float m2 = s.tpack[2 * (size_t)ip.idx[2] + 1].x, m3 = s.tpack[2 * (size_t)ip.idx[3] + 1].x;
+        m.a = V3{bilerp(t0.x, t1.x, t2.x, t3.x, fx, fy), bilerp(t0.y, t1.y, t2.y, t3.y, fx, fy),
+                 bilerp(t0.z, t1.z, t2.z, t3.z, fx, fy)};
+        m.r = bilerp(t0.w, t1.w, t2.w, t3.w, fx, fy);
+        m.mu = bilerp(m0, m1, m2, m3, fx, fy);
+        return m;
+    }
     const float *a0 = s.albedo + 3 * (size_t)ip.idx[0], *a1 = s.albedo + 3 * (size_t)ip.idx[1];
     const float *a2 = s.albedo + 3 * (size_t)ip.idx[2], *a3 = s.albedo + 3 * (size_t)ip.idx[3];
     m.a = V3{bilerp(a0[0], a1[0], a2[0], a3[0], fx, fy), bilerp(a0[1], a1[1], a2[1], a3[1], fx, fy),
@@ -265,6 +278,16 @@ __device__ __forceinline__ uint32_t ev_miss(uint32_t k) { return fnv_word(fnv_wo
 __device__ __forceinline__ uint32_t ev_nee(uint32_t k, uint32_t vis) { return fnv_word(fnv_word(kFnvBasis, k | 0x10000u), vis); }
 __device__ __forceinline__ uint32_t ev_cand(uint32_t k, uint32_t s, uint32_t lobe, uint32_t tex) {
     return fnv_word(fnv_word(fnv_word(fnv_word(kFnvBasis, k | 0x20000u), s), lobe), tex);
+}
+
+// texture mode: the three texture arrays interleaved into 32-byte texel
+// records, once per call (the textures are trainable inputs)
+__global__ void k_pack_texels(const float *__restrict__ albedo, const float *__restrict__ rough,
+                              const float *__restrict__ metal, uint64_t n, float4 *__restrict__ out) {
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[2 * i] = make_float4(albedo[3 * i], albedo[3 * i + 1], albedo[3 * i + 2], rough[i]);
+    out[2 * i + 1] = make_float4(metal[i], 0.0f, 0.0f, 0.0f);
 }
 
 // ============================================================================

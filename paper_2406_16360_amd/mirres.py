@@ -591,6 +591,43 @@ def render_autograd(scene: GpuScene, views: Sequence, opts, vmat=None, albedo=No
     return _RenderFn.apply(scene, list(views), opts, vmat, albedo, rough, metal, env)
 
 
+class _FieldRenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, scene, views, opts, table, w1, b1, w2, b2, env):
+        f = scene.field.with_params(table=table, w1=w1, b1=b1, w2=w2, b2=b2)
+        sc = object.__new__(GpuScene)
+        sc.__dict__.update(scene.__dict__)
+        sc.field = f
+        sc.env = _dev(env)
+        img, tape = render(sc, views, opts, keep_tape=True)
+        ctx.scene, ctx.views, ctx.opts, ctx.tape = sc, views, opts, tape
+        return img
+
+    @staticmethod
+    def backward(ctx, gimg):
+        sc = ctx.scene
+        need = ctx.needs_input_grad
+        grads = {k: torch.zeros_like(getattr(sc.field, k)) if need[3 + i] else None
+                 for i, k in enumerate(FIELD_KEYS)}
+        grads["env"] = torch.zeros_like(sc.env) if need[8] else None
+        render_backward(sc, ctx.views, ctx.opts, gimg, tape=ctx.tape, grads=grads)
+        ctx.tape = None
+        return (None, None, None) + tuple(grads[k] for k in FIELD_KEYS) + (grads["env"],)
+
+
+def render_field_autograd(scene: GpuScene, views: Sequence, opts, table=None, w1=None, b1=None, w2=None, b2=None,
+                          env=None) -> torch.Tensor:
+    """Differentiable render of a field-material scene: gradients flow to
+    whichever of the field's table / w1 / b1 / w2 / b2 and env are passed as
+    tensors requiring grad (defaults: the scene's own tensors)."""
+    if scene.mat_mode != MAT_FIELD:
+        raise ValueError("render_field_autograd needs a scene with a material field")
+    f = scene.field
+    args = [f.table if table is None else table, f.w1 if w1 is None else w1, f.b1 if b1 is None else b1,
+            f.w2 if w2 is None else w2, f.b2 if b2 is None else b2, scene.env if env is None else env]
+    return _FieldRenderFn.apply(scene, list(views), opts, *args)
+
+
 # ------------------------------------------------------------------ denoiser
 class _DenoiseParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("sigma_rt", C.c_float), ("sigma_n", C.c_float), ("sigma_x", C.c_float)]

@@ -180,3 +180,18 @@ def test_field_plan_graph_matches_eager(mr):
         for k in e_g:
             ref = e_g[k]
             assert torch.allclose(g[k], ref, rtol=1e-4, atol=1e-5 * float(ref.abs().max()) + 1e-12), (rep, k)
+
+
+def test_field_autograd_matches_render_backward(mr):
+    """torch autograd through render_field_autograd gives render_backward's gradients."""
+    w = _field_workload("c1", levels=6, log2_table=12, n_min=4, n_max=64)
+    sc = mr.GpuScene.from_synth(w.scene)
+    params = {k: getattr(sc.field, k).clone().requires_grad_(True) for k in mr.FIELD_KEYS}
+    img = mr.render_field_autograd(sc, w.views, w.opts, **params)
+    wgt = torch.rand_like(img)
+    (img * wgt).sum().backward()
+    _, tape = mr.render(sc, w.views, w.opts, keep_tape=True)
+    ref = mr.render_backward(sc, w.views, w.opts, wgt, tape=tape)
+    for k in mr.FIELD_KEYS:
+        r = ref[k]
+        assert torch.allclose(params[k].grad, r, rtol=1e-4, atol=1e-5 * float(r.abs().max()) + 1e-12), k
