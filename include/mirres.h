@@ -345,6 +345,10 @@ void       mrs_plan_destroy(mrs_plan *plan);
 
 /* Bytes a tape for these views/options would take (host arithmetic). */
 int64_t    mrs_tape_bytes(const mrs_view *views, int32_t n_views, const mrs_options *opt);
+/* Releases a tape.  Its device buffers are kept by the library as a spare for
+ * the next tape on the same device (an optimisation loop renders with a tape
+ * every step) until a larger tape replaces them or mrs_release_workspace
+ * frees them.  NULL is ignored. */
 void       mrs_tape_destroy(mrs_tape *tape);
 
 /* Kernel timing for measurement: between mrs_profile_begin and
@@ -362,7 +366,8 @@ typedef struct {
 mrs_status mrs_profile_begin(void);
 mrs_status mrs_profile_end(mrs_kernel_time *out, int32_t cap, int32_t *n);
 
-/* Frees the library's internal device workspace (it regrows on demand). */
+/* Frees the library's internal device workspace and the spare tape buffers
+ * (they regrow on demand). */
 void        mrs_release_workspace(void);
 const char *mrs_last_error(void);
 

@@ -561,12 +561,54 @@ void grad_rec_fold(const mrs_scene *sc, const GradRec &gl, const float *rec, con
     k_grad_fold<<<nblocks(n, 256), 256, 0, s>>>(f);
 }
 
+// The last released tape's buffers, kept for the next tape on the same
+// device: an optimisation loop renders with a tape every step, and a
+// hipMalloc / hipFree pair of a few GB per step costs more than holding one
+// tape.  mrs_release_workspace frees them.
+struct SpareTape {
+    std::mutex mu;
+    int device = -1;
+    DevBuf hit, y, rr;
+};
+SpareTape g_spare;
+
+void move_buf(DevBuf &dst, DevBuf &src) {
+    dst.release();
+    dst.p = src.p;
+    dst.bytes = src.bytes;
+    src.p = nullptr;
+    src.bytes = 0;
+}
+
 mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B) {
     size_t n = (size_t)S * B;
-    TRY(t->hit.alloc(sizeof(float4) * n));
-    TRY(t->y.alloc(sizeof(float4) * n));
-    TRY(t->rr.alloc(sizeof(float) * n));
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_spare.mu);
+        if (g_spare.device == dev) {
+            if (g_spare.hit.bytes >= sizeof(float4) * n) move_buf(t->hit, g_spare.hit);
+            if (g_spare.y.bytes >= sizeof(float4) * n) move_buf(t->y, g_spare.y);
+            if (g_spare.rr.bytes >= sizeof(float) * n) move_buf(t->rr, g_spare.rr);
+        }
+    }
+    TRY(t->hit.reserve(sizeof(float4) * n));
+    TRY(t->y.reserve(sizeof(float4) * n));
+    TRY(t->rr.reserve(sizeof(float) * n));
+    t->device = dev;
     return MRS_OK;
+}
+
+// keeps a released tape's buffers as the spare (the larger of the two wins)
+void tape_recycle(mrs_tape *t) {
+    std::lock_guard<std::mutex> lk(g_spare.mu);
+    if (g_spare.device != t->device) {
+        g_spare.hit.release(); g_spare.y.release(); g_spare.rr.release();
+        g_spare.device = t->device;
+    }
+    if (t->hit.bytes > g_spare.hit.bytes) move_buf(g_spare.hit, t->hit);
+    if (t->y.bytes > g_spare.y.bytes) move_buf(g_spare.y, t->y);
+    if (t->rr.bytes > g_spare.rr.bytes) move_buf(g_spare.rr, t->rr);
 }
 
 // tape policy: keep the per-vertex records when asked and affordable
@@ -777,7 +819,15 @@ extern "C" int64_t mrs_tape_bytes(const mrs_view *views, int32_t n_views, const 
     return (int64_t)(S * (uint64_t)std::max(0, opt->bounces) * kTapeRecBytes);
 }
 
-extern "C" void mrs_tape_destroy(mrs_tape *t) { delete t; }
+extern "C" void mrs_tape_destroy(mrs_tape *t) {
+    if (!t) return;
+    // No wait here: the only writers of a recycled buffer are a later eager
+    // render, which is ordered after every earlier eager call (same stream, or
+    // the workspace's completion event), and plan creation, which synchronises
+    // the device first.
+    tape_recycle(t);
+    delete t;
+}
 
 extern "C" mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const float *d_dir, int64_t n,
                                 int32_t any_hit, float *d_hit, void *stream) {
@@ -848,6 +898,9 @@ extern "C" void mrs_release_workspace(void) {
     if (g_ws.done) (void)hipEventSynchronize(g_ws.done);
     g_ws.res.release_all();
     g_ws.uploaded.clear();
+    std::lock_guard<std::mutex> lk2(g_spare.mu);
+    g_spare.hit.release(); g_spare.y.release(); g_spare.rr.release();
+    g_spare.device = -1;
 }
 
 // ============================================================================

@@ -67,6 +67,7 @@ struct mrs_bvh {
 };
 
 struct mrs_tape {
+    int device = -1;          // device the buffers live on
     uint64_t samples = 0;     // S covered
     int32_t bounces = 0;
     uint64_t seed = 0;
