@@ -298,11 +298,45 @@ __device__ __forceinline__ int env_texel_of(const EnvTables &e, V3 d) {
     return row * e.W + col;
 }
 
-// solid-angle pdf of the env sampler at direction d, with its texel radiance
-__device__ __forceinline__ float env_pdf_dir(const EnvTables &e, V3 d, int texel, float4 lp) {
-    if (!(*e.total > 0.0)) return 0.0f;
+// whether the env sampler has any valid sample (read once per vertex by the
+// callers, so that the loads inside a candidate loop are not split by it)
+__device__ __forceinline__ bool env_valid(const EnvTables &e) { return *e.total > 0.0; }
+
+// solid-angle pdf of the env sampler at direction d, with its texel radiance;
+// ok = env_valid(e)
+__device__ __forceinline__ float env_pdf_dir(bool ok, V3 d, float4 lp) {
+    if (!ok) return 0.0f;
     float st = sqrtf(fmaxf(0.0f, 1.0f - d.y * d.y));
     return st > 0.0f ? lp.w / st : 0.0f;
+}
+
+// 16-byte loads through a raw buffer resource over [base, base + bytes) (base
+// and bytes uniform over the wavefront).  The compiler keeps each one a single
+// buffer_load_dwordx4: from a plain pointer it splits a 16-byte record into
+// narrower loads when its words are used on different paths, and every extra
+// scattered load instruction costs the memory pipeline one more cycle per
+// distinct cache line.  An offset at or past the end reads zeros.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float4 buffer_float4(__amdgpu_buffer_rsrc_t r, uint32_t index) {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, index * 16u, 0, 0);
+    return make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z), __uint_as_float(q.w));
+}
+__device__ __forceinline__ double2 buffer_double2(__amdgpu_buffer_rsrc_t r, uint32_t index) {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, index * 16u, 0, 0);
+    return make_double2(__hiloint2double((int)q.y, (int)q.x), __hiloint2double((int)q.w, (int)q.z));
+}
+
+// the env's per-texel tables as buffer resources (W H < 2^28 texels, so the
+// byte offsets fit in 32 bits)
+struct EnvBufs {
+    __amdgpu_buffer_rsrc_t cpair, lp;
+};
+__device__ __forceinline__ EnvBufs env_bufs(const EnvTables &e) {
+    const uint32_t bytes = (uint32_t)e.W * (uint32_t)e.H * 16u;
+    return EnvBufs{buffer_rsrc(e.cpair, bytes), buffer_rsrc(e.lp, bytes)};
 }
 
 // smallest i with cdf[i + 1] > u (cdf[0] = 0 <= u < 1 = cdf[n]): the unique i
@@ -316,19 +350,28 @@ __device__ __forceinline__ int interval_walk(const double2 *iv, int start, int n
     while (i < n - 1 && !(p.y > u)) { ++i; p = iv[i]; }
     return i;
 }
+// the same walk over the intervals base .. base + n - 1 of a buffer resource
+__device__ __forceinline__ int interval_walk(__amdgpu_buffer_rsrc_t iv, uint32_t base, int start, int n, double u,
+                                             double2 &p) {
+    int i = min(max(start, 0), n - 1);
+    p = buffer_double2(iv, base + i);
+    while (i > 0 && p.x > u) { --i; p = buffer_double2(iv, base + i); }
+    while (i < n - 1 && !(p.y > u)) { ++i; p = buffer_double2(iv, base + i); }
+    return i;
+}
 
 // CDF inversion (row from the marginal, column from the row's conditional,
 // linear remainder inside the texel), in double like the tables.
-__device__ __forceinline__ bool env_sample(const EnvTables &e, const MargView &mv, float u0f, float u1f, V3 &dir,
-                                           int &texel, float4 &lp, float &pdf) {
-    if (!(*e.total > 0.0)) return false;
+__device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb, bool ok, const MargView &mv,
+                                           float u0f, float u1f, V3 &dir, int &texel, float4 &lp, float &pdf) {
+    if (!ok) return false;
     double u0 = u0f, u1 = u1f;
     double2 pm, pc;
     int i = interval_walk(mv.pair, mv.guide[min((int)(u0 * e.H), e.H - 1)], e.H, u0, pm);
     // the CDF differences are formed in double, the in-texel fractions in float
     float fv = __fdividef((float)(u0 - pm.x), (float)(pm.y - pm.x));
-    const size_t row = (size_t)i * e.W;
-    int j = interval_walk(e.cpair + row, e.gcond[row + min((int)(u1 * e.W), e.W - 1)], e.W, u1, pc);
+    const uint32_t row = (uint32_t)i * (uint32_t)e.W;
+    int j = interval_walk(eb.cpair, row, e.gcond[row + min((int)(u1 * e.W), e.W - 1)], e.W, u1, pc);
     float fu = __fdividef((float)(u1 - pc.x), (float)(pc.y - pc.x));
     float v = ((float)i + fv) / (float)e.H, u = ((float)j + fu) / (float)e.W;
     float st, ct, sp, cp;
@@ -337,7 +380,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const MargView &m
     if (!(st > 0.0f)) return false;
     dir = V3{st * sp, ct, -st * cp};
     texel = i * e.W + j;
-    lp = e.lp[texel];
+    lp = buffer_float4(eb.lp, (uint32_t)texel);
     pdf = lp.w / st;
     return pdf > 0.0f;
 }

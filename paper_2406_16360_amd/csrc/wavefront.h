@@ -460,6 +460,8 @@ __device__ __forceinline__ void ris_select(const EnvTables &env, const MV &marg,
     o.y = V3{0, 0, 0}; o.fy = V3{0, 0, 0}; o.Ly = V3{0, 0, 0};
     o.sel = -1; o.ytex = -1;
     if (!front) return;
+    const bool env_ok = env_valid(env);
+    const EnvBufs eb = env_bufs(env);
     for (int s = 0; s < M; ++s) {
         float4 u = rng.draw((uint32_t)k, (uint32_t)s);
         V3 dir, wl;
@@ -467,7 +469,7 @@ __device__ __forceinline__ void ris_select(const EnvTables &env, const MV &marg,
         float4 lp;
         float qe, qb;
         if (s < Me) {
-            if (!env_sample(env, marg, u.x, u.y, dir, tex, lp, qe)) continue;
+            if (!env_sample(env, eb, env_ok, marg, u.x, u.y, dir, tex, lp, qe)) continue;
             wl = to_local(F, dir);
         } else {
             int lb = mix_sample(L, u.x, u.y, u.z, wl);
@@ -475,8 +477,8 @@ __device__ __forceinline__ void ris_select(const EnvTables &env, const MV &marg,
             dir = to_world(F, wl);
             tex = env_texel_of(env, dir);
             if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
-            lp = env.lp[tex];
-            qe = env_pdf_dir(env, dir, tex, lp);
+            lp = buffer_float4(eb.lp, (uint32_t)tex);
+            qe = env_pdf_dir(env_ok, dir, lp);
         }
         if (!(wl.z > 0.0f)) continue;
         V3 f = brdf_eval_pdf(L, wl, qb);
