@@ -99,12 +99,16 @@ constexpr int kLdsStackBytes = kLdsStack * 4;
 
 // Traversal stack: the first kLdsStack entries live in LDS, one column per
 // thread (entry i of thread t at [i * stride + t], so a wavefront touches
-// consecutive words); deeper entries spill to a private array.
+// consecutive words); deeper entries spill to a private array owned by the
+// caller.  The array is kept out of this struct: a dynamically indexed member
+// would put the whole struct, stack pointer included, in scratch memory, and
+// every push and pop would then go through the memory pipeline.
+constexpr int kSpillStack = kStackSize - kLdsStack;
 struct TStack {
     int *ref;          // LDS column of node refs
+    int *spill_ref;    // the caller's private int[kSpillStack]
     int stride;
     int sp = 0;
-    int spill_ref[kStackSize - kLdsStack];
     // the build rejects trees deeper than the stack, so a full stack is never
     // reached; if it were, the entry is dropped rather than written out of bounds.
     // The LDS accesses are relaxed workgroup-scope atomics, which the compiler
@@ -123,10 +127,11 @@ struct TStack {
 };
 
 // per-thread view of the kernel's dynamic LDS (kLdsStackBytes * blockDim bytes)
-__device__ __forceinline__ TStack make_stack(void *lds) {
+__device__ __forceinline__ TStack make_stack(void *lds, int *spill) {
     TStack st;
     st.stride = blockDim.x;
     st.ref = (int *)lds + threadIdx.x;
+    st.spill_ref = spill;
     return st;
 }
 
@@ -223,7 +228,8 @@ __device__ __forceinline__ void trace_wave(const BvhNode *__restrict__ nodes, co
     RayPre r = ray_pre(o, d);
     h = no_hit();
     occl = false;
-    TStack st = make_stack(lds);
+    int spill[kSpillStack];
+    TStack st = make_stack(lds, spill);
     int node = 0;
     while (__ballot(node != kNone) != 0) trace_iter<kAny>(nodes, tris, node != kNone, r, h, occl, st, node);
 }
@@ -271,7 +277,8 @@ static_assert(MRS_REFILL >= 1 && MRS_REFILL <= 64, "a refill needs between 1 and
 template <bool kAny, class Load, class Done>
 __device__ __forceinline__ void persistent_trace(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                                  uint32_t n, uint32_t *claim, void *lds, Load load, Done done) {
-    TStack st = make_stack(lds);
+    int spill[kSpillStack];
+    TStack st = make_stack(lds, spill);
     RayPre r;
     Hit h = no_hit();
     bool occl = false;
