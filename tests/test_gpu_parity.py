@@ -171,6 +171,14 @@ def test_forward_textured_full(mr, orc_mod):
     _pixel_check(w, r)
 
 
+def test_forward_tall_env_global_marginal(mr, orc_mod):
+    """An env map with more rows than shading keeps in LDS (1024): the
+    marginal CDF is walked in global memory instead."""
+    w = _textured(env=(1100, 6), res=(40, 24), spp=2)
+    r = _forward(mr, orc_mod, w, label="tall-env")
+    _pixel_check(w, r)
+
+
 def test_forward_multiview_ragged(mr, orc_mod):
     """Several views of different size, spp and sample offset in one call."""
     w = _textured(res=(33, 17), spp=3)

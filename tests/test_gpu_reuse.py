@@ -100,10 +100,12 @@ def _workloads():
     from tests.test_gpu_parity import _textured
     c1 = synth.config1()
     tex = _textured(res=(48, 40), spp=2)
-    return {"c1": c1, "textured": tex}
+    # more env rows than the initial RIS keeps in LDS: global marginal walk
+    tall = _textured(env=(1100, 6), res=(40, 24), spp=2)
+    return {"c1": c1, "textured": tex, "tall_env": tall}
 
 
-@pytest.mark.parametrize("kind", ["c1", "textured"])
+@pytest.mark.parametrize("kind", ["c1", "textured", "tall_env"])
 def test_reuse_spatial_and_temporal_frames(mr, orc_mod, kind):
     """Frame 0 (spatial only: no history yet), then frame 1 with the history
     of frame 0 on each side (spatial + temporal), at a new seed."""
