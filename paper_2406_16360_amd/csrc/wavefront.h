@@ -451,6 +451,40 @@ struct RisOut {
     uint32_t hev;                 // decision-hash events of the BRDF candidates (or of the reuse)
 };
 
+// candidate s of the streaming reservoir (env candidate if kEnv)
+template <bool kEnv, class MV>
+__device__ __forceinline__ void ris_candidate(const EnvTables &env, const EnvBufs &eb, bool env_ok, const MV &marg,
+                                              const Rng &rng, int k, int s, int Me, int Mb, const Lobe &L,
+                                              const Frame &F, bool want_hash, RisOut &o) {
+    float4 u = rng.draw((uint32_t)k, (uint32_t)s);
+    V3 dir, wl;
+    int tex;
+    float4 lp;
+    float qe, qb;
+    if (kEnv) {
+        if (!env_sample(env, eb, env_ok, marg, u.x, u.y, dir, tex, lp, qe)) return;
+        wl = to_local(F, dir);
+    } else {
+        int lb = mix_sample(L, u.x, u.y, u.z, wl);
+        if (!lb) return;
+        dir = to_world(F, wl);
+        tex = env_texel_of(env, dir);
+        if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
+        lp = buffer_float4(eb.lp, (uint32_t)tex);
+        qe = env_pdf_dir(env_ok, dir, lp);
+    }
+    if (!(wl.z > 0.0f)) return;
+    V3 f = brdf_eval_pdf(L, wl, qb);
+    float phat = (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
+    float den = (float)Me * qe + (float)Mb * qb;
+    if (!(phat > 0.0f) || !(den > 0.0f)) return;
+    float w = phat / den;
+    o.wsum += w;
+    if (u.w < w / o.wsum) {
+        o.sel = s; o.y = dir; o.fy = f; o.Ly = V3{lp.x, lp.y, lp.z}; o.phat = phat; o.ytex = tex; o.cos_y = wl.z;
+    }
+}
+
 template <class MV>
 __device__ __forceinline__ void ris_select(const EnvTables &env, const MV &marg, const Rng &rng, int k, int M, int Mb,
                                            const Lobe &L, const Frame &F, bool front, bool want_hash, RisOut &o) {
@@ -462,35 +496,10 @@ __device__ __forceinline__ void ris_select(const EnvTables &env, const MV &marg,
     if (!front) return;
     const bool env_ok = env_valid(env);
     const EnvBufs eb = env_bufs(env);
-    for (int s = 0; s < M; ++s) {
-        float4 u = rng.draw((uint32_t)k, (uint32_t)s);
-        V3 dir, wl;
-        int tex;
-        float4 lp;
-        float qe, qb;
-        if (s < Me) {
-            if (!env_sample(env, eb, env_ok, marg, u.x, u.y, dir, tex, lp, qe)) continue;
-            wl = to_local(F, dir);
-        } else {
-            int lb = mix_sample(L, u.x, u.y, u.z, wl);
-            if (!lb) continue;
-            dir = to_world(F, wl);
-            tex = env_texel_of(env, dir);
-            if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
-            lp = buffer_float4(eb.lp, (uint32_t)tex);
-            qe = env_pdf_dir(env_ok, dir, lp);
-        }
-        if (!(wl.z > 0.0f)) continue;
-        V3 f = brdf_eval_pdf(L, wl, qb);
-        float phat = (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
-        float den = (float)Me * qe + (float)Mb * qb;
-        if (!(phat > 0.0f) || !(den > 0.0f)) continue;
-        float w = phat / den;
-        o.wsum += w;
-        if (u.w < w / o.wsum) {
-            o.sel = s; o.y = dir; o.fy = f; o.Ly = V3{lp.x, lp.y, lp.z}; o.phat = phat; o.ytex = tex; o.cos_y = wl.z;
-        }
-    }
+    // candidates in order s = 0 .. M - 1: the Me env candidates, then the Mb
+    // BRDF ones, each kind in a loop of its own (no per-candidate branch)
+    for (int s = 0; s < Me; ++s) ris_candidate<true>(env, eb, env_ok, marg, rng, k, s, Me, Mb, L, F, want_hash, o);
+    for (int s = Me; s < M; ++s) ris_candidate<false>(env, eb, env_ok, marg, rng, k, s, Me, Mb, L, F, want_hash, o);
 }
 
 // A reservoir record: (y, W) and (M, decision-hash events of its own
