@@ -268,7 +268,7 @@ __global__ void k_depth(const int32_t *__restrict__ parent, int n, int leaf_base
 // nodes placed where the left one was, and compacts.  Merge ids and the
 // compaction come from prefix sums, so the tree is deterministic.
 // ---------------------------------------------------------------------------
-constexpr int kPlocRadius = 16;
+constexpr int kPlocRadius = 32;
 constexpr int kPlocBlock = 256;
 
 __device__ __forceinline__ float half_area(float4 l, float4 h) {

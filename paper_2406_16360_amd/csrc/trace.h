@@ -198,13 +198,19 @@ __device__ __forceinline__ int any_leaf(const TriRec *__restrict__ tris, const R
     return st.sp > 0 ? st.pop() : kNone;
 }
 
+// lanes waiting at a leaf that start a leaf phase, for any-hit and for
+// closest-hit traversal (closest-hit leaves cost more: their hits keep the
+// ray going, so batching more of them pays)
 #ifndef MRS_LEAF_BATCH
-#define MRS_LEAF_BATCH 8   // lanes waiting at a leaf that start a leaf phase
+#define MRS_LEAF_BATCH 8
+#endif
+#ifndef MRS_LEAF_BATCH_CLOSEST
+#define MRS_LEAF_BATCH_CLOSEST 12
 #endif
 
 // One traversal iteration of a wavefront (while-while traversal with
 // postponed leaves, after Aila and Laine, HPG 2009).  A lane whose next
-// reference is a leaf waits until at least MRS_LEAF_BATCH lanes of the
+// reference is a leaf waits until at least the leaf batch of lanes of the
 // wavefront are at a leaf, or none is at an inner node; then those lanes
 // test their leaves together.  Lanes at an inner node then visit it.  `live`
 // marks lanes with a ray; the closest-hit result (smallest t, ties to the
@@ -215,7 +221,7 @@ __device__ __forceinline__ void trace_iter(const BvhNode *__restrict__ nodes, co
                                            bool live, const RayPre &r, Hit &h, bool &occl, TStack &st, int &node) {
     const bool at_leaf = live && node < 0;
     const uint64_t leaves = __ballot(at_leaf), inner = __ballot(live && node >= 0);
-    if (inner == 0 || __popcll(leaves) >= MRS_LEAF_BATCH) {
+    if (inner == 0 || __popcll(leaves) >= (kAny ? MRS_LEAF_BATCH : MRS_LEAF_BATCH_CLOSEST)) {
         if (at_leaf) node = kAny ? any_leaf(tris, r, st, node, occl) : closest_leaf(tris, r, h, st, node);
     }
     if (live && node >= 0) node = inner_step(nodes, r, kAny ? INFINITY : h.t, st, node, kAny ? 2 : 0);
