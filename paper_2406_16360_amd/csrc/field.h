@@ -287,60 +287,66 @@ struct PointsPerm {
 // into feature j of the slot of corner k (16 values).  Device-scope float
 // atomics are carried out past L2, one memory-side request per cache line an
 // instruction touches, so the values are not issued lane by lane:
-//   - a half-wave whose pending lanes all lie in one cell (neighbouring
-//     points of a tile at the coarse levels) sums its 16 values over the
-//     half (butterfly) and its first pending lane adds them;
-//   - otherwise every pending lane stages its 16 (offset, value) pairs in
-//     LDS, corner pairs along x first (their slots are adjacent on dense
-//     levels, and on hashed levels when the lower x is even, since the x
-//     prime is 1), and the wavefront issues them transposed: instruction j
-//     takes the 16 pairs of lanes 4j..4j+3, so it touches a few cache lines
-//     instead of 64.
+//   - consecutive pending lanes of a half-wave whose points lie in the same
+//     cell form a run (the points come in Morton order, so the points of a
+//     cell are mostly adjacent); a segmented suffix sum over the half gives
+//     each run's first lane the run's 16 totals;
+//   - only those lanes issue: they stage their 16 (offset, value) pairs in
+//     LDS, packed densely, corner pairs along x first (their slots are
+//     adjacent on dense levels, and on hashed levels when the lower x is
+//     even, since the x prime is 1), and the wavefront issues them
+//     transposed: instruction j takes the pairs of runs 4j..4j+3, so it
+//     touches a few cache lines instead of 64.
 // Offsets count floats from the table gradient's base.  Every lane of the
 // wavefront calls it.
 constexpr int kScatterPairs = 16;
 __device__ __forceinline__ void scatter_level(float *gtab, uint32_t base, const uint32_t (&slot)[8],
                                               const float (&w)[8], float d0, float d1, const uint32_t (&cell)[3],
-                                              bool pending, uint32_t *s_off, float *s_val, int *s_cnt) {
-    const int lane = __lane_id();
-    const uint64_t half_mask = lane < 32 ? 0x00000000FFFFFFFFull : 0xFFFFFFFF00000000ull;
+                                              bool pending, uint32_t *s_off, float *s_val) {
+    const int lane = __lane_id(), hl = lane & 31;
     const uint64_t pm = __ballot(pending);
     if (pm == 0) return;
-    const uint64_t mine = pm & half_mask;
-    const int leader = mine ? __ffsll((unsigned long long)mine) - 1 : lane;
-    const uint32_t l0 = __shfl(cell[0], leader), l1 = __shfl(cell[1], leader), l2 = __shfl(cell[2], leader);
-    const bool differs = pending && (cell[0] != l0 || cell[1] != l1 || cell[2] != l2);
-    const bool agg = mine != 0 && (__ballot(differs) & half_mask) == 0;
+    const uint32_t q0 = __shfl_up(cell[0], 1), q1 = __shfl_up(cell[1], 1), q2 = __shfl_up(cell[2], 1);
+    const bool prev_pending = hl > 0 && ((pm >> (lane - 1)) & 1ull);
+    const bool head = pending && (!prev_pending || q0 != cell[0] || q1 != cell[1] || q2 != cell[2]);
+    const uint64_t hm = __ballot(head);
     float v[kScatterPairs];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         v[2 * k] = pending ? w[k] * d0 : 0.0f;
         v[2 * k + 1] = pending ? w[k] * d1 : 0.0f;
     }
-    if (__ballot(agg) != 0) {
+    if (hm != pm) {   // some run has more than one lane
+        // last lane of this lane's run: before the next head or non-pending
+        // lane of the same half
+        const uint64_t bnd = hm | ~pm;
+        const uint64_t half_mask = lane < 32 ? 0x00000000FFFFFFFFull : 0xFFFFFFFF00000000ull;
+        const uint64_t after = lane == 63 ? 0ull : (~0ull << (lane + 1));
+        const uint64_t nb = bnd & half_mask & after;
+        const int end = nb ? __ffsll((unsigned long long)nb) - 2 : (lane < 32 ? 31 : 63);
 #pragma unroll
-        for (int e = 0; e < kScatterPairs; ++e) {
-            float t = agg ? v[e] : 0.0f;
+        for (int o = 1; o < 32; o <<= 1) {
 #pragma unroll
-            for (int o = 16; o >= 1; o >>= 1) t += __shfl_xor(t, o);
-            if (agg) v[e] = t;
+            for (int e = 0; e < kScatterPairs; ++e) {
+                const float t = __shfl_down(v[e], o);
+                if (lane + o <= end) v[e] += t;
+            }
         }
     }
-    const int n = agg ? (lane == leader ? kScatterPairs : 0) : (pending ? kScatterPairs : 0);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int pos = kScatterPairs * __popcll(hm & below);
+    if (head) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        s_off[lane * kScatterPairs + 2 * k] = base + 2 * slot[k];
-        s_off[lane * kScatterPairs + 2 * k + 1] = base + 2 * slot[k] + 1;
-        s_val[lane * kScatterPairs + 2 * k] = v[2 * k];
-        s_val[lane * kScatterPairs + 2 * k + 1] = v[2 * k + 1];
+        for (int k = 0; k < 8; ++k) {
+            s_off[pos + 2 * k] = base + 2 * slot[k];
+            s_off[pos + 2 * k + 1] = base + 2 * slot[k] + 1;
+            s_val[pos + 2 * k] = v[2 * k];
+            s_val[pos + 2 * k + 1] = v[2 * k + 1];
+        }
     }
-    s_cnt[lane] = n;
+    const int total = kScatterPairs * __popcll(hm);
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kScatterPairs; ++j) {
-        const int e = j * 64 + lane, src = e / kScatterPairs;
-        if ((e % kScatterPairs) < s_cnt[src]) atomicAdd(gtab + s_off[e], s_val[e]);
-    }
+    for (int e = lane; e < total; e += 64) atomicAdd(gtab + s_off[e], s_val[e]);
     __syncthreads();
 }
 
@@ -354,7 +360,6 @@ void k_field_backward(FieldDev f, Src src, const float *__restrict__ g, FieldGra
     __shared__ float4 sG[kFieldTile];
     __shared__ uint32_t s_off[64 * kScatterPairs];
     __shared__ float s_val[64 * kScatterPairs];
-    __shared__ int s_cnt[64];
     const int lane = threadIdx.x, half = lane >> 5, hid = lane & 31;
     const uint64_t ntiles = (src.count() + kFieldTile - 1) / kFieldTile;
     float w1c[16], w1r[16];
@@ -439,7 +444,7 @@ void k_field_backward(FieldDev f, Src src, const float *__restrict__ g, FieldGra
                 field_corners(u, N, (f.dense >> (l & 31)) & 1u, f.tmask, slot, w, cell);
                 const uint32_t base = (uint32_t)(l < f.L ? l : 0) << (f.log2T + 1);
                 scatter_level(out.table, base, slot, w, de[2 * q], de[2 * q + 1], cell, valid && l < f.L, s_off,
-                              s_val, s_cnt);
+                              s_val);
             }
         }
     }
