@@ -73,6 +73,35 @@ def test_field_backward_matches_oracle(mr, name):
         assert err < 1e-5, k
 
 
+def test_field_backward_runs_of_shared_cells(mr):
+    """Points that come in clusters of 1 to 40 (exact duplicates, or spread
+    from inside one finest cell to a few coarse cells), with gradient-free
+    points among them: consecutive points of a half-wave that share a cell at
+    a level are summed before the table's atomics, for runs of every length,
+    broken by the gradient-free points and by the half-wave boundary."""
+    from oracle.oracle import FieldRef
+    f = _field("paper", seed=9)
+    rng = np.random.default_rng(10)
+    span = f.hi - f.lo
+    pts = []
+    while len(pts) < 3000:
+        c = f.lo + rng.uniform(0.0, 1.0, 3) * span
+        m = int(rng.integers(1, 41))
+        spread = 0.0 if rng.random() < 0.2 else 10.0 ** rng.uniform(-6.0, -2.0)
+        pts.extend(c + rng.normal(scale=1.0, size=(m, 3)) * spread * span)
+    x = np.asarray(pts[:3000], np.float32)
+    g = rng.normal(size=(len(x), 4)).astype(np.float32)
+    g[rng.random(len(x)) < 0.1] = 0.0
+    ref = FieldRef(f).vjp(x, g)
+    gf = mr.Field.from_synth(f)
+    out = gf.backward(torch.tensor(x, device="cuda"), torch.tensor(g, device="cuda"))
+    for k in ("table", "w1", "b1", "w2", "b2"):
+        a, b = out[k].cpu().numpy(), ref[k]
+        err = np.abs(a - b).max() / np.abs(b).max()
+        print(f"   runs {k}: max err / max |grad| {err:.2e}")
+        assert err < 1e-5, k
+
+
 def test_field_backward_accumulates_and_skips_null(mr):
     from oracle.oracle import FieldRef
     f = _field("odd7", seed=6)
