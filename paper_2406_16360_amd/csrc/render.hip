@@ -418,6 +418,9 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
     Queue qa{r.qa_o.as<float4>(), r.qa_d.as<float4>(), r.qa_t.as<float4>()};
     Queue qb{r.qb_o.as<float4>(), r.qb_d.as<float4>(), r.qb_t.as<float4>()};
     IterCtr *ctr = r.ctr.as<IterCtr>();
+    // with reservoir reuse the reuse pass has traced every camera ray of the
+    // frame: the path tracer takes those hits instead of tracing again
+    const float4 *prim = job.reuse.on ? r.rprim.as<float4>() : nullptr;
     int bs = job.block;
     for (int it = 0; it < n_iter; ++it) {
         {
@@ -426,12 +429,13 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
         }
         {
             PROF(KID_GENERATE, s);
-            GenArgs ga{job.vt, job.op, qa, ctr, it, r.out.as<float4>(), ch.c0, hash};
+            GenArgs ga{job.vt, job.op, qa, ctr, it, r.out.as<float4>(), ch.c0, hash, prim, r.hits.as<float4>()};
             k_generate<<<nblocks(P, 256), 256, 0, s>>>(ga);
         }
         {
             PROF(KID_CLOSEST, s);
-            TraceArgs ta{job.sd.nodes, job.sd.tris, qa, r.hits.as<float4>(), ctr, it, claim + it * kClaimWords};
+            TraceArgs ta{job.sd.nodes, job.sd.tris, qa, r.hits.as<float4>(), ctr, it, claim + it * kClaimWords,
+                         prim != nullptr};
             k_trace_closest<<<persistent_blocks(P, bs), bs, kLdsStackBytes * bs, s>>>(ta);
         }
         if (field) {

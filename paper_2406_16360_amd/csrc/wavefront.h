@@ -398,6 +398,8 @@ __global__ void k_schedule(IterCtr *__restrict__ ctr, int it, Sched *__restrict_
 struct GenArgs {
     ViewTable vt; Opts op; Queue q; IterCtr *ctr; int it;
     float4 *out; uint64_t out_base; uint32_t *hash;
+    const float4 *prim;   // with reservoir reuse: the primary hits it traced, per sample (else null)
+    float4 *hits;         // the iteration's hit records (written here for camera rays when prim is given)
 };
 
 __global__ void k_generate(GenArgs a) {
@@ -414,6 +416,10 @@ __global__ void k_generate(GenArgs a) {
     a.q.o[slot] = make_float4(o.x, o.y, o.z, __uint_as_float((uint32_t)g));
     a.q.d[slot] = make_float4(d.x, d.y, d.z, __int_as_float(1));
     a.q.t[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    if (a.prim) {   // the same ray's hit, already traced by the reuse pass
+        const float4 p = a.prim[g];
+        a.hits[slot] = make_float4(0.0f, p.x, p.y, p.z);
+    }
     a.out[g - a.out_base] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (a.hash) a.hash[g - a.out_base] = 0u;
 }
@@ -422,13 +428,14 @@ struct TraceArgs {
     const BvhNode *nodes; const TriRec *tris;
     Queue q; float4 *hits; IterCtr *ctr; int it;
     uint32_t *claim;      // kClaimWords zeroed claim counters
+    int continuing_only;  // trace only the continuing rays (the camera rays' hits are given)
 };
 
 // persistent: launched with a fixed grid that fills the device once
 __global__ __launch_bounds__(256) void k_trace_closest(TraceArgs a) {
     extern __shared__ int lds_stack[];
     IterCtr &c = a.ctr[a.it];
-    const uint32_t n = c.n_live;
+    const uint32_t n = a.continuing_only ? c.n_in : c.n_live;
     if (blockIdx.x * blockDim.x >= n) return;
     persistent_trace<false>(
         a.nodes, a.tris, n, a.claim, lds_stack,
