@@ -343,7 +343,9 @@ mrs_status mrs_plan_info(const mrs_plan *plan, int64_t *samples, int32_t *keeps_
 /* waits for the device, then frees the plan and its buffers */
 void       mrs_plan_destroy(mrs_plan *plan);
 
-/* Bytes a tape for these views/options would take (host arithmetic). */
+/* Bytes a tape for these views/options would take (host arithmetic): 36 per
+ * path vertex; a tape recorded with field materials (MRS_MAT_FIELD) also keeps
+ * the field's output at each vertex, 16 bytes more. */
 int64_t    mrs_tape_bytes(const mrs_view *views, int32_t n_views, const mrs_options *opt);
 /* Releases a tape.  Its device buffers are kept by the library as a spare for
  * the next tape on the same device (an optimisation loop renders with a tape

@@ -99,6 +99,7 @@ constexpr uint64_t kOutChunkMax = 1ull << 26;   // samples per super-chunk of th
 constexpr uint32_t kPoolDefault = 1u << 23;      // paths in flight
 constexpr int kBlockDefault = 64;                // threads per workgroup of the trace and shade kernels
 constexpr uint64_t kTapeRecBytes = 36;           // tape bytes per path vertex
+constexpr uint64_t kTapeFieldBytes = 16;         // and, in field mode, the field's output at the vertex
 constexpr uint64_t kAdjChunk = 1ull << 24;        // samples per adjoint launch
 
 struct Chunk { uint64_t c0, c1, pix0, pix1; };
@@ -110,7 +111,7 @@ struct Res {
     DevBuf views;                                              // ViewDev table
     DevBuf qa_o, qa_d, qa_t, qb_o, qb_d, qb_t, hits, so, sd, sc; // path pool queues
     DevBuf ctr, sched, out;                                    // iteration counters, scheduler, sample radiance
-    DevBuf ct_hit, ct_y, ct_rr;                                // chunk tape (recompute mode)
+    DevBuf ct_hit, ct_y, ct_rr, ct_fm;                         // chunk tape (recompute mode)
     DevBuf grec;                                               // adjoint gradient records
     DevBuf fm, fvtx, gvtx;                                     // field mode: pool materials, vertex materials and gradients
     DevBuf rprim, rfmat, rr0, rr1;                             // reuse: primary hits, their field output, reservoirs
@@ -118,7 +119,7 @@ struct Res {
     DevBuf tpack;                                              // texture mode: interleaved texel records
     void release_all() {
         for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &views, &qa_o, &qa_d, &qa_t, &qb_o,
-                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &grec, &fm, &fvtx, &gvtx,
+                          &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &ct_fm, &grec, &fm, &fvtx, &gvtx,
                           &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort, &tpack})
             b->release();
     }
@@ -515,11 +516,18 @@ mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, con
     for (uint64_t a0 = c0; a0 < c1; a0 += kAdjChunk) {
         uint64_t n = std::min<uint64_t>(kAdjChunk, c1 - a0);
         SceneDev sd = job.sd;
+        uint64_t fm_stride = n;
         if (job.sd.mat_mode == MRS_MAT_FIELD) {
-            PROF(KID_FIELD, s);
-            PointsTape src{tp, job.sd.tris, a0, n, job.op.B};
-            k_field_eval<PointsTape><<<nblocks(src.count(), kFieldTile), 64, 0, s>>>(job.fd, src, r.fvtx.as<float>());
-            sd.fm = r.fvtx.as<float4>();
+            if (tp.fm) {   // the forward kept the field's output at every vertex
+                sd.fm = tp.fm + (a0 - tp.base);
+                fm_stride = tp.S;
+            } else {
+                PROF(KID_FIELD, s);
+                PointsTape src{tp, job.sd.tris, a0, n, job.op.B};
+                k_field_eval<PointsTape><<<nblocks(src.count(), kFieldTile), 64, 0, s>>>(job.fd, src,
+                                                                                          r.fvtx.as<float>());
+                sd.fm = r.fvtx.as<float4>();
+            }
         }
         const int kgrad = job.op.grad_mode == MRS_GRAD_PRIMARY ? 1 : job.op.B;
         if (field) {
@@ -529,7 +537,7 @@ mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, con
         {
             PROF(KID_ADJOINT, s);
             AdjArgs aa{sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env,
-                       rec, gl.env_base, gl.n_mat > 0 ? 1 : 0, r.gvtx.as<float4>(), field ? 1 : 0};
+                       rec, gl.env_base, gl.n_mat > 0 ? 1 : 0, r.gvtx.as<float4>(), field ? 1 : 0, fm_stride};
             k_adjoint<<<nblocks(n, kAdjBlock), kAdjBlock, 0, s>>>(aa);
         }
         if (field) {
@@ -572,7 +580,7 @@ void grad_rec_fold(const mrs_scene *sc, const GradRec &gl, const float *rec, con
 struct SpareTape {
     std::mutex mu;
     int device = -1;
-    DevBuf hit, y, rr;
+    DevBuf hit, y, rr, fm;
 };
 SpareTape g_spare;
 
@@ -584,7 +592,7 @@ void move_buf(DevBuf &dst, DevBuf &src) {
     src.bytes = 0;
 }
 
-mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B) {
+mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B, bool field) {
     size_t n = (size_t)S * B;
     int dev = -1;
     (void)hipGetDevice(&dev);
@@ -594,11 +602,13 @@ mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B) {
             if (g_spare.hit.bytes >= sizeof(float4) * n) move_buf(t->hit, g_spare.hit);
             if (g_spare.y.bytes >= sizeof(float4) * n) move_buf(t->y, g_spare.y);
             if (g_spare.rr.bytes >= sizeof(float) * n) move_buf(t->rr, g_spare.rr);
+            if (field && g_spare.fm.bytes >= sizeof(float4) * n) move_buf(t->fm, g_spare.fm);
         }
     }
     TRY(t->hit.reserve(sizeof(float4) * n));
     TRY(t->y.reserve(sizeof(float4) * n));
     TRY(t->rr.reserve(sizeof(float) * n));
+    if (field) TRY(t->fm.reserve(sizeof(float4) * n));
     t->device = dev;
     return MRS_OK;
 }
@@ -607,19 +617,21 @@ mrs_status tape_alloc(mrs_tape *t, uint64_t S, int B) {
 void tape_recycle(mrs_tape *t) {
     std::lock_guard<std::mutex> lk(g_spare.mu);
     if (g_spare.device != t->device) {
-        g_spare.hit.release(); g_spare.y.release(); g_spare.rr.release();
+        g_spare.hit.release(); g_spare.y.release(); g_spare.rr.release(); g_spare.fm.release();
         g_spare.device = t->device;
     }
     if (t->hit.bytes > g_spare.hit.bytes) move_buf(g_spare.hit, t->hit);
     if (t->y.bytes > g_spare.y.bytes) move_buf(g_spare.y, t->y);
     if (t->rr.bytes > g_spare.rr.bytes) move_buf(g_spare.rr, t->rr);
+    if (t->fm.bytes > g_spare.fm.bytes) move_buf(g_spare.fm, t->fm);
 }
 
 // tape policy: keep the per-vertex records when asked and affordable
 mrs_status decide_tape(const Job &job, const mrs_options *opt, bool wanted, mrs_tape **out) {
     *out = nullptr;
     if (!wanted || opt->tape_mode == MRS_TAPE_OFF) return MRS_OK;
-    uint64_t bytes = job.S * job.op.B * kTapeRecBytes;
+    const bool field = job.sd.mat_mode == MRS_MAT_FIELD;
+    uint64_t bytes = job.S * job.op.B * (kTapeRecBytes + (field ? kTapeFieldBytes : 0));
     uint64_t budget = (uint64_t)opt->tape_budget;
     if (budget == 0) {
         size_t fr = 0, tot = 0;
@@ -628,7 +640,7 @@ mrs_status decide_tape(const Job &job, const mrs_options *opt, bool wanted, mrs_
     }
     if (opt->tape_mode != MRS_TAPE_ON && bytes > budget) return MRS_OK;
     mrs_tape *t = new mrs_tape();
-    mrs_status st = tape_alloc(t, job.S, job.op.B);
+    mrs_status st = tape_alloc(t, job.S, job.op.B, field);
     if (st != MRS_OK) {
         delete t;
         if (opt->tape_mode == MRS_TAPE_ON) return st;
@@ -641,7 +653,7 @@ mrs_status decide_tape(const Job &job, const mrs_options *opt, bool wanted, mrs_
 }
 
 Tape tape_view(const mrs_tape *t) {
-    return Tape{t->hit.as<float4>(), t->y.as<float4>(), t->rr.as<float>(), 0, t->samples};
+    return Tape{t->hit.as<float4>(), t->y.as<float4>(), t->rr.as<float>(), 0, t->samples, t->fm.as<float4>()};
 }
 
 // forward launch sequence (eager or under capture)
@@ -686,8 +698,11 @@ mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, co
         TRY(r.ct_hit.reserve(sizeof(float4) * n));
         TRY(r.ct_y.reserve(sizeof(float4) * n));
         TRY(r.ct_rr.reserve(sizeof(float) * n));
+        const bool field = sc->mat_mode == MRS_MAT_FIELD;
+        if (field) TRY(r.ct_fm.reserve(sizeof(float4) * n));
         for (const Chunk &ch : chunks) {
-            Tape tp{r.ct_hit.as<float4>(), r.ct_y.as<float4>(), r.ct_rr.as<float>(), ch.c0, cap};
+            Tape tp{r.ct_hit.as<float4>(), r.ct_y.as<float4>(), r.ct_rr.as<float>(), ch.c0, cap,
+                    field ? r.ct_fm.as<float4>() : nullptr};
             TRY(run_wavefront(j, ch, tp, 1, nullptr, r, s));
             TRY(adjoint(j, tp, ch.c0, ch.c1, dimg, grads, gl, rec, r, s));
         }
@@ -903,7 +918,7 @@ extern "C" void mrs_release_workspace(void) {
     g_ws.res.release_all();
     g_ws.uploaded.clear();
     std::lock_guard<std::mutex> lk2(g_spare.mu);
-    g_spare.hit.release(); g_spare.y.release(); g_spare.rr.release();
+    g_spare.hit.release(); g_spare.y.release(); g_spare.rr.release(); g_spare.fm.release();
     g_spare.device = -1;
 }
 
@@ -1022,6 +1037,7 @@ extern "C" mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *vi
             PTRY(p->res.ct_hit.alloc(sizeof(float4) * n));
             PTRY(p->res.ct_y.alloc(sizeof(float4) * n));
             PTRY(p->res.ct_rr.alloc(sizeof(float) * n));
+            if (scene->mat_mode == MRS_MAT_FIELD) PTRY(p->res.ct_fm.alloc(sizeof(float4) * n));
         }
     }
 #undef PTRY

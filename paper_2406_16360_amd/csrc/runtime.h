@@ -75,4 +75,5 @@ struct mrs_tape {
     mrs::DevBuf hit;          // float4 [B][S]: (b1, b2, leaf index, env texel)
     mrs::DevBuf y;            // float4 [B][S]: (y, W if the shadow ray was unoccluded else 0)
     mrs::DevBuf rr;           // float  [B][S]: continuation factor 1/q_rr (1 without roulette), 0 = path ended
+    mrs::DevBuf fm;           // float4 [B][S], field mode only: the field's output at the hit
 };

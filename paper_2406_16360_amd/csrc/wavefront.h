@@ -69,6 +69,7 @@ struct Tape {
     float *rr;     // [B][S]: continuation factor, 0 = path ended
     uint64_t base; // sample index of entry 0
     uint64_t S;    // samples per vertex slice
+    float4 *fm;    // field mode, when kept: [B][S] the field's output at the hit (else null)
 };
 
 struct ViewTable {
@@ -676,6 +677,7 @@ __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS
                 a.tape.hit[ti] = make_float4(b1, b2, __int_as_float(leaf), __int_as_float(ytex));
                 a.tape.y[ti] = make_float4(y.x, y.y, y.z, Wy);
                 a.tape.rr[ti] = cont ? rrf : 0.0f;
+                if (a.tape.fm) a.tape.fm[ti] = a.s.fm[i];
             }
         }
         if (a.hash) a.hash[g - a.out_base] ^= hev;
@@ -766,6 +768,7 @@ struct AdjArgs {
     int mat_on;            // some material gradient array is wanted
     float4 *gvtx;          // field mode: dL/d(field output) per path vertex, slot (k - 1) n + j
     int field_on;          // field mode: some field gradient array is wanted
+    uint64_t fm_stride;    // field mode: the field output of vertex (k, j) is s.fm[(k - 1) fm_stride + j]
 };
 
 // ---------------------------------------------------------------------------
@@ -866,7 +869,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
         dk[k - 1] = d;
         Surf S = surface(a.s, leaf, th.x, th.y, d);
         Interp ip;
-        Mat m = clamp_material(a.s.mat_mode == MRS_MAT_FIELD ? field_material(a.s.fm[(uint64_t)(k - 1) * a.n + j])
+        Mat m = clamp_material(a.s.mat_mode == MRS_MAT_FIELD ? field_material(a.s.fm[(uint64_t)(k - 1) * a.fm_stride + j])
                                                              : fetch_material(a.s, S.prim, th.x, th.y, ip));
         Lobe L = make_lobe(m, to_local(S.F, d * -1.0f), a.op.spec);
         float4 ty = a.tape.y[ti];
@@ -915,7 +918,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
             V3 dd = dk[k - 1];
             Surf S = surface(a.s, leaf, th.x, th.y, dd);
             const bool field = a.s.mat_mode == MRS_MAT_FIELD;
-            MatRaw raw = field ? field_material(a.s.fm[(uint64_t)(k - 1) * a.n + j])
+            MatRaw raw = field ? field_material(a.s.fm[(uint64_t)(k - 1) * a.fm_stride + j])
                                : fetch_material(a.s, S.prim, th.x, th.y, ip);
             Mat m = clamp_material(raw);
             Lobe L = make_lobe(m, to_local(S.F, dd * -1.0f), a.op.spec);
