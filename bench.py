@@ -48,9 +48,11 @@ HBM_PEAK_GBPS = 8000.0
 NODE_B, TRI_B, HIT_B, CAND_B, PIX_B, ENVG_B, VREC_B = 32, 36, 36, 20, 12, 24, 64
 # material field, per point: hit or tape record 16 B, triangle 36 B, 16
 # levels x 8 corners x 8 B of table entries, output 16 B; the pull-back adds
-# the read-modify-write of the same 128 entries
+# the read-modify-write of the same 128 entries; the output kept on the tape
+# for the backward is 16 B more per hit
 FIELD_B = 16 + 36 + 128 * 8 + 16
 FIELD_BWD_B = FIELD_B + 2 * 128 * 8
+FIELD_TAPE_B = 16
 
 
 def kernel_bytes(cnt, n, spp, tex, field=False, reuse_k=0, ris_m=32):
@@ -67,7 +69,8 @@ def kernel_bytes(cnt, n, spp, tex, field=False, reuse_k=0, ris_m=32):
                    + per["hits"] * VREC_B,
     }
     if field:
-        kb["field_eval"] = 2 * per["hits"] * FIELD_B          # forward pass and the adjoint's replay
+        kb["field_eval"] = per["hits"] * FIELD_B              # the forward pass (the tape keeps its output)
+        kb["shade"] += per["hits"] * FIELD_TAPE_B            # that output written to the tape
         kb["field_backward"] = per["hits"] * FIELD_BWD_B
     if reuse_k:
         # one more camera ray per sample, the initial RIS at its primary vertex,
@@ -458,8 +461,6 @@ def main():
         if args.mode == "fwd":
             kb.pop("adjoint")
             kb.pop("field_backward", None)
-            if "field_eval" in kb:
-                kb["field_eval"] /= 2                          # no adjoint replay
         balg = sum(kb.values())
         roof, kern = roofline_from(prof, kb, S, args.steps, args.workload)
         extra = {"path_roofline": {"alg_bytes_per_sample": balg,
