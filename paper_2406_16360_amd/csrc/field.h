@@ -371,7 +371,11 @@ void k_field_backward(FieldDev f, Src src, const float *__restrict__ g, FieldGra
     for (int o = 0; o < kFieldOut; ++o) w2h[o] = f.w2[o * kFieldHidden + hid];
     f32x16 gw1 = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     float gw2[kFieldOut] = {0.0f, 0.0f, 0.0f, 0.0f}, gb2[kFieldOut] = {0.0f, 0.0f, 0.0f, 0.0f}, gb1 = 0.0f;
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // each block walks a contiguous range of tiles: with the points in Morton
+    // order its tiles are neighbours, so their table lines stay in cache
+    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t tb = blockIdx.x * per, te = tb + per < ntiles ? tb + per : ntiles;
+    for (uint64_t t = tb; t < te; ++t) {
         const uint64_t i = t * kFieldTile + hid;
         V3 x = V3{0, 0, 0};
         bool valid = src.get(i, x);
