@@ -96,7 +96,7 @@ struct ProfScope {
 // jobs and buffers
 // ============================================================================
 constexpr uint64_t kOutChunkMax = 1ull << 26;   // samples per super-chunk of the output buffer
-constexpr uint32_t kPoolDefault = 1u << 23;      // paths in flight
+constexpr uint32_t kPoolDefault = 1u << 25;      // paths in flight (160 B each: 5.4 GB at the default)
 constexpr int kBlockDefault = 64;                // threads per workgroup of the trace and shade kernels
 constexpr uint64_t kTapeRecBytes = 36;           // tape bytes per path vertex
 constexpr uint64_t kTapeFieldBytes = 16;         // and, in field mode, the field's output at the vertex
