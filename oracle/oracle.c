@@ -73,7 +73,9 @@ static void cross3(const double a[3], const double b[3], double r[3]) {
 }
 static void sub3(const double a[3], const double b[3], double r[3]) { r[0] = a[0]-b[0]; r[1] = a[1]-b[1]; r[2] = a[2]-b[2]; }
 static void normalize3(double a[3]) { double l = sqrt(dot3(a, a)); a[0] /= l; a[1] /= l; a[2] /= l; }
-static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+/* clamp to [lo, hi]; NaN (no order) goes to lo: a material value that is
+ * not a number takes the lower end of its range */
+static double clampd(double x, double lo, double hi) { return !(x >= lo) ? lo : (x > hi ? hi : x); }
 
 /* ------------------------------------------------------------------ */
 /* dual numbers (value, derivative) for forward-mode differentiation   */
@@ -86,9 +88,10 @@ static dual dmul(dual a, dual b) { dual r = { a.v * b.v, a.d * b.v + a.v * b.d }
 static dual ddiv(dual a, dual b) { dual r = { a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v) }; return r; }
 static dual dscale(dual a, double s) { dual r = { a.v * s, a.d * s }; return r; }
 static dual dsqrt(dual a) { double s = sqrt(a.v); dual r = { s, s > 0 ? a.d / (2.0 * s) : 0.0 }; return r; }
-/* clamp with the derivative passed on the closed interval (torch.clamp rule) */
+/* clamp with the derivative passed on the closed interval (torch.clamp
+ * rule); NaN goes to lo with no derivative, as in clampd */
 static dual dclamp(dual a, double lo, double hi) {
-    if (a.v < lo) return dc(lo);
+    if (!(a.v >= lo)) return dc(lo);
     if (a.v > hi) return dc(hi);
     return a;
 }
@@ -940,9 +943,11 @@ static void material_plain(const orc_ctx *c, const interp *ip, double m[5]) {
     for (int i = 0; i < 5; ++i) m[i] = md[i].v;
 }
 
+/* env radiance max(0, L) with its derivative on L >= 0; a NaN channel is
+ * radiance 0 with no derivative, like a negative one */
 static dual env_d(const orc_ctx *c, int32_t texel, int ch, seed_t sd) {
     dual x = param_value(c, PK_ENV, (int64_t)texel * 3 + ch, sd);
-    if (x.v < 0.0) return dc(0.0);
+    if (!(x.v >= 0.0)) return dc(0.0);
     return x;
 }
 
@@ -991,6 +996,22 @@ static void camera_ray(const orc_view *vw, int x, int y, double u0, double u1, d
     normalize3(d);
 }
 
+/* Conditioning hook (orc_options.jitter): unit vector d moved by up to
+ * jitter x 2^-24 per component and renormalised, from the Philox stream of
+ * (pixel, sample, view, vertex k, block 0xC000 + slot) under key jitter_seed:
+ * slot 0 the camera ray, 1 the geometric normal, 2 the continuation
+ * direction, 16 + s candidate s.  It stands for the rounding an FP32
+ * evaluation of the same path commits. */
+static void jitter_unit(const orc_options *opt, uint32_t pixel, uint32_t sc, uint32_t vi, int k, uint32_t slot,
+                        double d[3]) {
+    if (!(opt->jitter > 0.0)) return;
+    double u[4];
+    uniforms4(opt->jitter_seed, pixel, sc, vi, (uint32_t)k, 0xC000u + slot, u);
+    const double eps = opt->jitter * (1.0 / 16777216.0);
+    for (int a = 0; a < 3; ++a) d[a] += eps * (2.0 * u[a] - 1.0);
+    normalize3(d);
+}
+
 /* Shading point of a surface hit (Sec. 3 "Rendering"): position from the
  * barycentrics, geometric normal turned towards the viewer, shading frame and
  * clamped material. */
@@ -1016,6 +1037,14 @@ static void shading_point(const orc_ctx *c, const hitrec *hr, const double d[3],
         interp ip; material_interp(c, hr->prim, hr->b1, hr->b2, &ip);
         material_plain(c, &ip, S->m);
     }
+}
+
+/* the normal of shading point S of vertex k after the conditioning hook,
+ * and its frame */
+static void jitter_normal(const orc_options *opt, uint32_t pixel, uint32_t sc, uint32_t vi, int k, shpt *S) {
+    if (!(opt->jitter > 0.0)) return;
+    jitter_unit(opt, pixel, sc, vi, k, 1, S->n);
+    orc_frame(S->n, S->t, S->b);
 }
 
 /* RIS over Me env + Mb BRDF candidates with a streaming weighted reservoir
@@ -1044,11 +1073,15 @@ static void ris_vertex(const orc_ctx *c, const shpt *S, const orc_options *opt, 
         int ok;
         if (s < Me) {
             ok = env_sample(c, u[0], u[1], w, &qe, &tex);
-            if (ok) qb = mix_pdf(S->n, S->wo, w, S->m, spec);
+            if (ok) {
+                jitter_unit(opt, pixel, sc, vi, k, 16u + (uint32_t)s, w);
+                qb = mix_pdf(S->n, S->wo, w, S->m, spec);
+            }
         } else {
             int lb = mix_sample(S->n, S->t, S->b, S->wo, S->m, spec, u[0], u[1], u[2], w);
             ok = lb != 0;
             if (ok) {
+                jitter_unit(opt, pixel, sc, vi, k, 16u + (uint32_t)s, w);
                 qb = mix_pdf(S->n, S->wo, w, S->m, spec);
                 qe = env_pdf_dir(c, w);
                 tex = env_texel_of(c, w);
@@ -1141,10 +1174,12 @@ static int primary_vertex(const orc_ctx *c, const orc_view *views, int32_t vi, i
     double u[4], o[3], d[3];
     uniforms4(opt->seed, (uint32_t)pixel, sc, (uint32_t)vi, 0, 0, u);
     camera_ray(vw, pixel % vw->w, pixel / vw->w, u[0], u[1], o, d);
+    jitter_unit(opt, (uint32_t)pixel, sc, (uint32_t)vi, 0, 0, d);
     cnt[ORC_C_CLOSEST_RAYS]++;
     hitrec hr = trace_closest(c, o, d, 0, &cnt[ORC_C_CLOSEST_NODES], &cnt[ORC_C_CLOSEST_TRIS]);
     if (hr.prim < 0) return 0;
     shading_point(c, &hr, d, 0, S);
+    jitter_normal(opt, (uint32_t)pixel, sc, (uint32_t)vi, 1, S);
     risres rr;
     ris_vertex(c, S, opt, (uint32_t)pixel, sc, (uint32_t)vi, 1, &rr, h, cnt);
     for (int a = 0; a < 3; ++a) r0->y[a] = rr.y[a];
@@ -1242,6 +1277,7 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
     uniforms4(opt->seed, (uint32_t)pixel, S, (uint32_t)vi, 0, 0, u);
     double o[3], d[3];
     camera_ray(vw, pixel % vw->w, pixel / vw->w, u[0], u[1], o, d);
+    jitter_unit(opt, (uint32_t)pixel, S, (uint32_t)vi, 0, 0, d);
     double T[3] = { 1, 1, 1 };
     rgb[0] = rgb[1] = rgb[2] = 0.0;
     uint32_t h = 0;
@@ -1269,6 +1305,7 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
         V->nee = 0; V->W = 0.0; V->ytex = -1; V->q = 0.0; V->rr = 1.0;
         shpt Sp;
         shading_point(c, &hr, d, rec->nv - 1, &Sp);
+        jitter_normal(opt, (uint32_t)pixel, S, (uint32_t)vi, k, &Sp);
         for (int a = 0; a < 3; ++a) { V->p[a] = Sp.p[a]; V->n[a] = Sp.n[a]; V->wo[a] = Sp.wo[a]; }
         const double *m = Sp.m;
         double pn = fmax(fabs(V->p[0]), fmax(fabs(V->p[1]), fabs(V->p[2])));
@@ -1315,6 +1352,7 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
         uniforms4(opt->seed, (uint32_t)pixel, S, (uint32_t)vi, (uint32_t)k, 0xFFFFu, u);
         double wi[3];
         int lobe = co > 0.0 ? mix_sample(V->n, Sp.t, Sp.b, V->wo, m, spec, u[0], u[1], u[2], wi) : 0;
+        if (lobe) jitter_unit(opt, (uint32_t)pixel, S, (uint32_t)vi, k, 2, wi);
         double q = lobe ? mix_pdf(V->n, V->wo, wi, m, spec) : 0.0;
         if (!lobe || !(q > 0.0)) { h ^= ev_vertex((uint32_t)k, (uint32_t)hr.prim, (uint32_t)sel, 2u); break; }
         double f[3];
@@ -1386,6 +1424,7 @@ static int check_args(const orc_ctx *c, const orc_view *views, int32_t nviews, c
         opt->ris_m_brdf > opt->ris_m) return -1;
     if (opt->reuse && (opt->reuse->spatial < 0 || opt->reuse->spatial > ORC_REUSE_MAXK || opt->reuse->radius < 1 ||
                        opt->reuse->radius > 64 || opt->reuse->m_cap < 1)) return -1;
+    if (!(opt->jitter >= 0.0) || opt->jitter > 1e6) return -1;
     for (int64_t i = 0; i < n; ++i) {
         int32_t v = items[3 * i], p = items[3 * i + 1], s = items[3 * i + 2];
         if (v < 0 || v >= nviews) return -1;

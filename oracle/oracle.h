@@ -116,6 +116,12 @@ typedef struct {
     int32_t  background;   /* 0: env radiance on primary miss, 1: black */
     int32_t  grad_mode;    /* 0: full path, 1: primary vertex only */
     const orc_reuse *reuse; /* nullable: no reuse */
+    /* Test hook for conditioning studies: every unit vector the path derives
+     * (camera ray, geometric normal, candidate and continuation directions)
+     * moves by up to `jitter` units of 2^-24 per component, from a Philox
+     * stream keyed by jitter_seed, and is renormalised.  0: no change. */
+    double   jitter;
+    uint64_t jitter_seed;
 } orc_options;
 
 enum { ORC_C_CLOSEST_RAYS = 0, ORC_C_CLOSEST_NODES, ORC_C_CLOSEST_TRIS,

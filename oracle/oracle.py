@@ -46,7 +46,8 @@ class _Reuse(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("bounces", C.c_int32), ("ris_m", C.c_int32), ("ris_m_brdf", C.c_int32),
                 ("rr_start", C.c_int32), ("seed", C.c_uint64), ("brdf", C.c_int32),
-                ("background", C.c_int32), ("grad_mode", C.c_int32), ("reuse", C.c_void_p)]
+                ("background", C.c_int32), ("grad_mode", C.c_int32), ("reuse", C.c_void_p),
+                ("jitter", C.c_double), ("jitter_seed", C.c_uint64)]
 
 
 _lib = None
@@ -149,9 +150,12 @@ def reuse_struct(o, prev: Optional[np.ndarray] = None, out: Optional[np.ndarray]
 
 
 def options_struct(o, reuse: Optional[_Reuse] = None) -> _Options:
+    """The C options; `jitter` / `jitter_seed` attributes of `o`, when
+    present, switch on the conditioning hook (orc_options.jitter)."""
     return _Options(int(o.bounces), int(o.ris_m), int(o.ris_m_brdf), int(o.rr_start), int(o.seed),
                     int(o.brdf), int(o.background), int(o.grad_mode),
-                    C.addressof(reuse) if reuse is not None else None)
+                    C.addressof(reuse) if reuse is not None else None,
+                    float(getattr(o, "jitter", 0.0)), int(getattr(o, "jitter_seed", 0)) & (2 ** 64 - 1))
 
 
 class FieldRef:

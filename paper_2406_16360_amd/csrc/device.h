@@ -281,6 +281,8 @@ struct EnvTables {
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
     const double *total;    // device: total sampling weight (no valid sample when 0)
+    const double *rcos;     // [H + 1] cos(i pi / H): the direction's y at the edge above row i
+    const double2 *csphi;   // [W + 1] (cos, sin) of phi_j = pi (2 j / W - 1): the edge left of column j
 };
 
 // the marginal intervals and guide, from the tables or from a copy in LDS
@@ -289,13 +291,35 @@ struct MargView {
     const int32_t *guide;
 };
 
+// Nearest texel of direction d.  theta is atan2(sin theta, d_y) with
+// sin theta = sqrt(d_x^2 + d_z^2): acos(d_y) (and 1 - d_y^2) lose most of
+// their digits to cancellation near the poles.  The float mapping decides,
+// except within kTexEdge of a texel width from a row or column edge: there
+// the float value of u W or v H (atan2f and the scaling round it by up to
+// ~1e-4 of a texel width) can land on the wrong side, so the side is settled
+// in double against the edge itself.  theta >= i pi / H iff d_y <= cos(i pi / H), and
+// phi >= phi_j iff d_x cos(phi_j) + d_z sin(phi_j) >= 0 (phi = atan2(d_x,
+// -d_z) within pi of phi_j, which holds next to the float estimate).  The
+// seam at phi = +-pi and the poles keep the clamped float estimate.
+constexpr float kTexEdge = 2e-3f;
 __device__ __forceinline__ int env_texel_of(const EnvTables &e, V3 d) {
     float dy = fminf(fmaxf(d.y, -1.0f), 1.0f);
-    float theta = acosf(dy), phi = atan2f(d.x, -d.z);
-    float u = phi * (0.5f * kInvPi) + 0.5f, v = theta * kInvPi;
-    int col = (int)floorf(u * (float)e.W), row = (int)floorf(v * (float)e.H);
-    col = min(max(col, 0), e.W - 1);
-    row = min(max(row, 0), e.H - 1);
+    float theta = atan2f(sqrtf(d.x * d.x + d.z * d.z), d.y), phi = atan2f(d.x, -d.z);
+    float x = (phi * (0.5f * kInvPi) + 0.5f) * (float)e.W, v = theta * kInvPi * (float)e.H;
+    float fx = floorf(x), fv = floorf(v);
+    float rx = x - fx, rv = v - fv;
+    int col = min(max((int)fx, 0), e.W - 1), row = min(max((int)fv, 0), e.H - 1);
+    if (rx < kTexEdge || rx > 1.0f - kTexEdge) {
+        int j = (int)fx + (rx < 0.5f ? 0 : 1);    // the nearest column edge
+        if (j > 0 && j < e.W) {
+            const double2 cs = e.csphi[j];
+            col = ((double)d.x * cs.x + (double)d.z * cs.y >= 0.0) ? j : j - 1;
+        }
+    }
+    if (rv < kTexEdge || rv > 1.0f - kTexEdge) {
+        int i = (int)fv + (rv < 0.5f ? 0 : 1);    // the nearest row edge
+        if (i > 0 && i < e.H) row = ((double)dy <= e.rcos[i]) ? i : i - 1;
+    }
     return row * e.W + col;
 }
 
@@ -307,7 +331,7 @@ __device__ __forceinline__ bool env_valid(const EnvTables &e) { return *e.total 
 // ok = env_valid(e)
 __device__ __forceinline__ float env_pdf_dir(bool ok, V3 d, float4 lp) {
     if (!ok) return 0.0f;
-    float st = sqrtf(fmaxf(0.0f, 1.0f - d.y * d.y));
+    float st = sqrtf(d.x * d.x + d.z * d.z);   // sin theta without the cancellation of 1 - d_y^2 near the poles
     return st > 0.0f ? lp.w / st : 0.0f;
 }
 

@@ -107,7 +107,7 @@ struct Chunk { uint64_t c0, c1, pix0, pix1; };
 // Device buffers one launch sequence works in: the library's shared
 // workspace for eager calls, or a plan's own set.
 struct Res {
-    DevBuf wts, cond, marg, rowsum, info, lp, gmarg, gcond, mpair, cpair;   // environment tables
+    DevBuf wts, cond, marg, rowsum, info, lp, gmarg, gcond, mpair, cpair, rcos, csphi;   // environment tables
     DevBuf views;                                              // ViewDev table
     DevBuf qa_o, qa_d, qa_t, qb_o, qb_d, qb_t, hits, so, sd, sc; // path pool queues
     DevBuf ctr, sched, out;                                    // iteration counters, scheduler, sample radiance
@@ -118,7 +118,7 @@ struct Res {
     DevBuf fkey, fkey2, fval, fval2, fsort;                    // field mode: pull-back order (keys, values, sort scratch)
     DevBuf tpack;                                              // texture mode: interleaved texel records
     void release_all() {
-        for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &views, &qa_o, &qa_d, &qa_t, &qb_o,
+        for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &rcos, &csphi, &views, &qa_o, &qa_d, &qa_t, &qb_o,
                           &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &ct_fm, &grec, &fm, &fvtx, &gvtx,
                           &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort, &tpack})
             b->release();
@@ -272,6 +272,10 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
         P += (uint64_t)v.w * v.h;
     }
     if (S >= (1ull << 32)) return fail(MRS_EOVERFLOW, "%llu samples exceed 2^32 - 1 per call", (unsigned long long)S);
+    if (job.reuse.prev && job.reuse.out) {
+        const uintptr_t a = (uintptr_t)job.reuse.prev, b = (uintptr_t)job.reuse.out, nb = sizeof(float) * 8 * S;
+        if (a < b + nb && b < a + nb) return fail(MRS_EINVAL, "reservoir_out overlaps reservoir_prev");
+    }
     job.S = S;
     job.pixels = P;
     job.op.B = op->bounces; job.op.M = op->ris_m; job.op.Mb = op->ris_m_brdf; job.op.rr_start = op->rr_start;
@@ -347,6 +351,8 @@ mrs_status reserve_env(const mrs_scene *sc, Res &r) {
     TRY(r.gcond.reserve(sizeof(int32_t) * nt));
     TRY(r.mpair.reserve(sizeof(double2) * H));
     TRY(r.cpair.reserve(sizeof(double2) * nt));
+    TRY(r.rcos.reserve(sizeof(double) * (H + 1)));
+    TRY(r.csphi.reserve(sizeof(double2) * (W + 1)));
     return MRS_OK;
 }
 
@@ -391,12 +397,14 @@ mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
         k_env_marg<<<1, 64, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
         k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.info.as<double>(), r.marg.as<double>(),
                                             r.cond.as<double>(), r.lp.as<float4>(), r.gmarg.as<int32_t>(),
-                                            r.gcond.as<int32_t>(), r.mpair.as<double2>(), r.cpair.as<double2>());
+                                            r.gcond.as<int32_t>(), r.mpair.as<double2>(), r.cpair.as<double2>(),
+                                            r.rcos.as<double>(), r.csphi.as<double2>());
     }
     EnvTables &e = job.sd.env;
     e.mpair = r.mpair.as<double2>(); e.cpair = r.cpair.as<double2>();
     e.gmarg = r.gmarg.as<int32_t>(); e.gcond = r.gcond.as<int32_t>();
     e.lp = r.lp.as<float4>(); e.raw = sc->env; e.total = r.info.as<double>();
+    e.rcos = r.rcos.as<double>(); e.csphi = r.csphi.as<double2>();
     e.W = W; e.H = H;
     return MRS_OK;
 }
@@ -441,7 +449,7 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
         }
         if (field) {
             PROF(KID_FIELD, s);
-            PointsHits src{r.hits.as<float4>(), job.sd.tris, ctr, it};
+            PointsHits src{r.hits.as<float4>(), job.sd.tris, ctr, it, qa.o, qa.d};
             k_field_eval<PointsHits><<<nblocks(P, kFieldTile), 64, 0, s>>>(job.fd, src, r.fm.as<float>());
         }
         {

@@ -109,7 +109,9 @@ __global__ void k_reuse_primary(ReuseArgs a) {
     V3 o, d;
     camera_ray(vw, sid.pixel, u.x, u.y, o, d);
     const Hit h = trace_closest(a.s.nodes, a.s.tris, o, d, lds_stack);
-    a.prim[g] = make_float4(h.b1, h.b2, __int_as_float(h.leaf >= 0 ? h.leaf : -1), 0.0f);
+    float b1 = h.b1, b2 = h.b2;
+    if (h.leaf >= 0) refine_hit(a.s.tris[h.leaf], o, d, b1, b2);
+    a.prim[g] = make_float4(b1, b2, __int_as_float(h.leaf >= 0 ? h.leaf : -1), 0.0f);
 }
 
 // kMargLds: the env's marginal intervals and guide go to LDS first, as in

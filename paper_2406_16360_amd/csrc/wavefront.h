@@ -146,11 +146,17 @@ __device__ __forceinline__ MatRaw fetch_material(const SceneDev &s, int prim, fl
         m.mu = bary(p0[4], p1[4], p2[4], b1, b2);
         return m;
     }
-    float u = bary(s.uv[2 * v0], s.uv[2 * v1], s.uv[2 * v2], b1, b2);
-    float v = bary(s.uv[2 * v0 + 1], s.uv[2 * v1 + 1], s.uv[2 * v2 + 1], b1, b2);
-    float x = u * (float)s.tw - 0.5f, y = v * (float)s.th - 0.5f;
-    float x0 = floorf(x), y0 = floorf(y);
-    float fx = x - x0, fy = y - y0;
+    // uv and the texel coordinates in double: in float, u itself is held to
+    // 2^-24, which is 2.4e-4 of a texel of a 4096-wide texture, enough to move
+    // a small bilinear weight by several percent of itself
+    const double db1 = b1, db2 = b2;
+    const double u0 = s.uv[2 * v0], u1 = s.uv[2 * v1], u2 = s.uv[2 * v2];
+    const double w0 = s.uv[2 * v0 + 1], w1 = s.uv[2 * v1 + 1], w2 = s.uv[2 * v2 + 1];
+    const double u = u0 + db1 * (u1 - u0) + db2 * (u2 - u0);
+    const double v = w0 + db1 * (w1 - w0) + db2 * (w2 - w0);
+    const double x = u * (double)s.tw - 0.5, y = v * (double)s.th - 0.5;
+    const double x0 = floor(x), y0 = floor(y);
+    const float fx = (float)(x - x0), fy = (float)(y - y0);
     int i0 = wrapi((int)x0, s.tw), i1 = wrapi((int)x0 + 1, s.tw);
     int j0 = wrapi((int)y0, s.th), j1 = wrapi((int)y0 + 1, s.th);
     ip.n = 4;
@@ -196,6 +202,29 @@ __device__ __forceinline__ Mat clamp_material(const MatRaw &r) {
     return m;
 }
 
+// Barycentrics (b1, b2) of the point where the ray o + t d meets the plane
+// of triangle (a, b, c), in double (Moeller and Trumbore, JGT 1997).  The
+// traversal's float test decides which triangle is hit; its float
+// barycentrics carry a few ulps of the coordinates relative to the
+// triangle's size (1e-4 for a 1e-3-wide triangle three units away), which a
+// fine texture's bilinear weights then magnify.  Every consumer of a hit
+// (shading, the field pass, the reuse pass) refines it the same way from the
+// same ray, so they agree.  A ray parallel to the plane keeps the inputs.
+__device__ __forceinline__ void refine_hit(const TriRec &tr, V3 o, V3 d, float &b1, float &b2) {
+    const double ax = tr.a.x, ay = tr.a.y, az = tr.a.z;
+    const double e1x = (double)tr.b.x - ax, e1y = (double)tr.b.y - ay, e1z = (double)tr.b.z - az;
+    const double e2x = (double)tr.c.x - ax, e2y = (double)tr.c.y - ay, e2z = (double)tr.c.z - az;
+    const double dx = d.x, dy = d.y, dz = d.z;
+    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const double det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0) return;
+    const double inv = 1.0 / det;
+    const double sx = (double)o.x - ax, sy = (double)o.y - ay, sz = (double)o.z - az;
+    const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    b1 = (float)((sx * px + sy * py + sz * pz) * inv);
+    b2 = (float)((dx * qx + dy * qy + dz * qz) * inv);
+}
+
 // hit position from the leaf-order triangle and barycentrics (as surface())
 __device__ __forceinline__ V3 hit_point(const TriRec *__restrict__ tris, int leaf, float b1, float b2) {
     TriRec tr = tris[leaf];
@@ -208,6 +237,7 @@ __device__ __forceinline__ V3 hit_point(const TriRec *__restrict__ tris, int lea
 // continued the path and its own entry is a hit).
 struct PointsHits {
     const float4 *hits; const TriRec *tris; const IterCtr *ctr; int it;
+    const float4 *qo, *qd;   // the iteration's rays (refined barycentrics, as in shading)
     __device__ __forceinline__ uint64_t count() const { return ctr[it].n_live; }
     __device__ __forceinline__ uint64_t gindex(uint64_t i) const { return i; }
     __device__ __forceinline__ bool get(uint64_t i, V3 &p) const {
@@ -215,7 +245,9 @@ struct PointsHits {
         const float4 h = hits[i];
         const int leaf = __float_as_int(h.w);
         if (leaf < 0) return false;
-        p = hit_point(tris, leaf, h.y, h.z);
+        float b1 = h.y, b2 = h.z;
+        refine_hit(tris[leaf], xyz(qo[i]), xyz(qd[i]), b1, b2);
+        p = hit_point(tris, leaf, b1, b2);
         return true;
     }
 };
@@ -346,7 +378,8 @@ __global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__r
 __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
                              const double *__restrict__ info, const double *__restrict__ marg,
                              const double *__restrict__ cond, float4 *__restrict__ lp, int32_t *__restrict__ gmarg,
-                             int32_t *__restrict__ gcond, double2 *__restrict__ mpair, double2 *__restrict__ cpair) {
+                             int32_t *__restrict__ gcond, double2 *__restrict__ mpair, double2 *__restrict__ cpair,
+                             double *__restrict__ rcos, double2 *__restrict__ csphi) {
     int i = blockIdx.x;
     double total = info[0];
     // the CDFs as intervals (cdf[t], cdf[t + 1])
@@ -374,6 +407,13 @@ __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const 
             int lo = 0, hi = H - 1;
             while (lo < hi) { int mid = (lo + hi) >> 1; if (marg[mid + 1] > t) hi = mid; else lo = mid + 1; }
             gmarg[t0] = lo;
+        }
+        // texel edges of the direction -> texel mapping
+        for (int t0 = threadIdx.x; t0 <= H; t0 += blockDim.x) rcos[t0] = cospi((double)t0 / H);
+        for (int t0 = threadIdx.x; t0 <= W; t0 += blockDim.x) {
+            double sn, cs;
+            sincospi(2.0 * (double)t0 / W - 1.0, &sn, &cs);
+            csphi[t0] = make_double2(cs, sn);
         }
     }
 }
@@ -618,6 +658,7 @@ __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS
             SampleId sid = decode(a.vt, g);
             Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
             float b1 = hr.y, b2 = hr.z;
+            refine_hit(a.s.tris[leaf], xyz(po), d, b1, b2);
             Surf S = surface(a.s, leaf, b1, b2, d);
             Interp ip;
             Mat m = clamp_material(a.s.mat_mode == MRS_MAT_FIELD ? field_material(a.s.fm[i])
@@ -784,8 +825,16 @@ struct AdjArgs {
 // into the caller's arrays.
 // ---------------------------------------------------------------------------
 constexpr int kMatRec = 8, kEnvRec = 4;
-constexpr int kScatSlots = 13;   // pairs a lane stages per flush
+constexpr int kMatChannels = 5;      // albedo rgb, roughness, metallic per interpolation entry
+constexpr int kEnvChannels = 3;      // rgb per env texel
+constexpr int kEntriesPerFlush = 2;  // interpolation entries a lane stages per flush
+constexpr int kScatSlots = 13;       // pairs a lane stages per flush
 constexpr int kAdjBlock = 256;
+// The largest flush of a vertex: kEntriesPerFlush entries of every material
+// channel plus the env texel.  put() drops pairs past kScatSlots, so this
+// bound is what keeps the scatter lossless.
+static_assert(kScatSlots >= kEntriesPerFlush * kMatChannels + kEnvChannels,
+              "a flush stages more pairs than a lane has slots");
 
 struct WaveScatter {
     uint32_t *off;       // this wavefront's staging in LDS: [64][kScatSlots] offsets,
@@ -820,12 +869,12 @@ struct WaveScatter {
 
 // material pairs of interpolation entries q0 and q1 (those that exist)
 __device__ __forceinline__ void put_material(WaveScatter &ws, const Interp &ip, int q0, const float *gm) {
-    for (int q = q0; q < q0 + 2 && q < ip.n; ++q) {
+    for (int q = q0; q < q0 + kEntriesPerFlush && q < ip.n; ++q) {
         const float w = ip.w[q];
         if (w == 0.0f) continue;
         const uint32_t base = kMatRec * (uint32_t)ip.idx[q];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) ws.put(base + c, w * gm[c]);
+        for (int c = 0; c < kMatChannels; ++c) ws.put(base + c, w * gm[c]);
     }
 }
 
@@ -969,6 +1018,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
             T = T * Bk[k - 1];
         }
         // group 1: interpolation entries 0 and 1, and the env texel
+        static_assert(kEntriesPerFlush == 2, "the two groups below cover the four bilinear entries");
         if (has && a.mat_on) put_material(ws, ip, 0, gm);
         if (etex >= 0 && a.genv) {
             const float *raw = a.s.env.raw + 3 * (size_t)etex;
@@ -979,13 +1029,13 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
         }
         ws.flush();
         // group 2: interpolation entries 2 and 3
-        if (has && a.mat_on) put_material(ws, ip, 2, gm);
+        if (has && a.mat_on) put_material(ws, ip, kEntriesPerFlush, gm);
         ws.flush();
     }
 }
 
 // one thread per sample, every lane in the vertex loop of the scatter
-__global__ void __launch_bounds__(kAdjBlock) k_adjoint(AdjArgs a) {
+__global__ void __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint(AdjArgs a) {
     __shared__ uint32_t s_off[kAdjBlock * kScatSlots];
     __shared__ float s_val[kAdjBlock * kScatSlots];
     __shared__ int s_cnt[kAdjBlock];

@@ -180,6 +180,26 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else t.data_ptr()
 
 
+def _need(t: Optional[torch.Tensor], name: str, shape, dtype=torch.float32) -> None:
+    """Caller-supplied buffers the kernels write or read by element count:
+    contiguous GPU tensors of exactly this dtype and shape (None passes)."""
+    if t is None:
+        return
+    shape = tuple(int(x) for x in shape)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous() \
+            or tuple(t.shape) != shape:
+        got = (f"{'cuda' if t.is_cuda else 'cpu'} {t.dtype} {tuple(t.shape)} "
+               f"{'contiguous' if t.is_contiguous() else 'strided'}") if isinstance(t, torch.Tensor) else type(t)
+        raise ValueError(f"mirres: {name} must be a contiguous {dtype} GPU tensor of shape {shape}, got {got}")
+
+
+def _overlap(a: Optional[torch.Tensor], b: Optional[torch.Tensor]) -> bool:
+    if a is None or b is None:
+        return False
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    return a0 < b0 + b.numel() * b.element_size() and b0 < a0 + a.numel() * a.element_size()
+
+
 @dataclasses.dataclass
 class RenderOptions:
     bounces: int = 3
@@ -384,6 +404,28 @@ class GpuScene:
                       _ptr(self.metal), tw, th, _ptr(self.env), self.env.shape[1], self.env.shape[0],
                       self.field.struct() if self.field is not None else _Field())
 
+    def param_shapes(self) -> Dict[str, Tuple[int, ...]]:
+        """Shapes of the parameter groups a gradient dict may hold."""
+        sh = {"env": tuple(self.env.shape)}
+        if self.mat_mode == MAT_VERTEX:
+            sh["vmat"] = tuple(self.vmat.shape)
+        elif self.mat_mode == MAT_FIELD:
+            sh.update({k: tuple(getattr(self.field, k).shape) for k in FIELD_KEYS})
+        else:
+            sh.update(albedo=tuple(self.albedo.shape), rough=tuple(self.rough.shape), metal=tuple(self.metal.shape))
+        return sh
+
+    def check_grads(self, grads: Dict[str, Optional[torch.Tensor]]) -> None:
+        """Every gradient buffer matches its parameter group (the adjoint
+        adds into each element); unknown keys are an error."""
+        sh = self.param_shapes()
+        for k, t in grads.items():
+            if t is None:
+                continue
+            if k not in sh:
+                raise ValueError(f"mirres: no parameter group {k!r} in this scene (groups: {sorted(sh)})")
+            _need(t, f"grads[{k!r}]", sh[k])
+
     def zero_grads(self) -> Dict[str, torch.Tensor]:
         """Zeroed gradient buffers for every parameter of the scene."""
         g = {"env": torch.zeros_like(self.env)}
@@ -428,10 +470,15 @@ def render(scene: GpuScene, views: Sequence, opts, keep_tape: bool = False, debu
     o = RenderOptions.from_any(opts)
     vs, npix, _ = views_struct(views)
     dev = scene.pos.device
+    S = total_samples(views)
+    _need(out, "out", (npix, 3))
+    _need(reservoir_prev, "reservoir_prev", (S, 8))
+    _need(reservoir_out, "reservoir_out", (S, 8))
+    if _overlap(reservoir_prev, reservoir_out):
+        raise ValueError("mirres: reservoir_out must not share memory with reservoir_prev")
     img = out if out is not None else torch.empty((npix, 3), dtype=torch.float32, device=dev)
     dbg_rgb = dbg_hash = None
     if debug:
-        S = total_samples(views)
         dbg_rgb = torch.empty((S, 3), dtype=torch.float32, device=dev)
         dbg_hash = torch.empty((S,), dtype=torch.int32, device=dev)
     op = o.struct(dbg_rgb, dbg_hash, reservoir_prev, reservoir_out)
@@ -456,9 +503,14 @@ def render_backward(scene: GpuScene, views: Sequence, opts, grad_image: torch.Te
     tape, reservoir_prev must be the one the forward call used."""
     o = RenderOptions.from_any(opts)
     vs, npix, _ = views_struct(views)
-    gi = _dev(grad_image).reshape(npix, 3)
+    gi = _dev(grad_image)
+    if gi.numel() != 3 * npix:
+        raise ValueError(f"mirres: grad_image must hold {npix} x 3 values, got {tuple(grad_image.shape)}")
+    gi = gi.reshape(npix, 3)
+    _need(reservoir_prev, "reservoir_prev", (total_samples(views), 8))
     if grads is None:
         grads = scene.zero_grads()
+    scene.check_grads(grads)
     g = _grads_struct(grads)
     op = o.struct(reservoir_prev=reservoir_prev)
     sc = scene.struct()
@@ -501,6 +553,11 @@ class Plan:
             self.grad_image = torch.zeros_like(self.image)
             self.grads = scene.zero_grads()
             g = _grads_struct(self.grads)
+        S = total_samples(self.views)
+        _need(reservoir_prev, "reservoir_prev", (S, 8))
+        _need(reservoir_out, "reservoir_out", (S, 8))
+        if _overlap(reservoir_prev, reservoir_out):
+            raise ValueError("mirres: reservoir_out must not share memory with reservoir_prev")
         self.reservoir_prev, self.reservoir_out = reservoir_prev, reservoir_out   # bound: keep them alive
         op = self.opts.struct(self.dbg_rgb, self.dbg_hash, reservoir_prev, reservoir_out)
         sc = scene.struct()
@@ -662,13 +719,18 @@ class Denoiser:
         if nbytes < 0:
             raise MirresError(-1, "invalid denoiser views or parameters")
         self.work = torch.empty(((nbytes + 3) // 4,), dtype=torch.float32, device=self.normal.device)
+        self.generation = 0       # forwards run so far: the workspace holds the last one's state
 
     def forward(self, color: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         c = _dev(color)
+        if c.numel() != 3 * self.npix:
+            raise ValueError(f"mirres: color must hold {self.npix} x 3 values, got {tuple(color.shape)}")
+        _need(out, "out", tuple(c.shape))
         res = out if out is not None else torch.empty_like(c)
         _check(_lib.mrs_denoise(C.addressof(self.vs), self.nviews, C.byref(self.params), c.data_ptr(),
                                 self.normal.data_ptr(), self.position.data_ptr(), res.data_ptr(),
                                 self.work.data_ptr(), _stream(stream)))
+        self.generation += 1
         return res
 
     def backward(self, grad_out: torch.Tensor, stream=None) -> torch.Tensor:
@@ -684,14 +746,21 @@ class _DenoiseFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, color, den):
         ctx.den = den
-        return den.forward(color)
+        out = den.forward(color)
+        ctx.generation = den.generation
+        return out
 
     @staticmethod
     def backward(ctx, g):
+        if ctx.den.generation != ctx.generation:
+            raise RuntimeError("mirres: this Denoiser ran another forward after the one being differentiated; "
+                               "its workspace no longer holds that call's levels (use one Denoiser per "
+                               "denoised image in a graph)")
         return ctx.den.backward(g.contiguous()), None
 
 
 def denoise_autograd(color: torch.Tensor, den: "Denoiser") -> torch.Tensor:
-    """Differentiable denoise(color); the backward of each call uses the
-    workspace of that call, so do not run another forward before it."""
+    """Differentiable denoise(color).  The backward reads the Denoiser's
+    workspace, which holds the latest forward only: a second forward on the
+    same Denoiser before this call's backward makes that backward raise."""
     return _DenoiseFn.apply(color, den)

@@ -518,6 +518,26 @@ def sample_items(workload: Workload, n: int, seed: int) -> np.ndarray:
     return np.stack([vi, local // spp, local % spp], -1).astype(np.int32)
 
 
+def sample_pixels(workload: Workload, n: int, seed: int) -> np.ndarray:
+    """Seeded subset of (view, pixel) pairs, uniform over pixels, sorted."""
+    rng = np.random.default_rng(seed)
+    sizes = np.array([v.w * v.h for v in workload.views], np.int64)
+    cum = np.concatenate([[0], np.cumsum(sizes)])
+    g = np.sort(rng.choice(int(cum[-1]), size=min(n, int(cum[-1])), replace=False))
+    vi = np.searchsorted(cum, g, side="right") - 1
+    return np.stack([vi, g - cum[vi]], -1).astype(np.int32)
+
+
+def pixel_items(workload: Workload, pixels: np.ndarray) -> np.ndarray:
+    """Every sample of the given (view, pixel) pairs, pixel after pixel."""
+    pixels = np.asarray(pixels, np.int32).reshape(-1, 2)
+    spp = np.array([workload.views[v].spp for v in pixels[:, 0]], np.int64)
+    rep = np.repeat(np.arange(len(pixels)), spp)
+    first = np.concatenate([[0], np.cumsum(spp)[:-1]])
+    s = np.arange(int(spp.sum())) - np.repeat(first, spp)
+    return np.stack([pixels[rep, 0], pixels[rep, 1], s], -1).astype(np.int32)
+
+
 def all_items(workload: Workload) -> np.ndarray:
     out = []
     for vi, v in enumerate(workload.views):

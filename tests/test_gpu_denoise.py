@@ -113,3 +113,22 @@ def test_denoise_rejects_bad_parameters(mr):
         mr.Denoiser(views, z, z, levels=4)
     with pytest.raises(mr.MirresError):
         mr.Denoiser(views, z, z, sigma_rt=0.0)
+
+
+def test_denoise_autograd_refuses_a_stale_workspace(mr):
+    """Two differentiable denoises through one Denoiser: the first one's
+    backward would read the second one's levels, so it raises."""
+    views = VIEW_SETS["uneven"]
+    c, n, x = _buffers(15, views)
+    den = mr.Denoiser(views, torch.tensor(n, device="cuda"), torch.tensor(x, device="cuda"))
+    ct = torch.tensor(c, device="cuda", requires_grad=True)
+    a = mr.denoise_autograd(ct, den)
+    b = mr.denoise_autograd(ct * 2.0, den)
+    with pytest.raises(RuntimeError, match="another forward"):
+        a.sum().backward()
+    # the latest call still differentiates
+    ct.grad = None
+    b2 = mr.denoise_autograd(ct, den)
+    b2.sum().backward()
+    assert torch.isfinite(ct.grad).all()
+    del b

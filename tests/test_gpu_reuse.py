@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from paper_2406_16360_amd import synth
-from tests.parity import grad_report, within
+from tests.parity import PIXEL_FRAC, SPREAD_FACTOR, check_gradients, oracle_trials, within
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +56,12 @@ def _frame(mr, orc_mod, w, sc, orc, prev_g=None, prev_o=None, flip_prev=None):
     items = synth.all_items(w)
     o_rgb, o_h, o_res = orc.render(w.views, w.opts, items, prev=prev_o, reservoirs=True)
     flip = dh.cpu().numpy().view(np.uint32) != o_h
+    # the oracle with its conditioning hook on: decisions that change there are
+    # unstable, and the spread of its values widens the bar (tests/parity.py)
+    spread = np.zeros_like(o_rgb)
+    for o_t, h_t, _ in oracle_trials(orc, w.views, w.opts, items, prev=prev_o):
+        flip |= np.asarray(h_t) != o_h
+        spread = np.maximum(spread, np.abs(o_t - o_rgb))
     if flip_prev is not None:
         flip = flip | flip_prev
     nb = _neighbours(w, items, orc_mod)
@@ -64,29 +70,28 @@ def _frame(mr, orc_mod, w, sc, orc, prev_g=None, prev_o=None, flip_prev=None):
         if n and flip[np.array(n)].any():
             ext[i] = True
     return dict(g=drgb.cpu().numpy(), o=o_rgb, flip=ext, img=img.cpu().numpy(), out_g=out_g, out_o=o_res,
-                items=items, dh=dh)
+                items=items, dh=dh, spread=spread, o_h=o_h)
 
 
-def _check(r, label, frac=2e-3):
-    """Per-sample bar as for plain rendering; the final reservoirs of unflipped
-    samples agree.  Returns the mask to carry into the next frame: flips, and
-    records outside the bar (float32 sampling residue at grazing directions),
+def _check(r, label, frac=PIXEL_FRAC):
+    """Per-sample bar as for plain rendering (within 1e-4 relative / 1e-6
+    absolute, or within the oracle's own spread in the conditioning trials), every
+    sample outside it on an (extended) flip, at most `frac` of the samples
+    outside; the final reservoirs of unflipped samples agree.  Returns the
+    mask to carry into the next frame: flips, and records outside the bar,
     since the next frame merges them."""
-    ok = within(r["g"], r["o"])
+    plain = within(r["g"], r["o"])
+    ok = plain | (np.abs(r["g"] - r["o"]) <= SPREAD_FACTOR * r["spread"]).all(-1)
     bad = ~ok
-    print(f"[{label}] samples={len(ok)} not-ok={bad.sum()} flips(ext)={r['flip'].sum()} "
-          f"not-ok-without-flip={np.sum(bad & ~r['flip'])}", flush=True)
+    print(f"[{label}] samples={len(ok)} outside-bar={bad.sum()} unstable(ext)={r['flip'].sum()} "
+          f"outside-without-flip={np.sum(bad & ~r['flip'])} within-conditioning={np.sum(ok & ~plain)}", flush=True)
     og, oo = r["out_g"].cpu().numpy(), r["out_o"]
     for i in np.flatnonzero(bad & ~r["flip"])[:4]:
         rel = np.abs(r["g"][i] - r["o"][i]) / (np.abs(r["o"][i]) + 1e-12)
         print(f"   sample {i}: rel err {rel.max():.2e}  W gpu {og[i, 3]:.6g} oracle {oo[i, 3]:.6g}  "
               f"M {og[i, 4]:.0f}  |o| {np.abs(r['o'][i]).max():.3g}")
-    assert bad.mean() <= frac
-    # A reused direction that is grazing at the merging vertex makes cos W a
-    # product of a small and a large float32 factor whose relative errors are
-    # about ulp / cos; the residue without flips is held to 5e-4 of samples
-    # (2e-4 without reuse), with the reservoirs themselves equal.
-    assert np.sum(bad & ~r["flip"]) <= max(1, int(5e-4 * len(ok)))
+    assert np.sum(bad & ~r["flip"]) == 0, f"{label}: samples outside the bar without a flip"
+    assert bad.mean() <= frac, f"{label}: {bad.sum()} samples outside the bar"
     keep = ~r["flip"]
     assert np.array_equal(og[keep, 4], oo[keep, 4].astype(np.float32)), "merged confidences differ"
     wok = np.abs(og[:, 3] - oo[:, 3]) <= 1e-4 * np.abs(oo[:, 3]) + 1e-7
@@ -161,13 +166,12 @@ def test_reuse_gradient_matches_oracle(mr, orc_mod):
     gr = mr.render_backward(sc, w.views, w.opts, torch.tensor(gi, device="cuda"), tape=None,
                             reservoir_prev=r0["out_g"])
     dl = gi[pix_of_item].astype(np.float64) / w.views[0].spp
-    og = orc.grad(w.views, w.opts, items, dl, prev=prev_o)
+    got = {k: v.cpu().numpy() for k, v in gg.items()}
+    og = check_gradients(got, orc, w.views, w.opts, items, dl, "reuse-grad", prev=prev_o)
     for k in og:
-        a, c = gg[k].cpu().numpy(), gr[k].cpu().numpy()
-        bad, rms = grad_report(a, og[k])
-        print(f"[reuse-grad] {k}: rms={rms:.3e} bad={bad.sum()}/{bad.size} "
-              f"tape-vs-recompute={np.abs(a - c).max() / rms:.2e}", flush=True)
-        assert bad.mean() <= 1e-3, k
+        a, c = got[k], gr[k].cpu().numpy()
+        rms = np.sqrt(np.mean(og[k] ** 2)) + 1e-300
+        print(f"[reuse-grad] {k}: tape-vs-recompute={np.abs(a - c).max() / rms:.2e}", flush=True)
         assert np.abs(a - c).max() <= 1e-4 * rms, k
 
 

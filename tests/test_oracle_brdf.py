@@ -128,3 +128,22 @@ def test_frame_orthonormal(oracle_lib):
         assert np.allclose(M[2], n)
         assert np.allclose(M @ M.T, np.eye(3), atol=1e-12)
         assert abs(abs(np.linalg.det(M)) - 1.0) < 1e-12   # handedness is irrelevant
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3, 0.7, 1.0])
+def test_schlick_f0_metallic_blend_at_normal_incidence(oracle_lib, mu):
+    """At wo = wi = n the half vector is n, so the Schlick factor is F0 itself,
+    D(1) = 1 / (pi alpha^2) and G1 = 1 on both sides:
+    f = (1 - mu) a / pi + F0 / (4 pi alpha^2) with F0 = 0.04 (1 - mu) + mu a.
+    A blend with the weights swapped, or F0 without the albedo, fails for
+    0 < mu < 1 or for coloured albedo."""
+    for a, r in [((0.2, 0.5, 0.9), 0.5), ((1.0, 0.0, 0.35), 0.3), ((0.05, 0.6, 0.75), 0.9)]:
+        a = np.array(a)
+        alpha = r * r
+        f = oracle_lib.brdf_eval(N, N, N, [*a, r, mu], brdf=1)
+        f0 = 0.04 * (1.0 - mu) + mu * a
+        expect = (1.0 - mu) * a / np.pi + f0 / (4.0 * np.pi * alpha ** 2)
+        assert np.allclose(f, expect, rtol=1e-12, atol=0), (a, r, f, expect)
+        # the Lambert-only BRDF keeps the diffuse part alone
+        fl = oracle_lib.brdf_eval(N, N, N, [*a, r, mu], brdf=0)
+        assert np.allclose(fl, (1.0 - mu) * a / np.pi, rtol=1e-12, atol=0)
