@@ -313,6 +313,28 @@ mrs_status mrs_denoise_backward(const mrs_view *views, int32_t n_views, const mr
                                 const float *d_normal, const float *d_position, const float *d_work,
                                 const float *d_grad_out, float *d_grad_in, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * mrs_denoise forward without a caller workspace.  It computes the same
+ * image as mrs_denoise with the same arguments, allocates nothing and keeps
+ * no state for mrs_denoise_backward.
+ *   Scratch   The intermediate levels of one view live in a static device
+ *             array of MRS_DENOISE_SCRATCH_BYTES that each GPU the library
+ *             runs on holds until the process ends.  Views are filtered one
+ *             after another through it: a view needs 12 bytes per pixel for
+ *             two levels and 24 for three (none for one level), so a view of
+ *             up to 2,796,202 pixels fits at three levels.  Nothing in it needs
+ *             to start at zero.  Every call on a GPU shares that GPU's array:
+ *             calls that overlap on one GPU (other streams or threads) race and
+ *             must be serialised by the caller.
+ *   Buffers   As mrs_denoise; d_color_out must not overlap d_color_in.
+ * Errors: as mrs_denoise, plus MRS_EOVERFLOW (a view beyond the scratch
+ * limit, checked before any GPU work) and MRS_EHIP. */
+#define MRS_DENOISE_SCRATCH_BYTES (64ll << 20)
+mrs_status mrs_denoise_noalloc(const mrs_view *views, int32_t n_views, const mrs_denoise_params *p,
+                               const float *d_color_in, const float *d_normal, const float *d_position,
+                               float *d_color_out, void *stream);
+
 /* Plans: a render (and optionally its adjoint) for fixed views, options and
  * bound device arrays, with every buffer the passes need allocated by the
  * plan at creation (pool, output, env tables, tape or recompute chunk tape).

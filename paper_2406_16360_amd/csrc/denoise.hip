@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "device.h"
 #include "runtime.h"
@@ -25,6 +26,7 @@ namespace mrs {
 namespace {
 
 #define HIPTRY_ST(x, what) do { mrs_status st_ = hip_check((x), what); if (st_ != MRS_OK) return st_; } while (0)
+#define TRY_ST(x) do { mrs_status st_ = (x); if (st_ != MRS_OK) return st_; } while (0)
 
 constexpr int kTile = 16;
 __constant__ float kB3[5] = {1.0f / 16, 4.0f / 16, 6.0f / 16, 4.0f / 16, 1.0f / 16};
@@ -34,24 +36,26 @@ struct LevelArgs {
     const float *g, *out, *k;      // adjoint only: dL/d out, out = c_{i+1}, normalisation
     float *dst, *kdst;             // forward: c_{i+1} and k; adjoint: dL/dc_i
     int w, h, stride;
-    int64_t off;                   // first pixel of the view in the packed images
+    int64_t off;                   // first pixel of the view in the G-buffer (and g, out, k)
+    int64_t coff, doff;            // first pixel of the view in c and in dst (and kdst)
     float inv_rt2, inv_n2, inv_x2; // 1 / sigma^2
 };
 
 __device__ __forceinline__ float sq3(float ax, float ay, float az) { return ax * ax + ay * ay + az * az; }
 
-// tile loader: `fields` float3 arrays, pixel (ty, tx) of the apron-padded tile
+// tile loader: `fields` float3 arrays (each with the view's first pixel at
+// its own offset), pixel (ty, tx) of the apron-padded tile
 template <int kFields>
-__device__ __forceinline__ void stage(const float *const (&src)[kFields], float *lds, int span, int x0, int y0,
-                                      int w, int h, int64_t off) {
+__device__ __forceinline__ void stage(const float *const (&src)[kFields], const int64_t (&off)[kFields], float *lds,
+                                      int span, int x0, int y0, int w, int h) {
     for (int t = threadIdx.y * kTile + threadIdx.x; t < span * span; t += kTile * kTile) {
         int ty = t / span, tx = t - ty * span;
         int gx = x0 + tx, gy = y0 + ty;
         if (gx < 0 || gx >= w || gy < 0 || gy >= h) continue;
-        int64_t p = off + (int64_t)gy * w + gx;
+        int64_t p = (int64_t)gy * w + gx;
 #pragma unroll
         for (int f = 0; f < kFields; ++f) {
-            const float *s = src[f] + 3 * p;
+            const float *s = src[f] + 3 * (off[f] + p);
             float *d = lds + (size_t)(f * 3) * span * span + t;
             d[0] = s[0];
             d[span * span] = s[1];
@@ -65,7 +69,8 @@ __global__ __launch_bounds__(kTile *kTile) void k_eawt(LevelArgs a) {
     const int s = a.stride, apron = 2 * s, span = kTile + 2 * apron, area = span * span;
     const int x0 = blockIdx.x * kTile - apron, y0 = blockIdx.y * kTile - apron;
     const float *src[3] = {a.c, a.n, a.x};
-    stage<3>(src, tile, span, x0, y0, a.w, a.h, a.off);
+    const int64_t offs[3] = {a.coff, a.off, a.off};
+    stage<3>(src, offs, tile, span, x0, y0, a.w, a.h);
     __syncthreads();
     const int gx = blockIdx.x * kTile + threadIdx.x, gy = blockIdx.y * kTile + threadIdx.y;
     if (gx >= a.w || gy >= a.h) return;
@@ -91,10 +96,10 @@ __global__ __launch_bounds__(kTile *kTile) void k_eawt(LevelArgs a) {
             sr += wq * qr; sg += wq * qg; sb += wq * qb;
         }
     }
-    const int64_t p = a.off + (int64_t)gy * a.w + gx;
+    const int64_t p = a.doff + (int64_t)gy * a.w + gx;
     const float ik = 1.0f / k;
     a.dst[3 * p] = sr * ik; a.dst[3 * p + 1] = sg * ik; a.dst[3 * p + 2] = sb * ik;
-    a.kdst[p] = k;
+    if (a.kdst) a.kdst[p] = k;
 }
 
 __global__ __launch_bounds__(kTile *kTile) void k_eawt_adjoint(LevelArgs a) {
@@ -103,7 +108,8 @@ __global__ __launch_bounds__(kTile *kTile) void k_eawt_adjoint(LevelArgs a) {
     const int s = a.stride, apron = 2 * s, span = kTile + 2 * apron, area = span * span;
     const int x0 = blockIdx.x * kTile - apron, y0 = blockIdx.y * kTile - apron;
     const float *src[5] = {a.c, a.n, a.x, a.g, a.out};
-    stage<5>(src, tile, span, x0, y0, a.w, a.h, a.off);
+    const int64_t offs[5] = {a.coff, a.off, a.off, a.off, a.off};
+    stage<5>(src, offs, tile, span, x0, y0, a.w, a.h);
     float *K = tile + 15 * area;
     for (int t = threadIdx.y * kTile + threadIdx.x; t < area; t += kTile * kTile) {
         int ty = t / span, tx = t - ty * span;
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(kTile *kTile) void k_eawt_adjoint(LevelArgs a) {
             db += aq * (gqb * ikq - m * (cb - qb));
         }
     }
-    const int64_t p = a.off + (int64_t)gy * a.w + gx;
+    const int64_t p = a.doff + (int64_t)gy * a.w + gx;
     a.dst[3 * p] = dr; a.dst[3 * p + 1] = dg; a.dst[3 * p + 2] = db;
 }
 
@@ -171,7 +177,7 @@ size_t lds_bytes(int planes, int stride) {
 
 LevelArgs level_args(const mrs_view &v, const mrs_denoise_params *dp, int stride) {
     LevelArgs a{};
-    a.w = v.w; a.h = v.h; a.stride = stride; a.off = v.pixel_offset;
+    a.w = v.w; a.h = v.h; a.stride = stride; a.off = a.coff = a.doff = v.pixel_offset;
     a.inv_rt2 = 1.0f / (dp->sigma_rt * dp->sigma_rt);
     a.inv_n2 = 1.0f / (dp->sigma_n * dp->sigma_n);
     a.inv_x2 = 1.0f / (dp->sigma_x * dp->sigma_x);
@@ -248,4 +254,82 @@ extern "C" mrs_status mrs_denoise_backward(const mrs_view *views, int32_t n_view
         g = dst;
     }
     return hip_check(hipGetLastError(), "mrs_denoise_backward launch");
+}
+
+// ============================================================================
+// The forward without a caller workspace, for callers that cannot allocate
+// device memory.  The intermediate levels of one view live in `scratch`, a
+// static device array that each GPU holds from the library's first use on it
+// until the process ends.  Views are filtered one after another through the
+// same two images, so the limit is per view.
+// ============================================================================
+namespace mrs {
+namespace {
+
+constexpr size_t kScratchFloats = MRS_DENOISE_SCRATCH_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current.  The host-side symbol is not a device address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+mrs_status scratch_ptr(float **out) {
+    int dev = -1;
+    HIPTRY_ST(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MRS_EUNSUPPORTED, "mrs_denoise_noalloc: device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPTRY_ST(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(MRS_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MRS_OK;
+}
+
+// colour images of one view the intermediate levels need: none for one
+// level, one for two, two (ping-pong) for more
+uint64_t noalloc_images(int levels) { return (uint64_t)std::min(levels - 1, 2); }
+
+}  // namespace
+}  // namespace mrs
+
+extern "C" mrs_status mrs_denoise_noalloc(const mrs_view *views, int32_t n_views, const mrs_denoise_params *dp,
+                                          const float *d_color_in, const float *d_normal, const float *d_position,
+                                          float *d_color_out, void *stream) {
+    clear_error();
+    uint64_t P = 0;
+    mrs_status st = check(views, n_views, dp, P);
+    if (st != MRS_OK) return st;
+    if (!d_color_in || !d_normal || !d_position || !d_color_out)
+        return fail(MRS_EINVAL, "mrs_denoise_noalloc: null buffer");
+    const uintptr_t in0 = (uintptr_t)d_color_in, out0 = (uintptr_t)d_color_out, nb = sizeof(float) * 3 * P;
+    if (in0 < out0 + nb && out0 < in0 + nb) return fail(MRS_EINVAL, "mrs_denoise_noalloc: output overlaps the input");
+    const int L = dp->levels;
+    const uint64_t imgs = noalloc_images(L);
+    for (int v = 0; v < n_views; ++v) {
+        const uint64_t need = imgs * 3 * (uint64_t)views[v].w * (uint64_t)views[v].h;
+        if (need > kScratchFloats)
+            return fail(MRS_EOVERFLOW, "mrs_denoise_noalloc: view %d (%dx%d, %d levels) needs %llu scratch bytes, the limit is %llu",
+                        v, views[v].w, views[v].h, L, (unsigned long long)(sizeof(float) * need),
+                        (unsigned long long)MRS_DENOISE_SCRATCH_BYTES);
+    }
+    float *scr = nullptr;
+    if (imgs) TRY_ST(scratch_ptr(&scr));
+    hipStream_t s = (hipStream_t)stream;
+    for (int v = 0; v < n_views; ++v) {
+        const uint64_t img = 3 * (uint64_t)views[v].w * (uint64_t)views[v].h;
+        for (int i = 0; i < L; ++i) {
+            const int stride = 1 << i;
+            LevelArgs a = level_args(views[v], dp, stride);
+            a.n = d_normal; a.x = d_position; a.kdst = nullptr;
+            if (i == 0) { a.c = d_color_in; } else { a.c = scr + img * ((i - 1) & 1); a.coff = 0; }
+            if (i == L - 1) { a.dst = d_color_out; } else { a.dst = scr + img * (i & 1); a.doff = 0; }
+            k_eawt<<<grid_of(views[v]), dim3(kTile, kTile), lds_bytes(9, stride), s>>>(a);
+        }
+    }
+    return hip_check(hipGetLastError(), "mrs_denoise_noalloc launch");
 }

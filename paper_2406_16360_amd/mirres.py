@@ -87,7 +87,7 @@ DEFAULT_BUILDER = int(os.environ.get("MIRRES_BVH_BUILDER", BVH_PLOC))
 EXPORTS = ["mrs_build_bvh", "mrs_build_bvh_with", "mrs_bvh_refit", "mrs_bvh_destroy", "mrs_bvh_info", "mrs_trace", "mrs_render", "mrs_render_backward",
            "mrs_plan_create", "mrs_plan_forward", "mrs_plan_backward", "mrs_plan_info", "mrs_plan_destroy",
            "mrs_tape_bytes", "mrs_tape_destroy", "mrs_gbuffer", "mrs_denoise_work_bytes", "mrs_denoise",
-           "mrs_denoise_backward", "mrs_field_eval", "mrs_field_backward", "mrs_profile_begin", "mrs_profile_end",
+           "mrs_denoise_backward", "mrs_denoise_noalloc", "mrs_field_eval", "mrs_field_backward", "mrs_profile_begin", "mrs_profile_end",
            "mrs_release_workspace", "mrs_last_error"]
 
 
@@ -115,6 +115,8 @@ def _load():
     lib.mrs_denoise.argtypes = [p, i32, p, p, p, p, p, p, p]
     lib.mrs_denoise_backward.restype = i32
     lib.mrs_denoise_backward.argtypes = [p, i32, p, p, p, p, p, p, p]
+    lib.mrs_denoise_noalloc.restype = i32
+    lib.mrs_denoise_noalloc.argtypes = [p, i32, p, p, p, p, p, p]
     lib.mrs_field_eval.restype = i32
     lib.mrs_field_eval.argtypes = [C.POINTER(_Field), p, i64, p, p]
     lib.mrs_field_backward.restype = i32
@@ -740,6 +742,23 @@ class Denoiser:
                                          self.normal.data_ptr(), self.position.data_ptr(), self.work.data_ptr(),
                                          g.data_ptr(), gi.data_ptr(), _stream(stream)))
         return gi
+
+
+def denoise_noalloc(views: Sequence, color: torch.Tensor, normal: torch.Tensor, position: torch.Tensor,
+                    out: torch.Tensor, levels: int = 3, sigma_rt: float = 1.0, sigma_n: float = 0.5,
+                    sigma_x: float = 0.5, stream=None) -> torch.Tensor:
+    """The denoiser's forward into the caller's `out` without any device
+    allocation: the library's static scratch holds the intermediate levels
+    (mrs_denoise_noalloc).  No state is kept for a backward."""
+    vs, npix, _ = views_struct(views)
+    params = _DenoiseParams(levels, sigma_rt, sigma_n, sigma_x)
+    bufs = {"color": color, "normal": normal, "position": position, "out": out}
+    for k, t in bufs.items():
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == 3 * npix):
+            raise ValueError(f"denoise_noalloc: {k} must be a contiguous float32 GPU tensor of {npix} x 3")
+    _check(_lib.mrs_denoise_noalloc(C.addressof(vs), len(views), C.byref(params), color.data_ptr(),
+                                    normal.data_ptr(), position.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
 
 
 class _DenoiseFn(torch.autograd.Function):
