@@ -20,13 +20,22 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, s) for s in SOURCES]
-    cmd = ["hipcc", *FLAGS, *srcs, "-o", LIB + ".tmp"]
+# measured memory ceilings for the benchmark's roofline report (not part of the renderer)
+ROOFS_LIB = os.path.join(PKG, "libmrsroofs.so")
+ROOFS_SOURCES = ["roofs.hip"]
+
+
+def _compile(sources, out, verbose):
+    cmd = ["hipcc", *FLAGS, *[os.path.join(HERE, s) for s in sources], "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(SOURCES, LIB, verbose)
+    _compile(ROOFS_SOURCES, ROOFS_LIB, verbose)
     return LIB
 
 

@@ -96,7 +96,7 @@ struct ProfScope {
 // jobs and buffers
 // ============================================================================
 constexpr uint64_t kOutChunkMax = 1ull << 26;   // samples per super-chunk of the output buffer
-constexpr uint32_t kPoolDefault = 1u << 25;      // paths in flight (160 B each: 5.4 GB at the default)
+constexpr uint32_t kPoolDefault = 1u << 26;      // paths in flight: a whole output chunk (160 B each: 10.7 GB)
 constexpr int kBlockDefault = 64;                // threads per workgroup of the trace and shade kernels
 constexpr uint64_t kTapeRecBytes = 36;           // tape bytes per path vertex
 constexpr uint64_t kTapeFieldBytes = 16;         // and, in field mode, the field's output at the vertex
@@ -182,10 +182,8 @@ struct Job {
 
 inline unsigned nblocks(uint64_t n, int b) { return (unsigned)std::max<uint64_t>(1, (n + b - 1) / b); }
 
-// Grid of a persistent traversal launch: enough blocks of b threads to hold
-// every wavefront slot of the current device (32 wave64 per CU), capped by
-// the blocks needed for n rays.  Extra blocks find the queue drained and exit.
-unsigned persistent_blocks(uint64_t n, int b) {
+// compute units of the current device (cached per device)
+int device_cus() {
     static std::atomic<int> cus[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
@@ -194,7 +192,22 @@ unsigned persistent_blocks(uint64_t n, int b) {
         if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
         cus[dev].store(c, std::memory_order_relaxed);
     }
-    return std::min<unsigned>(nblocks(n, b), (unsigned)((uint64_t)c * 2048 / b));
+    return c;
+}
+
+// Grid of a persistent traversal launch: enough blocks of b threads to hold
+// every wavefront slot of the current device (32 wave64 per CU), capped by
+// the blocks needed for n rays.  Extra blocks find the queue drained and exit.
+unsigned persistent_blocks(uint64_t n, int b) {
+    return std::min<unsigned>(nblocks(n, b), (unsigned)((uint64_t)device_cus() * 2048 / b));
+}
+
+// Grid of a grid-stride kernel over a queue whose length only the device
+// knows: per_cu blocks per compute unit (several rounds of resident blocks,
+// so the hardware still balances the tail), capped by the blocks needed for
+// a full pool of n entries.
+unsigned stride_blocks(uint64_t n, int b, int per_cu) {
+    return std::min<unsigned>(nblocks(n, b), (unsigned)(device_cus() * per_cu));
 }
 
 mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views, const mrs_options *op, Job &job) {
@@ -328,7 +341,14 @@ uint64_t max_chunk(const std::vector<Chunk> &cs) {
     return m;
 }
 
-int iterations(const Job &job, uint64_t n, uint32_t P) { return (int)((n * job.op.B + P - 1) / P) + job.op.B + 1; }
+// Wavefront iterations that cover a chunk of n samples through a pool of P
+// paths (n <= P: every sample starts in the first iteration).  While samples
+// wait, the pool is full and an iteration retires P path vertices, at most n B
+// in all; the last sample admitted then needs at most B - 1 more.
+int iterations(const Job &job, uint64_t n, uint32_t P) {
+    const int B = job.op.B;
+    return n <= P ? B : (int)((n * B + P - 1) / P) + B;
+}
 
 // scene pointers the kernels read (the BVH's validated face copy for shading)
 void bind_scene(const mrs_scene *sc, Job &job) {
@@ -439,7 +459,7 @@ mrs_status run_wavefront(const Job &job, const Chunk &ch, Tape tape, int use_tap
         {
             PROF(KID_GENERATE, s);
             GenArgs ga{job.vt, job.op, qa, ctr, it, r.out.as<float4>(), ch.c0, hash, prim, r.hits.as<float4>()};
-            k_generate<<<nblocks(P, 256), 256, 0, s>>>(ga);
+            k_generate<<<stride_blocks(P, 256, 16), 256, 0, s>>>(ga);
         }
         {
             PROF(KID_CLOSEST, s);

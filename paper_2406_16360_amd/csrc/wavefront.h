@@ -443,10 +443,7 @@ struct GenArgs {
     float4 *hits;         // the iteration's hit records (written here for camera rays when prim is given)
 };
 
-__global__ void k_generate(GenArgs a) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const IterCtr c = a.ctr[a.it];
-    if (i >= c.n_new) return;
+__device__ __forceinline__ void generate_one(const GenArgs &a, const IterCtr &c, uint32_t i) {
     uint64_t g = c.gen_base + i;
     SampleId sid = decode(a.vt, g);
     Rng rng{a.op.k0, a.op.k1, sid.pixel, sid.sample, (uint32_t)sid.view};
@@ -463,6 +460,15 @@ __global__ void k_generate(GenArgs a) {
     }
     a.out[g - a.out_base] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (a.hash) a.hash[g - a.out_base] = 0u;
+}
+
+// Grid-stride over the iteration's new samples: the grid is sized for the
+// device, not the pool, so an iteration that admits few or no samples costs a
+// handful of blocks instead of pool / 256 of them.
+__global__ void k_generate(GenArgs a) {
+    const IterCtr c = a.ctr[a.it];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < c.n_new; i += gridDim.x * blockDim.x)
+        generate_one(a, c, i);
 }
 
 struct TraceArgs {

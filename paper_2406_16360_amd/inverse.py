@@ -23,12 +23,15 @@ import torch
 from . import mirres, synth
 
 
-def _rmse(a: torch.Tensor, b: torch.Tensor) -> float:
-    return float((a - b).pow(2).mean().sqrt())
+def _rmse(a: torch.Tensor, b: torch.Tensor, mask: torch.Tensor | None = None) -> float:
+    d = (a - b).pow(2)
+    if mask is not None:                                     # texels some step has seen (nonzero gradient)
+        d = d[mask]                                          # (H, W) mask over (H, W) or (H, W, 3)
+    return float(d.mean().sqrt()) if d.numel() else float("nan")
 
 
 def run(n_views=100, res=800, spp=2, target_spp=256, steps=200, lr=1e-2, rows=500, cols=1000, tex_res=4096,
-        env_hw=(512, 1024), bounces=5, ris_m=32, log_every=10, seed=5):
+        env_hw=(512, 1024), bounces=5, ris_m=32, log_every=10, seed=5, fixed_env=False):
     w = synth.config5(n_views=n_views, res=res, rows=rows, cols=cols, tex_res=tex_res, env_hw=env_hw)
     for v in w.views:
         v.spp = spp
@@ -49,14 +52,26 @@ def run(n_views=100, res=800, spp=2, target_spp=256, steps=200, lr=1e-2, rows=50
     albedo = torch.full_like(gt.albedo, 0.5).requires_grad_(True)
     rough = torch.full_like(gt.rough, 0.5).requires_grad_(True)
     metal = torch.full_like(gt.metal, 0.5).requires_grad_(True)
-    env = torch.full_like(gt.env, float(gt.env.mean())).requires_grad_(True)
+    if fixed_env:                                            # ablation: the lighting is known
+        env = gt.env.clone()
+    else:
+        env = torch.full_like(gt.env, float(gt.env.mean())).requires_grad_(True)
     params = [albedo, rough, metal, env]
-    optim = torch.optim.Adam(params, lr=lr)
+    init = [p.detach().clone() for p in params]
+    optim = torch.optim.Adam([p for p in params if p.requires_grad], lr=lr)
     npix = target.shape[0]
+    # Texels that received a gradient in some step: the error over them says
+    # how well the observed part of each texture is recovered; texels no view
+    # reaches keep their initial value and only dilute the whole-texture RMSE.
+    seen = [torch.zeros(p.shape[:2], dtype=torch.bool, device=p.device) for p in params]
+    names = ("albedo", "rough", "metal", "env")
+    truth = (gt.albedo, gt.rough, gt.metal, gt.env)
 
     def errors():
-        return {"albedo": _rmse(albedo.detach(), gt.albedo), "rough": _rmse(rough.detach(), gt.rough),
-                "metal": _rmse(metal.detach(), gt.metal), "env": _rmse(env.detach(), gt.env)}
+        e = {k: _rmse(p.detach(), t) for k, p, t in zip(names, params, truth)}
+        e.update({k + "_seen": _rmse(p.detach(), t, m) for k, p, t, m in zip(names, params, truth, seen)})
+        e.update({k + "_seen_frac": float(m.float().mean()) for k, m in zip(names, seen)})
+        return e
 
     log = [{"step": 0, **errors()}]
     torch.cuda.synchronize()
@@ -68,6 +83,12 @@ def run(n_views=100, res=800, spp=2, target_spp=256, steps=200, lr=1e-2, rows=50
         loss = (img - target).pow(2).sum() / npix
         optim.zero_grad(set_to_none=False)
         loss.backward()
+        with torch.no_grad():
+            for m, p in zip(seen, params):
+                if p.grad is None:
+                    continue
+                g = p.grad != 0
+                m |= g.any(-1) if g.dim() == 3 else g
         optim.step()
         with torch.no_grad():                                # keep parameters in their valid ranges
             albedo.clamp_(0.0, 1.0)
@@ -75,14 +96,17 @@ def run(n_views=100, res=800, spp=2, target_spp=256, steps=200, lr=1e-2, rows=50
             metal.clamp_(0.0, 1.0)
             env.clamp_(min=0.0)
         if (it + 1) % log_every == 0 or it + 1 == steps:
-            rec = {"step": it + 1, "loss": float(loss), **errors(), "s": time.perf_counter() - t1}
+            rec = {"step": it + 1, "loss": float(loss.detach()), **errors(), "s": time.perf_counter() - t1}
             log.append(rec)
             print(json.dumps(rec), flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
+    # step 0 over the texels the run ended up seeing (the mask is empty before the first step)
+    log[0].update({k + "_seen": _rmse(p, t, m) for k, p, t, m in zip(names, init, truth, seen)})
     S = sum(v.w * v.h * v.spp for v in w.views)
     return {"workload": w.name, "triangles": w.scene.nf, "views": n_views, "res": res, "spp": spp,
             "target_spp": target_spp, "bounces": bounces, "ris_m": ris_m, "steps": steps, "lr": lr,
+            "env_optimised": not fixed_env,
             "steps_per_s": steps / dt, "samples_per_s": steps * S / dt, "target_render_s": t_target,
             "initial": log[0], "final": log[-1]}
 
@@ -94,13 +118,16 @@ def main():
     ap.add_argument("--res", type=int, default=800)
     ap.add_argument("--target-spp", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--spp", type=int, default=2)
+    ap.add_argument("--fixed-env", action="store_true", help="hold the environment map at the ground truth")
     ap.add_argument("--small", action="store_true", help="8 views of 256^2, 100k triangles, 1024^2 textures")
     a = ap.parse_args()
     if a.small:
-        res = run(n_views=8, res=256, target_spp=64, steps=a.steps, lr=a.lr, rows=158, cols=316, tex_res=1024,
-                  env_hw=(128, 256))
+        res = run(n_views=8, res=256, spp=a.spp, target_spp=64, steps=a.steps, lr=a.lr, rows=158, cols=316,
+                  tex_res=1024, env_hw=(128, 256), fixed_env=a.fixed_env)
     else:
-        res = run(n_views=a.views, res=a.res, target_spp=a.target_spp, steps=a.steps, lr=a.lr)
+        res = run(n_views=a.views, res=a.res, spp=a.spp, target_spp=a.target_spp, steps=a.steps, lr=a.lr,
+                  fixed_env=a.fixed_env)
     print(json.dumps(res), flush=True)
 
 
