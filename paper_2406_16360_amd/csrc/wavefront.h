@@ -822,65 +822,182 @@ struct AdjArgs {
 // Gradient scatter.  The adjoint accumulates into an internal record buffer:
 // one kMatRec-float record per material texel (texture mode: albedo rgb,
 // roughness, metallic) or per mesh vertex (vertex mode: its five values), then
-// one kEnvRec-float record per env texel (rgb).  A wavefront stages the
-// (offset, value) pairs of its lanes in LDS, lane after lane, and issues them
-// transposed, so that one atomic instruction covers a few lanes' consecutive
-// record words instead of 64 scattered words.  The atomics are carried out
+// one kEnvRec-float record per env texel (rgb).  The atomics are carried out
 // past L2, one memory-side request per cache line an instruction touches, so
-// this cuts the requests several fold.  k_grad_fold then adds the records
-// into the caller's arrays.
+// a wavefront never issues its lanes' values as they come.  Per flush it
+// takes one of two forms, the same for all its lanes:
+//  - merged, when neighbouring lanes share records (the spp samples of a pixel
+//    and the pixels of a row at the primary vertex of a fine texture): the
+//    lanes sum their values per record in an LDS hash table (open addressing,
+//    keyed by the record's first word), and the wavefront then issues one
+//    atomic per distinct record word, a record's words from adjacent lanes;
+//  - staged, otherwise (deeper vertices, textures coarser than the pixels):
+//    the lanes write their (offset, value) pairs to LDS, lane after lane, and
+//    the wavefront issues them transposed, a few lanes' consecutive record
+//    words per instruction; merging would cost LDS round trips for nothing.
+// k_grad_fold then adds the records into the caller's arrays.
 // ---------------------------------------------------------------------------
 constexpr int kMatRec = 8, kEnvRec = 4;
 constexpr int kMatChannels = 5;      // albedo rgb, roughness, metallic per interpolation entry
 constexpr int kEnvChannels = 3;      // rgb per env texel
-constexpr int kEntriesPerFlush = 2;  // interpolation entries a lane stages per flush
-constexpr int kScatSlots = 13;       // pairs a lane stages per flush
+constexpr int kEntriesPerFlush = 2;  // interpolation entries a lane adds per flush
+constexpr int kScatSlots = 13;       // staged form: pairs a lane stages per flush
+constexpr int kAggBits = 8;
+constexpr int kAggSlots = 1 << kAggBits;   // merged form: hash slots per wavefront
+constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
 constexpr int kAdjBlock = 256;
-// The largest flush of a vertex: kEntriesPerFlush entries of every material
-// channel plus the env texel.  put() drops pairs past kScatSlots, so this
-// bound is what keeps the scatter lossless.
+// The largest flush of a lane: kEntriesPerFlush material records and one env
+// record.  The staged form drops pairs past kScatSlots and the merged form
+// needs free slots to end its probing, so these bounds keep the scatter lossless.
 static_assert(kScatSlots >= kEntriesPerFlush * kMatChannels + kEnvChannels,
               "a flush stages more pairs than a lane has slots");
+static_assert(64 * (kEntriesPerFlush + 1) <= kAggSlots * 3 / 4, "a flush can fill the hash table");
+static_assert(kAggSlots % 64 == 0, "slots are cleared and compacted 64 at a time");
+// LDS words per wavefront: the two forms share one region
+constexpr int kStageWords = 64 * kScatSlots * 2 + 64;
+constexpr int kAggWords = kAggSlots * (2 + kMatChannels);
+constexpr int kScatWords = kStageWords > kAggWords ? kStageWords : kAggWords;
 
 struct WaveScatter {
-    uint32_t *off;       // this wavefront's staging in LDS: [64][kScatSlots] offsets,
-    float *val;          // values,
-    int *cnt;            // and [64] counts
+    uint32_t *lds;       // this wavefront's kScatWords words
     float *rec;
+    uint32_t env_base;   // first word of the env records
     uint32_t lane;
-    int n;               // pairs staged by this lane
-    __device__ __forceinline__ void put(uint32_t o, float v) {
-        if (v == 0.0f || n >= kScatSlots) return;
-        off[lane * kScatSlots + n] = o;
-        val[lane * kScatSlots + n] = v;
-        ++n;
+    bool merge;          // form of the current flush (wavefront-uniform)
+    bool clean;          // the hash table is empty (no staged flush since it was cleared)
+    int n;               // staged form: pairs staged by this lane
+
+    // staged form: [64][kScatSlots] offsets, values, [64] counts
+    __device__ __forceinline__ uint32_t *s_off() { return lds; }
+    __device__ __forceinline__ float *s_val() { return (float *)(lds + 64 * kScatSlots); }
+    __device__ __forceinline__ int *s_cnt() { return (int *)(lds + 2 * 64 * kScatSlots); }
+    // merged form: [kAggSlots] keys, [kAggSlots][kMatChannels] sums, [kAggSlots] compacted slots
+    __device__ __forceinline__ uint32_t *h_key() { return lds; }
+    __device__ __forceinline__ float *h_val() { return (float *)(lds + kAggSlots); }
+    __device__ __forceinline__ uint32_t *h_list() { return lds + kAggSlots * (1 + kMatChannels); }
+
+    __device__ __forceinline__ static void sync() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // issues every staged pair; all lanes of the wavefront call it together
-    __device__ __forceinline__ void flush() {
-        cnt[lane] = n;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Picks the form of the next flushes from each lane's first material
+    // record and env record (kAggEmpty: none): merged when at least a quarter
+    // of the lanes with a record share one with the lane before them.
+    __device__ __forceinline__ void begin(uint32_t kmat, uint32_t kenv) {
+        const uint32_t pm = __shfl_up(kmat, 1), pe = __shfl_up(kenv, 1);
+        const bool same = lane > 0 && ((kmat != kAggEmpty && kmat == pm) || (kenv != kAggEmpty && kenv == pe));
+        const int nsame = __popcll(__ballot(same));
+        const int nact = __popcll(__ballot(kmat != kAggEmpty || kenv != kAggEmpty));
+        merge = nact > 0 && 4 * nsame >= nact;
+        if (merge && !clean) {
+            for (uint32_t s = lane; s < (uint32_t)kAggSlots; s += 64) {
+                h_key()[s] = kAggEmpty;
 #pragma unroll
-        for (int j = 0; j < kScatSlots; ++j) {
-            const uint32_t e = j * 64 + lane, src = e / kScatSlots, r = e - src * kScatSlots;
-            if ((int)r < cnt[src]) atomicAdd(rec + off[e], val[e]);
+                for (int c = 0; c < kMatChannels; ++c) h_val()[s * kMatChannels + c] = 0.0f;
+            }
+            sync();
+            clean = true;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        n = 0;
+        if (!merge) clean = false;
+    }
+    // adds scale * g[c] to word c of the record at word offset `base` (zeros
+    // are dropped; the products are formed where they are used, so that they
+    // need no registers across the slot search)
+    template <int NCH>
+    __device__ __forceinline__ void add(uint32_t base, float scale, const float (&g)[NCH]) {
+        if (!merge) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const float v = scale * g[c];
+                if (v == 0.0f || n >= kScatSlots) continue;
+                s_off()[lane * kScatSlots + n] = base + c;
+                s_val()[lane * kScatSlots + n] = v;
+                ++n;
+            }
+            return;
+        }
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) any |= scale * g[c] != 0.0f;
+        if (!any) return;
+        uint32_t h = (base * 2654435761u) >> (32 - kAggBits);   // multiplicative (Fibonacci) hashing
+        int p = 0;
+        for (; p < kAggSlots; ++p) {
+            const uint32_t old = atomicCAS(h_key() + h, kAggEmpty, base);
+            if (old == kAggEmpty || old == base) break;
+            h = (h + 1) & (kAggSlots - 1);
+        }
+        if (p == kAggSlots) {                      // not reached (the table is never full)
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (scale * g[c] != 0.0f) atomicAdd(rec + base + c, scale * g[c]);
+            return;
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const float v = scale * g[c];
+            if (v != 0.0f) atomicAdd(h_val() + h * kMatChannels + c, v);
+        }
+    }
+    // issues what the flush holds; all lanes of the wavefront call it together
+    __device__ __forceinline__ void flush() {
+        if (!merge) {
+            s_cnt()[lane] = n;
+            sync();
+#pragma unroll 1
+            for (int j = 0; j < kScatSlots; ++j) {
+                const uint32_t e = j * 64 + lane, src = e / kScatSlots, r = e - src * kScatSlots;
+                if ((int)r < s_cnt()[src]) atomicAdd(rec + s_off()[e], s_val()[e]);
+            }
+            sync();
+            n = 0;
+            return;
+        }
+        sync();
+        // compact the taken slots, material records first (kMatChannels words
+        // each), then env records (kEnvChannels words each)
+        uint32_t nm = 0, total = 0;
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int r = 0; r < kAggSlots / 64; ++r) {
+                const uint32_t s = r * 64 + lane, k = h_key()[s];
+                const bool take = k != kAggEmpty && ((k < env_base) == (pass == 0));
+                const uint64_t m = __ballot(take);
+                if (take) h_list()[total + __popcll(m & ((1ull << lane) - 1))] = s;
+                total += (uint32_t)__popcll(m);
+            }
+            if (pass == 0) nm = total;
+        }
+        sync();
+        const uint32_t wm = nm * kMatChannels, np = wm + (total - nm) * kEnvChannels;
+        for (uint32_t e = lane; e < np; e += 64) {
+            uint32_t i, c;
+            if (e < wm) { i = e / kMatChannels; c = e - i * kMatChannels; }
+            else { const uint32_t q = (e - wm) / kEnvChannels; c = e - wm - q * kEnvChannels; i = nm + q; }
+            const uint32_t s = h_list()[i];
+            const float v = h_val()[s * kMatChannels + c];
+            if (v != 0.0f) atomicAdd(rec + h_key()[s] + c, v);
+        }
+        sync();
+        for (uint32_t i = lane; i < total; i += 64) {
+            const uint32_t s = h_list()[i];
+            h_key()[s] = kAggEmpty;
+#pragma unroll
+            for (int c = 0; c < kMatChannels; ++c) h_val()[s * kMatChannels + c] = 0.0f;
+        }
+        sync();
     }
 };
 
-// material pairs of interpolation entries q0 and q1 (those that exist)
-__device__ __forceinline__ void put_material(WaveScatter &ws, const Interp &ip, int q0, const float *gm) {
-    for (int q = q0; q < q0 + kEntriesPerFlush && q < ip.n; ++q) {
+// material records of interpolation entries q0 and q1 (those that exist)
+__device__ __forceinline__ void put_material(WaveScatter &ws, const Interp &ip, int q0, const float (&gm)[kMatChannels]) {
+#pragma unroll
+    for (int q = q0; q < q0 + kEntriesPerFlush && q < ip.n; ++q) {   // unrolled: ip stays in registers
         const float w = ip.w[q];
         if (w == 0.0f) continue;
-        const uint32_t base = kMatRec * (uint32_t)ip.idx[q];
-#pragma unroll
-        for (int c = 0; c < kMatChannels; ++c) ws.put(base + c, w * gm[c]);
+        ws.add(kMatRec * (uint32_t)ip.idx[q], w, gm);
     }
 }
 
@@ -1025,13 +1142,15 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
         }
         // group 1: interpolation entries 0 and 1, and the env texel
         static_assert(kEntriesPerFlush == 2, "the two groups below cover the four bilinear entries");
+        const bool env_rec = etex >= 0 && a.genv;
+        ws.begin(has && a.mat_on && ip.n > 0 ? kMatRec * (uint32_t)ip.idx[0] : kAggEmpty,
+                 env_rec ? a.env_base + kEnvRec * (uint32_t)etex : kAggEmpty);
         if (has && a.mat_on) put_material(ws, ip, 0, gm);
-        if (etex >= 0 && a.genv) {
+        if (env_rec) {
             const float *raw = a.s.env.raw + 3 * (size_t)etex;
-            const uint32_t base = a.env_base + kEnvRec * (uint32_t)etex;
-            ws.put(base + 0, raw[0] >= 0.0f ? ge.x : 0.0f);
-            ws.put(base + 1, raw[1] >= 0.0f ? ge.y : 0.0f);
-            ws.put(base + 2, raw[2] >= 0.0f ? ge.z : 0.0f);
+            const float v[kEnvChannels] = {raw[0] >= 0.0f ? ge.x : 0.0f, raw[1] >= 0.0f ? ge.y : 0.0f,
+                                           raw[2] >= 0.0f ? ge.z : 0.0f};
+            ws.add(a.env_base + kEnvRec * (uint32_t)etex, 1.0f, v);
         }
         ws.flush();
         // group 2: interpolation entries 2 and 3
@@ -1042,12 +1161,9 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
 
 // one thread per sample, every lane in the vertex loop of the scatter
 __global__ void __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint(AdjArgs a) {
-    __shared__ uint32_t s_off[kAdjBlock * kScatSlots];
-    __shared__ float s_val[kAdjBlock * kScatSlots];
-    __shared__ int s_cnt[kAdjBlock];
-    const uint32_t w = threadIdx.x / 64;
-    WaveScatter ws{s_off + w * 64 * kScatSlots, s_val + w * 64 * kScatSlots, s_cnt + w * 64, a.rec,
-                   (uint32_t)__lane_id(), 0};
+    __shared__ uint32_t s_scat[kAdjBlock / 64 * kScatWords];
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);   // wavefront-uniform
+    WaveScatter ws{s_scat + w * kScatWords, a.rec, a.env_base, (uint32_t)__lane_id(), false, false, 0};
     uint64_t j = blockIdx.x * (uint64_t)kAdjBlock + threadIdx.x;
     adjoint_sample(a, j < a.n, j, ws);
 }
