@@ -177,6 +177,17 @@ typedef struct {
     int32_t  reuse_m_cap;        /* temporal confidence cap in multiples of ris_m, >= 1 */
     const float *reservoir_prev; /* nullable device [S][8]: the previous frame's final reservoirs */
     float   *reservoir_out;      /* nullable device [S][8]: this frame's final reservoirs (must not alias prev) */
+    /* 1: mrs_render_backward sums every gradient word in a fixed order, so
+     * its output is bitwise reproducible for the same inputs, whatever the
+     * order in which the device runs the work.  Each sample writes its
+     * (word, value) pairs to slots of its own, a stable radix sort groups
+     * them by word, and one thread adds each word's run in sample order
+     * (library-owned: 368 B per bounce per sample of a 2^20-sample launch,
+     * pairs and sorted copy, plus the sort's scratch).
+     * For tests and debugging: several times slower than the default (0),
+     * whose float atomics land in any order.  Texture and vertex materials
+     * only: MRS_EINVAL with MRS_MAT_FIELD. */
+    int32_t  deterministic;
 } mrs_options;
 
 /* Gradient outputs (device, ACCUMULATED with +=; the caller zeroes them).

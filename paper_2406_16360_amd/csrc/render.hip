@@ -117,10 +117,12 @@ struct Res {
     DevBuf rprim, rfmat, rr0, rr1;                             // reuse: primary hits, their field output, reservoirs
     DevBuf fkey, fkey2, fval, fval2, fsort;                    // field mode: pull-back order (keys, values, sort scratch)
     DevBuf tpack;                                              // texture mode: interleaved texel records
+    DevBuf dkey, dkey2, dval, dval2, dsort;                    // deterministic adjoint: pairs, sorted pairs, sort scratch
     void release_all() {
         for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &lp, &gmarg, &gcond, &mpair, &cpair, &rcos, &csphi, &views, &qa_o, &qa_d, &qa_t, &qb_o,
                           &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &ct_fm, &grec, &fm, &fvtx, &gvtx,
-                          &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort, &tpack})
+                          &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort, &tpack, &dkey, &dkey2, &dval, &dval2,
+                          &dsort})
             b->release();
     }
 };
@@ -178,6 +180,7 @@ struct Job {
     ViewTable vt{};
     uint32_t pool = kPoolDefault;
     int block = kBlockDefault;
+    bool det = false;             // deterministic adjoint (ordered sums instead of atomics)
 };
 
 inline unsigned nblocks(uint64_t n, int b) { return (unsigned)std::max<uint64_t>(1, (n + b - 1) / b); }
@@ -246,6 +249,9 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
     if (op->tape_mode < MRS_TAPE_AUTO || op->tape_mode > MRS_TAPE_OFF) return fail(MRS_EINVAL, "unknown tape_mode %d", op->tape_mode);
     if (op->pool < 0) return fail(MRS_EINVAL, "pool must be >= 0");
     if (op->block != 0 && (op->block < 64 || op->block > 256 || op->block % 64)) return fail(MRS_EINVAL, "block must be 0 or a multiple of 64 in [64, 256]");
+    if (op->deterministic != 0 && op->deterministic != 1) return fail(MRS_EINVAL, "deterministic must be 0 or 1");
+    if (op->deterministic && sc->mat_mode == MRS_MAT_FIELD)
+        return fail(MRS_EINVAL, "deterministic mode covers texture and vertex materials, not the material field");
     if (op->reuse_spatial != 0 || op->reuse_temporal != 0) {
         if (op->reuse_spatial < 0 || op->reuse_spatial > kReuseMaxK) return fail(MRS_EINVAL, "reuse_spatial must be in [0, %d]", kReuseMaxK);
         if (op->reuse_radius < 1 || op->reuse_radius > 64) return fail(MRS_EINVAL, "reuse_radius must be in [1, 64]");
@@ -296,6 +302,7 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
     job.op.k0 = (uint32_t)op->seed; job.op.k1 = (uint32_t)(op->seed >> 32);
     job.pool = op->pool > 0 ? (uint32_t)op->pool : kPoolDefault;
     job.block = op->block > 0 ? op->block : kBlockDefault;
+    job.det = op->deterministic != 0;
     return MRS_OK;
 }
 
@@ -536,13 +543,26 @@ mrs_status reserve_field_vertices(const Job &job, uint64_t samples, Res &r) {
     return MRS_OK;
 }
 
+// Deterministic mode: kPairsPerVertex * B (record word, value) pairs per
+// sample of a kDetChunk-sample adjoint launch, their sorted copies and the
+// sort's scratch.
+constexpr uint64_t kDetChunk = 1ull << 20;
+mrs_status reserve_det_pairs(const Job &job, uint64_t samples, Res &r) {
+    if (!job.det) return MRS_OK;
+    const size_t n = (size_t)std::min<uint64_t>(kDetChunk, samples) * kPairsPerVertex * job.op.B;
+    for (DevBuf *b : {&r.dkey, &r.dkey2, &r.dval, &r.dval2}) TRY(b->reserve(sizeof(uint32_t) * n));
+    TRY(r.dsort.reserve(std::max<size_t>(sort_pairs_tmp_bytes(n), 16)));
+    return MRS_OK;
+}
+
 mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, const float *dimg, const mrs_grads *gr,
                    const GradRec &gl, float *rec, Res &r, hipStream_t s) {
     const bool field = job.sd.mat_mode == MRS_MAT_FIELD && field_wanted(gr);
     if (gl.words == 0 && !field) return MRS_OK;
     const FieldGrads fg{gr->field.table, gr->field.w1, gr->field.b1, gr->field.w2, gr->field.b2};
-    for (uint64_t a0 = c0; a0 < c1; a0 += kAdjChunk) {
-        uint64_t n = std::min<uint64_t>(kAdjChunk, c1 - a0);
+    const uint64_t step = job.det ? kDetChunk : kAdjChunk;
+    for (uint64_t a0 = c0; a0 < c1; a0 += step) {
+        uint64_t n = std::min<uint64_t>(step, c1 - a0);
         SceneDev sd = job.sd;
         uint64_t fm_stride = n;
         if (job.sd.mat_mode == MRS_MAT_FIELD) {
@@ -566,7 +586,16 @@ mrs_status adjoint(const Job &job, const Tape &tp, uint64_t c0, uint64_t c1, con
             PROF(KID_ADJOINT, s);
             AdjArgs aa{sd, job.vt, job.op, tp, a0, n, dimg, gr->vmat, gr->albedo, gr->rough, gr->metal, gr->env,
                        rec, gl.env_base, gl.n_mat > 0 ? 1 : 0, r.gvtx.as<float4>(), field ? 1 : 0, fm_stride};
-            k_adjoint<<<nblocks(n, kAdjBlock), kAdjBlock, 0, s>>>(aa);
+            if (job.det) {
+                const uint64_t np = n * kPairsPerVertex * (uint64_t)job.op.B;
+                k_fill_u32<<<nblocks(np, 256), 256, 0, s>>>(r.dkey.as<uint32_t>(), np, kAggEmpty);
+                k_adjoint_det<<<nblocks(n, kAdjBlock), kAdjBlock, 0, s>>>(aa, r.dkey.as<uint32_t>(), r.dval.as<float>());
+                TRY(sort_pairs_u32(r.dkey.as<uint32_t>(), r.dkey2.as<uint32_t>(), r.dval.as<uint32_t>(),
+                                   r.dval2.as<uint32_t>(), np, r.dsort, s));
+                k_det_sum<<<nblocks(np, 256), 256, 0, s>>>(r.dkey2.as<uint32_t>(), r.dval2.as<float>(), np, rec);
+            } else {
+                k_adjoint<<<nblocks(n, kAdjBlock), kAdjBlock, 0, s>>>(aa);
+            }
         }
         if (field) {
             PROF(KID_FIELD_BWD, s);
@@ -710,6 +739,7 @@ mrs_status enqueue_backward(const Job &job, const std::vector<Chunk> &chunks, co
     const GradRec gl = grad_rec(sc, grads);
     if (gl.words) TRY(r.grec.reserve(4 * gl.words));
     if (sc->mat_mode == MRS_MAT_FIELD) TRY(reserve_field_vertices(j, j.S, r));
+    TRY(reserve_det_pairs(j, j.S, r));
     float *rec = r.grec.as<float>();
     grad_rec_clear(gl, rec, s);
     if (tape) {
@@ -1059,6 +1089,7 @@ extern "C" mrs_status mrs_plan_create(const mrs_scene *scene, const mrs_view *vi
     if (p->has_grads) {
         if (size_t words = grad_rec(scene, grads).words) PTRY(p->res.grec.reserve(4 * words));
         if (scene->mat_mode == MRS_MAT_FIELD) PTRY(reserve_field_vertices(job, job.S, p->res));
+        PTRY(reserve_det_pairs(job, job.S, p->res));
         PTRY(decide_tape(job, opt, true, &p->tape));
         if (!p->tape) {
             size_t n = (size_t)max_chunk(p->bwd_chunks) * job.op.B;

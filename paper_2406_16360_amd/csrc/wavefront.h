@@ -991,8 +991,34 @@ struct WaveScatter {
     }
 };
 
+// Deterministic form of the scatter: each sample writes its (record word,
+// value) pairs, in the order it produces them, to kPairsPerVertex * B slots
+// of its own; a stable sort by word and ordered sums (k_det_sum) then add
+// them up in sample order, so the gradients do not depend on the order in
+// which atomics land.  Unused slots keep the key kAggEmpty.
+constexpr int kPairsPerVertex = 2 * kEntriesPerFlush * kMatChannels + kEnvChannels;
+struct PairSink {
+    uint32_t *key;   // this sample's slots
+    float *val;
+    int cap, n;
+    __device__ __forceinline__ void begin(uint32_t, uint32_t) {}
+    template <int NCH>
+    __device__ __forceinline__ void add(uint32_t base, float scale, const float (&g)[NCH]) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const float v = scale * g[c];
+            if (v == 0.0f || n >= cap) continue;
+            key[n] = base + c;
+            val[n] = v;
+            ++n;
+        }
+    }
+    __device__ __forceinline__ void flush() {}
+};
+
 // material records of interpolation entries q0 and q1 (those that exist)
-__device__ __forceinline__ void put_material(WaveScatter &ws, const Interp &ip, int q0, const float (&gm)[kMatChannels]) {
+template <class Sink>
+__device__ __forceinline__ void put_material(Sink &ws, const Interp &ip, int q0, const float (&gm)[kMatChannels]) {
 #pragma unroll
     for (int q = q0; q < q0 + kEntriesPerFlush && q < ip.n; ++q) {   // unrolled: ip stays in registers
         const float w = ip.w[q];
@@ -1006,7 +1032,8 @@ __device__ __forceinline__ void put_material(WaveScatter &ws, const Interp &ip, 
 // T_{k+1} = T_k (.) beta_k, so dC/dm_k = T_k (.) (dD_k/dm_k + dbeta_k/dm_k (.) Li_{k+1})
 // with Li_k = D_k + beta_k (.) Li_{k+1} accumulated from the last vertex back.
 // The vertex loop of the scatter runs in step across the wavefront.
-__device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uint64_t j, WaveScatter &ws) {
+template <class Sink>
+__device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uint64_t j, Sink &ws) {
     const int B = a.op.B;
     uint64_t g = a.g0 + j;
     V3 gp = V3{0, 0, 0};
@@ -1166,6 +1193,29 @@ __global__ void __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(
     WaveScatter ws{s_scat + w * kScatWords, a.rec, a.env_base, (uint32_t)__lane_id(), false, false, 0};
     uint64_t j = blockIdx.x * (uint64_t)kAdjBlock + threadIdx.x;
     adjoint_sample(a, j < a.n, j, ws);
+}
+
+// deterministic mode: one thread per sample, its pairs to keys / vals (see PairSink)
+__global__ void __launch_bounds__(kAdjBlock) k_adjoint_det(AdjArgs a, uint32_t *keys, float *vals) {
+    const uint64_t j = blockIdx.x * (uint64_t)kAdjBlock + threadIdx.x;
+    const int cap = kPairsPerVertex * a.op.B;
+    const uint64_t slot = j < a.n ? j : 0;   // lanes past the end add nothing
+    PairSink ps{keys + slot * cap, vals + slot * cap, cap, 0};
+    adjoint_sample(a, j < a.n, j, ps);
+}
+
+// Ordered sums over the pairs sorted (stably) by record word: the first pair
+// of each run of equal words adds the run, in its sorted order, which is
+// sample order, to the record.  Each word has one run, so no atomics.
+__global__ void k_det_sum(const uint32_t *__restrict__ key, const float *__restrict__ val, uint64_t n,
+                          float *__restrict__ rec) {
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = key[i];
+    if (k == kAggEmpty || (i > 0 && key[i - 1] == k)) return;
+    float sum = 0.0f;
+    for (uint64_t q = i; q < n && key[q] == k; ++q) sum += val[q];
+    rec[k] += sum;
 }
 
 // adds the gradient records into the caller's arrays, one record per thread

@@ -63,7 +63,7 @@ class _Options(C.Structure):
                 ("tape_mode", C.c_int32), ("tape_budget", C.c_int64), ("pool", C.c_int32), ("block", C.c_int32),
                 ("debug_sample_rgb", C.c_void_p), ("debug_hash", C.c_void_p), ("reuse_spatial", C.c_int32),
                 ("reuse_radius", C.c_int32), ("reuse_temporal", C.c_int32), ("reuse_m_cap", C.c_int32),
-                ("reservoir_prev", C.c_void_p), ("reservoir_out", C.c_void_p)]
+                ("reservoir_prev", C.c_void_p), ("reservoir_out", C.c_void_p), ("deterministic", C.c_int32)]
 
 
 class _Grads(C.Structure):
@@ -220,6 +220,7 @@ class RenderOptions:
     reuse_radius: int = 16
     reuse_temporal: int = 0
     reuse_m_cap: int = 20
+    deterministic: int = 0
 
     @classmethod
     def from_any(cls, o) -> "RenderOptions":
@@ -232,7 +233,8 @@ class RenderOptions:
         return _Options(self.bounces, self.ris_m, self.ris_m_brdf, self.rr_start, self.seed & (2 ** 64 - 1), self.brdf,
                         self.background, self.grad_mode, self.tape_mode, self.tape_budget, self.pool, self.block,
                         _ptr(debug_rgb), _ptr(debug_hash), self.reuse_spatial, self.reuse_radius,
-                        self.reuse_temporal, self.reuse_m_cap, _ptr(reservoir_prev), _ptr(reservoir_out))
+                        self.reuse_temporal, self.reuse_m_cap, _ptr(reservoir_prev), _ptr(reservoir_out),
+                        self.deterministic)
 
 
 class Bvh:
