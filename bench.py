@@ -260,13 +260,16 @@ def bench_batched(args):
     print(f"# workload {w.name}: {S} samples/pass, {w.scene.nf} triangles", file=sys.stderr, flush=True)
     sc = mirres.GpuScene.from_synth(w.scene)
     opts = mirres.RenderOptions.from_any(w.opts)
-    tune = autotune.autotune(sc, w.views, opts, reps=2, verbose=True)
+    tune = autotune.autotune(sc, w.views, opts, reps=2, verbose=True, cache=None)
     opts.pool, opts.block = tune["pool"], tune["block"]
     target = mirres.render(_gt_target_scene(mirres, synth, sc, dev), w.views, opts).clone()
     plan = mirres.Plan(sc, w.views, opts, use_graph=True)
     t_batched = _timed(args, plan.forward)
     del plan
-    gplan = mirres.Plan(sc, w.views, opts, with_grad=True, use_graph=True)
+    # the fwd+bwd plan gets sizes tuned for the forward and backward together
+    gtune = autotune.autotune(sc, w.views, opts, reps=2, verbose=True, cache=None, with_grad=True)
+    gopts = mirres.RenderOptions(**{**opts.__dict__, "pool": gtune["pool"], "block": gtune["block"]})
+    gplan = mirres.Plan(sc, w.views, gopts, with_grad=True, use_graph=True)
     t_fwdbwd = _timed(args, lambda: _plan_step(gplan, target))
     keeps_tape = gplan.info()[1]
     del gplan
@@ -275,8 +278,8 @@ def bench_batched(args):
     # per-kernel times from eager fwd+bwd steps with the tuned sizes
     mirres.profile_begin()
     for _ in range(2):
-        img, tape = mirres.render(sc, w.views, opts, keep_tape=True)
-        mirres.render_backward(sc, w.views, opts, 2.0 * (img - target), tape=tape)
+        img, tape = mirres.render(sc, w.views, gopts, keep_tape=True)
+        mirres.render_backward(sc, w.views, gopts, 2.0 * (img - target), tape=tape)
     torch.cuda.synchronize()
     prof = mirres.profile_end()
     cpu, roof, extra = None, None, {}
@@ -294,11 +297,12 @@ def bench_batched(args):
            "ms_per_step": t_fwdbwd * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "views": len(w.views), "samples_per_step": S, "bounces": w.opts.bounces,
-                      "ris_m": w.opts.ris_m, "triangles": w.scene.nf, "pool": opts.pool, "block": opts.block,
-                      "tape": keeps_tape},
+                      "ris_m": w.opts.ris_m, "triangles": w.scene.nf, "pool": gopts.pool, "block": gopts.block,
+                      "tape": keeps_tape, "forward_pool": opts.pool, "forward_block": opts.block},
            "forward_batched": {"value": S / t_batched, "ms_per_step": t_batched * 1e3},
            "forward_64_plain_launches": {"value": S / t_plain, "ms_per_step": t_plain * 1e3},
            "batched_forward_speedup": t_plain / t_batched, "autotune": tune["table"],
+           "autotune_fwdbwd": gtune["table"],
            "roofline": roof, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out), flush=True)

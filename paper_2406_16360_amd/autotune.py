@@ -2,7 +2,8 @@
 
 Searches the path-pool size (paths in flight) and the workgroup size of the
 trace and shade kernels for a given scene, view set and options, timing
-graph replays of a plan's forward pass with HIP events (median of `reps`).
+graph replays of a plan's forward pass, or of its forward and backward
+passes (with_grad), with HIP events (median of `reps`).
 Results are cached in a JSON file keyed by the device name and a signature
 of the workload (samples, views, bounces, candidates, triangles, material
 mode), so a repeated optimisation loop pays the search once.
@@ -27,12 +28,12 @@ def _cache_path() -> str:
     return os.path.join(base, "paper_2406_16360_amd", "autotune.json")
 
 
-def workload_key(scene: mirres.GpuScene, views: Sequence, opts) -> str:
+def workload_key(scene: mirres.GpuScene, views: Sequence, opts, with_grad: bool = False) -> str:
     o = mirres.RenderOptions.from_any(opts)
     S = mirres.total_samples(views)
     dev = torch.cuda.get_device_name(scene.pos.device)
     return (f"{dev}|S={S}|views={len(views)}|B={o.bounces}|M={o.ris_m}|Mb={o.ris_m_brdf}|rr={o.rr_start}"
-            f"|nf={scene.faces.shape[0]}|mat={scene.mat_mode}")
+            f"|nf={scene.faces.shape[0]}|mat={scene.mat_mode}|grad={int(with_grad)}")
 
 
 def _load(path: str) -> Dict:
@@ -43,15 +44,20 @@ def _load(path: str) -> Dict:
         return {}
 
 
-def _time_forward(plan: mirres.Plan, reps: int) -> float:
-    plan.forward()                      # capture + first replay
+def _time_plan(plan: mirres.Plan, reps: int, with_grad: bool) -> float:
+    def step():
+        plan.forward()
+        if with_grad:
+            plan.backward()
+
+    step()                              # capture + first replay
     torch.cuda.synchronize()
     times = []
     stream = torch.cuda.current_stream()
     for _ in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        plan.forward()
+        step()
         b.record(stream)
         torch.cuda.synchronize()
         times.append(a.elapsed_time(b))
@@ -60,10 +66,11 @@ def _time_forward(plan: mirres.Plan, reps: int) -> float:
 
 def autotune(scene: mirres.GpuScene, views: Sequence, opts, pools: Sequence[int] = DEFAULT_POOLS,
              blocks: Sequence[int] = DEFAULT_BLOCKS, reps: int = 3, use_graph: bool = True,
-             cache: Optional[str] = "default", verbose: bool = False) -> Dict:
+             cache: Optional[str] = "default", verbose: bool = False, with_grad: bool = False) -> Dict:
     """Returns {"pool": P, "block": b, "ms": t, "table": [...]} for the fastest
-    forward pass; the caller copies pool/block into its RenderOptions."""
-    key = workload_key(scene, views, opts)
+    forward pass (with_grad: forward and backward, with dL/dI = 1 on every
+    pixel); the caller copies pool/block into its RenderOptions."""
+    key = workload_key(scene, views, opts, with_grad)
     path = _cache_path() if cache == "default" else cache
     if path:
         hit = _load(path).get(key)
@@ -77,8 +84,10 @@ def autotune(scene: mirres.GpuScene, views: Sequence, opts, pools: Sequence[int]
             continue
         for block in blocks:
             o = mirres.RenderOptions(**{**base.__dict__, "pool": int(pool), "block": int(block)})
-            plan = mirres.Plan(scene, views, o, use_graph=use_graph)
-            ms = _time_forward(plan, reps)
+            plan = mirres.Plan(scene, views, o, with_grad=with_grad, use_graph=use_graph)
+            if with_grad:
+                plan.grad_image.fill_(1.0)
+            ms = _time_plan(plan, reps, with_grad)
             del plan
             table.append({"pool": int(pool), "block": int(block), "ms": ms})
             if verbose:

@@ -10,6 +10,12 @@ is not correlated with the noise of the image it is computed from.
 
     python -m paper_2406_16360_amd.inverse --steps 200     # the full 1M-tri, 100x800^2 workload
     python -m paper_2406_16360_amd.inverse --small         # a reduced run
+
+With --ckpt PATH the loop saves the textures, the env, Adam's state, the step
+and the seen-texel masks every --ckpt-every steps (torch.save of tensors and
+numbers only, loaded back with weights_only=True); --resume continues from
+PATH.  With deterministic gradients (--deterministic) a resumed run gives the
+same bits as an uninterrupted one.
 """
 from __future__ import annotations
 
@@ -31,12 +37,14 @@ def _rmse(a: torch.Tensor, b: torch.Tensor, mask: torch.Tensor | None = None) ->
 
 
 def run(n_views=100, res=800, spp=2, target_spp=256, steps=200, lr=1e-2, rows=500, cols=1000, tex_res=4096,
-        env_hw=(512, 1024), bounces=5, ris_m=32, log_every=10, seed=5, fixed_env=False):
+        env_hw=(512, 1024), bounces=5, ris_m=32, log_every=10, seed=5, fixed_env=False, ckpt=None, ckpt_every=0,
+        resume=False, deterministic=False):
     w = synth.config5(n_views=n_views, res=res, rows=rows, cols=cols, tex_res=tex_res, env_hw=env_hw)
     for v in w.views:
         v.spp = spp
     opts = mirres.RenderOptions.from_any(w.opts)
     opts.bounces, opts.ris_m, opts.ris_m_brdf = bounces, ris_m, ris_m // 2
+    opts.deterministic = int(bool(deterministic))
     gt = mirres.GpuScene.from_synth(w.scene)
     t0 = time.perf_counter()
     targets = []
@@ -74,9 +82,24 @@ def run(n_views=100, res=800, spp=2, target_spp=256, steps=200, lr=1e-2, rows=50
         return e
 
     log = [{"step": 0, **errors()}]
+    start = 0
+    if resume:
+        st = torch.load(ckpt, map_location=albedo.device, weights_only=True)
+        with torch.no_grad():
+            for p, v in zip(params, st["params"]):
+                p.copy_(v)
+            for m, v in zip(seen, st["seen"]):
+                m.copy_(v)
+        optim.load_state_dict(st["optim"])
+        start, log = int(st["step"]), list(st["log"])
+
+    def save(step):
+        torch.save({"params": [p.detach() for p in params], "seen": seen, "optim": optim.state_dict(),
+                    "step": step, "log": log}, ckpt)
+
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for it in range(steps):
+    for it in range(start, steps):
         o = copy.copy(opts)
         o.seed = 1000 + it
         img = mirres.render_autograd(gt, w.views, o, albedo=albedo, rough=rough, metal=metal, env=env)
@@ -99,16 +122,19 @@ def run(n_views=100, res=800, spp=2, target_spp=256, steps=200, lr=1e-2, rows=50
             rec = {"step": it + 1, "loss": float(loss.detach()), **errors(), "s": time.perf_counter() - t1}
             log.append(rec)
             print(json.dumps(rec), flush=True)
+        if ckpt and ckpt_every and ((it + 1) % ckpt_every == 0 or it + 1 == steps):
+            save(it + 1)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
+    dt = max(time.perf_counter() - t1, 1e-9)
+    done = steps - start
     # step 0 over the texels the run ended up seeing (the mask is empty before the first step)
     log[0].update({k + "_seen": _rmse(p, t, m) for k, p, t, m in zip(names, init, truth, seen)})
     S = sum(v.w * v.h * v.spp for v in w.views)
     return {"workload": w.name, "triangles": w.scene.nf, "views": n_views, "res": res, "spp": spp,
             "target_spp": target_spp, "bounces": bounces, "ris_m": ris_m, "steps": steps, "lr": lr,
             "env_optimised": not fixed_env,
-            "steps_per_s": steps / dt, "samples_per_s": steps * S / dt, "target_render_s": t_target,
-            "initial": log[0], "final": log[-1]}
+            "steps_per_s": done / dt, "samples_per_s": done * S / dt, "target_render_s": t_target,
+            "initial": log[0], "final": log[-1], "params": [p.detach() for p in params]}
 
 
 def main():
@@ -120,14 +146,22 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-2)
     ap.add_argument("--spp", type=int, default=2)
     ap.add_argument("--fixed-env", action="store_true", help="hold the environment map at the ground truth")
+    ap.add_argument("--ckpt", default=None, help="checkpoint file")
+    ap.add_argument("--ckpt-every", type=int, default=0, help="save the checkpoint every K steps")
+    ap.add_argument("--resume", action="store_true", help="continue from --ckpt")
+    ap.add_argument("--deterministic", action="store_true", help="bitwise reproducible gradients (slower)")
     ap.add_argument("--small", action="store_true", help="8 views of 256^2, 100k triangles, 1024^2 textures")
     a = ap.parse_args()
+    if a.resume and not a.ckpt:
+        ap.error("--resume needs --ckpt")
+    kw = dict(fixed_env=a.fixed_env, ckpt=a.ckpt, ckpt_every=a.ckpt_every, resume=a.resume,
+              deterministic=a.deterministic)
     if a.small:
         res = run(n_views=8, res=256, spp=a.spp, target_spp=64, steps=a.steps, lr=a.lr, rows=158, cols=316,
-                  tex_res=1024, env_hw=(128, 256), fixed_env=a.fixed_env)
+                  tex_res=1024, env_hw=(128, 256), **kw)
     else:
-        res = run(n_views=a.views, res=a.res, spp=a.spp, target_spp=a.target_spp, steps=a.steps, lr=a.lr,
-                  fixed_env=a.fixed_env)
+        res = run(n_views=a.views, res=a.res, spp=a.spp, target_spp=a.target_spp, steps=a.steps, lr=a.lr, **kw)
+    res.pop("params")
     print(json.dumps(res), flush=True)
 
 

@@ -119,3 +119,7 @@ def test_autotune_small(mr, tmp_path):
     tuned = copy.copy(opts)
     tuned.pool, tuned.block = res["pool"], res["block"]
     assert torch.equal(mr.render(sc, views, tuned), mr.render(sc, views, opts))
+    # forward + backward plans are tuned under their own key
+    g = autotune.autotune(sc, views, opts, pools=(1 << 12, 1 << 14), blocks=(64,), reps=2, cache=cache,
+                          with_grad=True)
+    assert g["pool"] in (1 << 12, 1 << 14) and len(g["table"]) == 2
