@@ -491,6 +491,84 @@ __global__ void k_refit_nodes(int nnodes, BvhNode *__restrict__ nodes, const int
     }
 }
 
+// 1 for the binary nodes at even depth (the root at depth 0): the nodes that
+// get a traversal node.  Each thread climbs the parent links of its node.
+__global__ void k_wide_flags(const int32_t *__restrict__ npar, int nnodes, uint8_t *__restrict__ even) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnodes) return;
+    int d = 0;
+    for (int p = npar[i]; p >= 0 && d < nnodes; p = npar[p >> 1]) ++d;
+    even[i] = (d & 1) == 0;
+}
+
+// the smallest k with 253 * 2^k >= extent and 2^k >= one float ulp of
+// magnitude m (decoded bounds then round by less than a quantum)
+__device__ int wide_exponent(double extent, double m) {
+    int k = -126;
+    if (extent > 0.0) k = max(k, ilogb(extent / 253.0));
+    while (ldexp(253.0, k) < extent) ++k;
+    if (m > 0.0) k = max(k, ilogb(m) - 23);
+    return min(k, 127);
+}
+
+// Traversal node of every binary node at even depth: the children of its
+// two children (or a child itself when it is a leaf), boxes quantised
+// outwards against their union in double, one quantum of padding per side.
+__global__ void k_wide_build(const BvhNode *__restrict__ nodes, int nnodes, const uint8_t *__restrict__ even,
+                             WideNode *__restrict__ wn) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnodes || !even[i]) return;
+    float lo[4][3], hi[4][3];
+    int ref[4];
+    int nc = 0;
+    auto take = [&](const BvhNode &nd, int side) {
+        const float4 a = side ? nd.n1 : nd.n0;
+        const float zl = side ? nd.n2.z : nd.n2.x, zh = side ? nd.n2.w : nd.n2.y;
+        const int r = side ? nd.n3.y : nd.n3.x;
+        if (!(a.x <= a.y) || !(a.z <= a.w) || !(zl <= zh)) return false;   // empty slot
+        lo[nc][0] = a.x; hi[nc][0] = a.y; lo[nc][1] = a.z; hi[nc][1] = a.w; lo[nc][2] = zl; hi[nc][2] = zh;
+        ref[nc] = r;
+        ++nc;
+        return true;
+    };
+    const BvhNode nd = nodes[i];
+    for (int side = 0; side < 2; ++side) {
+        const int r = side ? nd.n3.y : nd.n3.x;
+        const float4 a = side ? nd.n1 : nd.n0;
+        const float zl = side ? nd.n2.z : nd.n2.x, zh = side ? nd.n2.w : nd.n2.y;
+        if (!(a.x <= a.y) || !(a.z <= a.w) || !(zl <= zh)) continue;       // empty slot
+        if (r < 0) { take(nd, side); continue; }
+        const BvhNode c = nodes[r];
+        take(c, 0);
+        take(c, 1);
+    }
+    WideNode w;
+    uint32_t meta = (uint32_t)nc << 24;
+    uint32_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+    float org[3] = {0.0f, 0.0f, 0.0f};
+    for (int ax = 0; ax < 3; ++ax) {
+        double L = INFINITY, H = -INFINITY;
+        for (int c = 0; c < nc; ++c) { L = fmin(L, (double)lo[c][ax]); H = fmax(H, (double)hi[c][ax]); }
+        if (nc == 0) { L = 0.0; H = 0.0; }
+        org[ax] = (float)L;                       // a float already: the smallest child bound
+        const int k = wide_exponent(H - L, fmax(fabs(L), fabs(H)));
+        meta |= (uint32_t)(k + 127) << (8 * ax);
+        const double sc = ldexp(1.0, k);
+        for (int c = 0; c < nc; ++c) {
+            const double ql = floor(((double)lo[c][ax] - (double)org[ax]) / sc) - 1.0;
+            const double qh = ceil(((double)hi[c][ax] - (double)org[ax]) / sc) + 1.0;
+            qlo[ax] |= (uint32_t)fmin(fmax(ql, 0.0), 255.0) << (8 * c);
+            qhi[ax] |= (uint32_t)fmin(fmax(qh, 0.0), 255.0) << (8 * c);
+        }
+    }
+    for (int c = nc; c < 4; ++c) ref[c] = 0;
+    w.a = make_float4(org[0], org[1], org[2], __uint_as_float(meta));
+    w.q = make_uint4(qlo[0], qhi[0], qlo[1], qhi[1]);
+    w.r = make_uint4(qlo[2], qhi[2], (uint32_t)ref[0], (uint32_t)ref[1]);
+    w.s = make_uint4((uint32_t)ref[2], (uint32_t)ref[3], 0u, 0u);
+    wn[i] = w;
+}
+
 __global__ void k_check_faces(const int32_t *__restrict__ faces, int nf, int nv, int32_t *__restrict__ bad) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
@@ -647,7 +725,9 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
         TRY(hip_check(hipMemcpyAsync(&h_depth, depth.p, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy"));
         TRY(hip_check(hipStreamSynchronize(s), "sync"));
         b->depth = h_depth;
-        if (h_depth + 2 > kStackSize) {
+        // a traversal node pushes at most 3 children, and a root-to-leaf path
+        // meets at most depth / 2 + 1 traversal nodes
+        if (3 * (h_depth / 2 + 1) + 2 > kStackSize) {
             st = fail(MRS_EOVERFLOW, "mrs_build_bvh: tree depth %d exceeds the traversal stack (%d)", h_depth, kStackSize);
             goto done;
         }
@@ -659,7 +739,13 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
     TRY(b->arrive.alloc(sizeof(int32_t) * b->nnodes));
     TRY(hip_check(hipMemsetAsync(b->npar.p, 0xFF, sizeof(int32_t) * b->nnodes, s), "memset"));
     k_node_parents<<<blocks(b->nnodes), 256, 0, s>>>((BvhNode *)b->nodes.p, b->nnodes, (int32_t *)b->npar.p);
-    TRY(hip_check(hipGetLastError(), "bvh parents"));
+    // traversal nodes
+    TRY(b->wnodes.alloc(sizeof(WideNode) * b->nnodes));
+    TRY(b->weven.alloc(b->nnodes));
+    k_wide_flags<<<blocks(b->nnodes), 256, 0, s>>>((const int32_t *)b->npar.p, b->nnodes, (uint8_t *)b->weven.p);
+    k_wide_build<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, b->nnodes,
+                                                   (const uint8_t *)b->weven.p, (WideNode *)b->wnodes.p);
+    TRY(hip_check(hipGetLastError(), "bvh parents and traversal nodes"));
     TRY(hip_check(hipStreamSynchronize(s), "sync"));
 #undef TRY
 done:
@@ -698,6 +784,8 @@ extern "C" mrs_status mrs_bvh_refit(mrs_bvh *b, const float *d_pos, int32_t nv, 
     k_refit_nodes<<<blocks(b->nnodes), 256, 0, s>>>(b->nnodes, (BvhNode *)b->nodes.p, (const int32_t *)b->npar.p,
                                                     (const TriRec *)b->tris.p, (float4 *)b->nlo.p, (float4 *)b->nhi.p,
                                                     (int32_t *)b->arrive.p);
+    k_wide_build<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, b->nnodes,
+                                                   (const uint8_t *)b->weven.p, (WideNode *)b->wnodes.p);
     return hip_check(hipGetLastError(), "mrs_bvh_refit launch");
 }
 

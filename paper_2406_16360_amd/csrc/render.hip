@@ -362,7 +362,7 @@ void bind_scene(const mrs_scene *sc, Job &job) {
     job.sd.faces = sc->bvh->faces.as<int32_t>(); job.sd.uv = sc->uv; job.sd.vmat = sc->vmat;
     job.sd.albedo = sc->albedo; job.sd.rough = sc->rough; job.sd.metal = sc->metal;
     job.sd.mat_mode = sc->mat_mode; job.sd.tw = sc->tw; job.sd.th = sc->th;
-    job.sd.nodes = sc->bvh->nodes.as<BvhNode>();
+    job.sd.nodes = sc->bvh->wnodes.as<WideNode>();
     job.sd.tris = sc->bvh->tris.as<TriRec>();
 }
 
@@ -915,7 +915,7 @@ extern "C" mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const f
     hipStream_t s = (hipStream_t)stream;
     {
         PROF(KID_TRACE, s);
-        k_trace_batch<<<nblocks((uint64_t)n, 256), 256, kLdsStackBytes * 256, s>>>(bvh->nodes.as<BvhNode>(), bvh->tris.as<TriRec>(),
+        k_trace_batch<<<nblocks((uint64_t)n, 256), 256, kLdsStackBytes * 256, s>>>(bvh->wnodes.as<WideNode>(), bvh->tris.as<TriRec>(),
                                                                d_orig, d_dir, n, any_hit ? 1 : 0, (float4 *)d_hit);
     }
     return hip_check(hipGetLastError(), "mrs_trace launch");

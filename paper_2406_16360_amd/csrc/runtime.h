@@ -64,6 +64,9 @@ struct mrs_bvh {
     // refit state: parent of every node slot ((slot << 1) | side, -1 at the
     // root), unpadded node boxes and arrival counters for the bottom-up pass
     mrs::DevBuf npar, nlo, nhi, arrive;
+    // traversal nodes (WideNode[nnodes], at the binary index of the node
+    // they stand for) and the flags of the binary nodes at even depth
+    mrs::DevBuf wnodes, weven;
 };
 
 struct mrs_tape {

@@ -1,5 +1,6 @@
-// BVH traversal for gfx950: closest hit and any hit over the LBVH node
-// layout (both child boxes per 64-byte node), with the watertight
+// BVH traversal for gfx950: closest hit and any hit over the traversal nodes
+// (four 8-bit quantised child boxes per 64-byte node, built from the binary
+// tree two levels at a time), with the watertight
 // ray-triangle test of Woop, Benthin and Wald (JCGT 2013): edges count as
 // inside, only t > 0 hits, degenerate triangles never hit, equal t resolves
 // to the lower original face id.
@@ -147,25 +148,64 @@ __device__ __forceinline__ Hit no_hit() {
 constexpr int kNone = INT_MIN;
 static_assert(kLeafMax <= 7, "leaf references encode count - 1 in three bits");
 
-// Inner-node visit: tests both child boxes against [0, tmax]; the nearer hit
-// child is next, the farther one is stacked; with no hit child the next
-// reference comes off the stack.
-__device__ __forceinline__ int inner_step(const BvhNode *__restrict__ nodes, const RayPre &r, float tmax, TStack &st,
+// Inner-node visit of a traversal node (WideNode): tests its up to four
+// child boxes against [0, tmax]; the nearest hit child is next, the other hit
+// children are stacked farthest first; with no hit child the next reference
+// comes off the stack.  A bound on axis a is o_a + q 2^e_a, so its slab
+// distance is q (2^e_a / d_a) + (o_a - origin_a) / d_a: one fma per bound.
+__device__ __forceinline__ void cswap(float &ta, int &ra, float &tb, int &rb) {
+    const bool sw = tb < ta;
+    const float t = sw ? tb : ta;
+    const int r = sw ? rb : ra;
+    tb = sw ? ta : tb; rb = sw ? ra : rb;
+    ta = t; ra = r;
+}
+__device__ __forceinline__ float qbyte(uint32_t w, int c) { return (float)((w >> (8 * c)) & 0xFFu); }
+template <bool kAny>
+__device__ __forceinline__ int inner_step(const WideNode *__restrict__ nodes, const RayPre &r, float tmax, TStack &st,
                                           int node, int ctr) {
-    BvhNode nd = nodes[node];
+    const WideNode nd = nodes[node];
     MRS_COUNT(ctr);
-    float tl, tr;
-    bool hl = slab(r, nd.n0.x, nd.n0.y, nd.n0.z, nd.n0.w, nd.n2.x, nd.n2.y, tmax, tl);
-    bool hr = slab(r, nd.n1.x, nd.n1.y, nd.n1.z, nd.n1.w, nd.n2.z, nd.n2.w, tmax, tr);
-    const int a = nd.n3.x, b = nd.n3.y;
-    if (hl && hr) {
-        bool lfirst = tl <= tr;
-        st.push(lfirst ? b : a);
-        return lfirst ? a : b;
+    const uint32_t meta = __float_as_uint(nd.a.w);
+    const int nc = (int)(meta >> 24);
+    const float mx = __uint_as_float((meta & 0xFFu) << 23) * r.inv.x, bx = (nd.a.x - r.o.x) * r.inv.x;
+    const float my = __uint_as_float(((meta >> 8) & 0xFFu) << 23) * r.inv.y, by = (nd.a.y - r.o.y) * r.inv.y;
+    const float mz = __uint_as_float(((meta >> 16) & 0xFFu) << 23) * r.inv.z, bz = (nd.a.z - r.o.z) * r.inv.z;
+    float t[4];
+    int ref[4] = {(int)nd.r.z, (int)nd.r.w, (int)nd.s.x, (int)nd.s.y};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float t0x = fmaf(qbyte(nd.q.x, c), mx, bx), t1x = fmaf(qbyte(nd.q.y, c), mx, bx);
+        const float t0y = fmaf(qbyte(nd.q.z, c), my, by), t1y = fmaf(qbyte(nd.q.w, c), my, by);
+        const float t0z = fmaf(qbyte(nd.r.x, c), mz, bz), t1z = fmaf(qbyte(nd.r.y, c), mz, bz);
+        const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+        const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+        t[c] = (c < nc && tn <= tf * 1.0000008f) ? tn : INFINITY;
     }
-    if (hl) return a;
-    if (hr) return b;
-    return st.sp > 0 ? st.pop() : kNone;
+    if (kAny) {
+        // any hit ends the ray, so the order of the hit children only moves
+        // the work around: the first hit child is next, the others stacked
+        int next = kNone;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (t[c] == INFINITY) continue;
+            if (next == kNone) next = ref[c];
+            else st.push(ref[c]);
+        }
+        if (next != kNone) return next;
+        return st.sp > 0 ? st.pop() : kNone;
+    }
+    // ascending by entry distance (misses last)
+    cswap(t[0], ref[0], t[1], ref[1]);
+    cswap(t[2], ref[2], t[3], ref[3]);
+    cswap(t[0], ref[0], t[2], ref[2]);
+    cswap(t[1], ref[1], t[3], ref[3]);
+    cswap(t[1], ref[1], t[2], ref[2]);
+    if (t[0] == INFINITY) return st.sp > 0 ? st.pop() : kNone;
+    if (t[3] != INFINITY) st.push(ref[3]);
+    if (t[2] != INFINITY) st.push(ref[2]);
+    if (t[1] != INFINITY) st.push(ref[1]);
+    return ref[0];
 }
 
 // Leaf visit for the closest hit: all its triangles, then the next stacked
@@ -217,19 +257,19 @@ __device__ __forceinline__ int any_leaf(const TriRec *__restrict__ tris, const R
 // lower face id) does not depend on the order of the visits.  Every lane
 // that is in the calling loop must call this.
 template <bool kAny>
-__device__ __forceinline__ void trace_iter(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+__device__ __forceinline__ void trace_iter(const WideNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                            bool live, const RayPre &r, Hit &h, bool &occl, TStack &st, int &node) {
     const bool at_leaf = live && node < 0;
     const uint64_t leaves = __ballot(at_leaf), inner = __ballot(live && node >= 0);
     if (inner == 0 || __popcll(leaves) >= (kAny ? MRS_LEAF_BATCH : MRS_LEAF_BATCH_CLOSEST)) {
         if (at_leaf) node = kAny ? any_leaf(tris, r, st, node, occl) : closest_leaf(tris, r, h, st, node);
     }
-    if (live && node >= 0) node = inner_step(nodes, r, kAny ? INFINITY : h.t, st, node, kAny ? 2 : 0);
+    if (live && node >= 0) node = inner_step<kAny>(nodes, r, kAny ? INFINITY : h.t, st, node, kAny ? 2 : 0);
 }
 
 // One ray per lane, all lanes of the wavefront iterating together.
 template <bool kAny>
-__device__ __forceinline__ void trace_wave(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris, V3 o,
+__device__ __forceinline__ void trace_wave(const WideNode *__restrict__ nodes, const TriRec *__restrict__ tris, V3 o,
                                            V3 d, void *lds, Hit &h, bool &occl) {
     RayPre r = ray_pre(o, d);
     h = no_hit();
@@ -241,7 +281,7 @@ __device__ __forceinline__ void trace_wave(const BvhNode *__restrict__ nodes, co
 }
 
 // closest hit: smallest t > 0, ties to the lower original face id
-__device__ __forceinline__ Hit trace_closest(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+__device__ __forceinline__ Hit trace_closest(const WideNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                              V3 o, V3 d, void *lds) {
     Hit h;
     bool occl;
@@ -250,7 +290,7 @@ __device__ __forceinline__ Hit trace_closest(const BvhNode *__restrict__ nodes, 
 }
 
 // any hit in (0, inf): visibility of a shadow ray
-__device__ __forceinline__ bool trace_any(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+__device__ __forceinline__ bool trace_any(const WideNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                           V3 o, V3 d, void *lds) {
     Hit h;
     bool occl;
@@ -281,7 +321,7 @@ static_assert(MRS_REFILL >= 1 && MRS_REFILL <= 64, "a refill needs between 1 and
 // done(i, hit, occluded) stores its result.  Every lane of the launch must
 // call this (block sizes are multiples of 64).
 template <bool kAny, class Load, class Done>
-__device__ __forceinline__ void persistent_trace(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+__device__ __forceinline__ void persistent_trace(const WideNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                                  uint32_t n, uint32_t *claim, void *lds, Load load, Done done) {
     int spill[kSpillStack];
     TStack st = make_stack(lds, spill);

@@ -51,7 +51,7 @@ struct SceneDev {
     const float4 *fm;   // field mode: materials from the field pass (per pool entry in shade, per vertex in the adjoint)
     const float4 *tpack; // texture mode: per texel (albedo rgb, roughness), (metallic, -, -, -), packed per call
     int mat_mode, tw, th;
-    const BvhNode *nodes;
+    const WideNode *nodes;   // traversal nodes
     const TriRec *tris;
     EnvTables env;
 };
@@ -472,14 +472,15 @@ __global__ void k_generate(GenArgs a) {
 }
 
 struct TraceArgs {
-    const BvhNode *nodes; const TriRec *tris;
+    const WideNode *nodes; const TriRec *tris;
     Queue q; float4 *hits; IterCtr *ctr; int it;
     uint32_t *claim;      // kClaimWords zeroed claim counters
     int continuing_only;  // trace only the continuing rays (the camera rays' hits are given)
 };
 
-// persistent: launched with a fixed grid that fills the device once
-__global__ __launch_bounds__(256) void k_trace_closest(TraceArgs a) {
+// persistent: launched with a fixed grid that fills the device once, held to
+// 8 wavefronts per SIMD (64 VGPRs), the occupancy its grid is sized for
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_trace_closest(TraceArgs a) {
     extern __shared__ int lds_stack[];
     IterCtr &c = a.ctr[a.it];
     const uint32_t n = a.continuing_only ? c.n_in : c.n_live;
@@ -737,7 +738,7 @@ __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS
 }
 
 struct ShadowArgs {
-    const BvhNode *nodes; const TriRec *tris;
+    const WideNode *nodes; const TriRec *tris;
     float4 *so, *sd, *sc; IterCtr *ctr; int it;
     float4 *out; uint64_t out_base; uint32_t *hash;
     Tape tape; int use_tape;
@@ -1249,7 +1250,7 @@ __global__ void k_grad_fold(FoldArgs f) {
     }
 }
 
-__global__ void k_trace_batch(const BvhNode *__restrict__ nodes, const TriRec *__restrict__ tris,
+__global__ void k_trace_batch(const WideNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                               const float *__restrict__ orig, const float *__restrict__ dir, int64_t n, int any,
                               float4 *__restrict__ out) {
     extern __shared__ int lds_stack[];
@@ -1267,7 +1268,7 @@ __global__ void k_trace_batch(const BvhNode *__restrict__ nodes, const TriRec *_
 
 // denoiser G-buffer: closest hit of the ray through each pixel centre
 struct GbufArgs {
-    const BvhNode *nodes; const TriRec *tris;
+    const WideNode *nodes; const TriRec *tris;
     ViewTable vt; uint64_t pixels;
     float *position, *normal;
 };
