@@ -8,7 +8,8 @@
 //   - PLOC (Meister and Bittner, TVCG 2018): rounds of nearest-neighbour
 //     merging over the same order;
 //   -> node layout with both child boxes per node, small subtrees collapsed
-//   into leaves of <= 4 triangles, triangles copied in leaf order.
+//   into leaves of <= kLeafMax triangles, triangles copied in leaf order;
+//   then the traversal nodes (four quantised child boxes) over that tree.
 // Refit moves the triangles to new vertex positions and recomputes the boxes
 // over the unchanged tree (the per-iteration update while vertices move).
 #include <hip/hip_runtime.h>

@@ -16,7 +16,7 @@ constexpr float kRoughMin = 0.05f;
 constexpr float kF0Dielectric = 0.04f;
 constexpr uint32_t kBlockCont = 0xFFFFu;   // Philox block of the continuation sample
 constexpr int kStackSize = 160;            // traversal stack (tree depth is checked at build)
-constexpr int kLeafMax = 4;                // triangles per collapsed leaf
+constexpr int kLeafMax = 2;                // triangles per collapsed leaf
 
 // ----------------------------------------------------------------------------
 // vector helpers
