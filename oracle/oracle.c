@@ -1000,8 +1000,8 @@ static void camera_ray(const orc_view *vw, int x, int y, double u0, double u1, d
  * jitter x 2^-24 per component and renormalised, from the Philox stream of
  * (pixel, sample, view, vertex k, block 0xC000 + slot) under key jitter_seed:
  * slot 0 the camera ray, 1 the geometric normal, 2 the continuation
- * direction, 16 + s candidate s.  It stands for the rounding an FP32
- * evaluation of the same path commits. */
+ * direction, 3 the field's input point, 16 + s candidate s.  It stands for
+ * the rounding an FP32 evaluation of the same path commits. */
 static void jitter_unit(const orc_options *opt, uint32_t pixel, uint32_t sc, uint32_t vi, int k, uint32_t slot,
                         double d[3]) {
     if (!(opt->jitter > 0.0)) return;
@@ -1040,11 +1040,24 @@ static void shading_point(const orc_ctx *c, const hitrec *hr, const double d[3],
 }
 
 /* the normal of shading point S of vertex k after the conditioning hook,
- * and its frame */
-static void jitter_normal(const orc_options *opt, uint32_t pixel, uint32_t sc, uint32_t vi, int k, shpt *S) {
+ * and its frame; with the material field, also the point the field is
+ * evaluated at (slot 3: each coordinate moved by up to jitter x 2^-24 of
+ * max(1, |coordinate|), the rounding of an FP32 hit position) and the
+ * material there */
+static void jitter_normal(const orc_ctx *c, const orc_options *opt, uint32_t pixel, uint32_t sc, uint32_t vi, int k,
+                          shpt *S) {
     if (!(opt->jitter > 0.0)) return;
     jitter_unit(opt, pixel, sc, vi, k, 1, S->n);
     orc_frame(S->n, S->t, S->b);
+    if (c->s.mat_mode == 2) {
+        double u[4];
+        uniforms4(opt->jitter_seed, pixel, sc, vi, (uint32_t)k, 0xC000u + 3u, u);
+        const double eps = opt->jitter * (1.0 / 16777216.0);
+        for (int a = 0; a < 3; ++a) S->p[a] += eps * fmax(1.0, fabs(S->p[a])) * (2.0 * u[a] - 1.0);
+        dual md[5]; seed_t none = { PK_NONE, -1 };
+        material_field_d(c, S->p, k, none, md);
+        for (int ch = 0; ch < 5; ++ch) S->m[ch] = md[ch].v;
+    }
 }
 
 /* RIS over Me env + Mb BRDF candidates with a streaming weighted reservoir
@@ -1179,7 +1192,7 @@ static int primary_vertex(const orc_ctx *c, const orc_view *views, int32_t vi, i
     hitrec hr = trace_closest(c, o, d, 0, &cnt[ORC_C_CLOSEST_NODES], &cnt[ORC_C_CLOSEST_TRIS]);
     if (hr.prim < 0) return 0;
     shading_point(c, &hr, d, 0, S);
-    jitter_normal(opt, (uint32_t)pixel, sc, (uint32_t)vi, 1, S);
+    jitter_normal(c, opt, (uint32_t)pixel, sc, (uint32_t)vi, 1, S);
     risres rr;
     ris_vertex(c, S, opt, (uint32_t)pixel, sc, (uint32_t)vi, 1, &rr, h, cnt);
     for (int a = 0; a < 3; ++a) r0->y[a] = rr.y[a];
@@ -1305,7 +1318,7 @@ static void trace_path(const orc_ctx *c, const orc_view *views, int32_t vi, int3
         V->nee = 0; V->W = 0.0; V->ytex = -1; V->q = 0.0; V->rr = 1.0;
         shpt Sp;
         shading_point(c, &hr, d, rec->nv - 1, &Sp);
-        jitter_normal(opt, (uint32_t)pixel, S, (uint32_t)vi, k, &Sp);
+        jitter_normal(c, opt, (uint32_t)pixel, S, (uint32_t)vi, k, &Sp);
         for (int a = 0; a < 3; ++a) { V->p[a] = Sp.p[a]; V->n[a] = Sp.n[a]; V->wo[a] = Sp.wo[a]; }
         const double *m = Sp.m;
         double pn = fmax(fabs(V->p[0]), fmax(fabs(V->p[1]), fabs(V->p[2])));

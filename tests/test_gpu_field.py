@@ -172,6 +172,19 @@ def test_field_gradient_matches_oracle(mr, orc_mod, kind, grad_mode):
     _grad_check(mr, orc_mod, w, r, label=f"field-{kind}-gm{grad_mode}", tape_rel=1e-4)
 
 
+@pytest.mark.parametrize("kind", ["c1", "textured"])
+def test_field_flat_tables_match_oracle(mr, orc_mod, kind):
+    """Tables of equal amplitude on every level (decay 0): the finest levels
+    make the material change fast with the hit position, so the oracle's
+    conditioning trials move the field's input point by FP32 rounding too.
+    Per-pixel bar and gradient bar as for the default tables."""
+    from tests.test_gpu_parity import _forward, _grad_check, _pixel_check
+    w = _field_workload(kind, decay=0.0)
+    r = _forward(mr, orc_mod, w, label=f"field-flat-{kind}")
+    _pixel_check(w, r, f"field-flat-{kind}")
+    _grad_check(mr, orc_mod, w, r, label=f"field-flat-{kind}", tape_rel=1e-4)
+
+
 def test_constant_field_matches_vertex_materials_on_gpu(mr):
     """A constant field renders like constant per-vertex materials (metallic 0)."""
     w = synth.config1()
