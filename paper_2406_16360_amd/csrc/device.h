@@ -274,10 +274,13 @@ __device__ __forceinline__ BrdfGrad brdf_grad(const Lobe &L, const Mat &m, V3 wi
 // so one aligned 16-byte load gives both ends of a bin.
 struct EnvTables {
     const double2 *mpair;   // [H] marginal CDF over rows, as intervals
-    const double2 *cpair;   // [H][W] conditional CDF of each row, as intervals
+    // [H][W] 32-byte texel records: the interval of the row's conditional CDF
+    // (cdf[j], cdf[j + 1]) as a double2, then (L_r, L_g, L_b clamped >= 0,
+    // pdf_uv / (2 pi^2)); an env candidate's last interval load and its
+    // radiance load then touch the same cache line
+    const float4 *rec;
     const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
     const int32_t *gcond;   // [H][W] guide per row
-    const float4 *lp;       // [H][W] (L_r, L_g, L_b clamped >= 0, pdf_uv / (2 pi^2))
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
     const double *total;    // device: total sampling weight (no valid sample when 0)
@@ -354,15 +357,19 @@ __device__ __forceinline__ double2 buffer_double2(__amdgpu_buffer_rsrc_t r, uint
     return make_double2(__hiloint2double((int)q.y, (int)q.x), __hiloint2double((int)q.w, (int)q.z));
 }
 
-// the env's per-texel tables as buffer resources (W H < 2^28 texels, so the
+// radiance and pdf entry of texel t
+__device__ __forceinline__ float4 env_lp(const EnvTables &e, int t) { return e.rec[2 * (size_t)t + 1]; }
+
+// the env's texel records as a buffer resource (W H < 2^27 texels, so the
 // byte offsets fit in 32 bits)
 struct EnvBufs {
-    __amdgpu_buffer_rsrc_t cpair, lp;
+    __amdgpu_buffer_rsrc_t rec;
 };
 __device__ __forceinline__ EnvBufs env_bufs(const EnvTables &e) {
-    const uint32_t bytes = (uint32_t)e.W * (uint32_t)e.H * 16u;
-    return EnvBufs{buffer_rsrc(e.cpair, bytes), buffer_rsrc(e.lp, bytes)};
+    const uint32_t bytes = (uint32_t)e.W * (uint32_t)e.H * 32u;
+    return EnvBufs{buffer_rsrc(e.rec, bytes)};
 }
+__device__ __forceinline__ float4 env_lp(const EnvBufs &eb, uint32_t t) { return buffer_float4(eb.rec, 2u * t + 1u); }
 
 // smallest i with cdf[i + 1] > u (cdf[0] = 0 <= u < 1 = cdf[n]): the unique i
 // with cdf[i] <= u < cdf[i + 1], over the intervals iv[i] = (cdf[i], cdf[i + 1]).
@@ -375,13 +382,13 @@ __device__ __forceinline__ int interval_walk(const double2 *iv, int start, int n
     while (i < n - 1 && !(p.y > u)) { ++i; p = iv[i]; }
     return i;
 }
-// the same walk over the intervals base .. base + n - 1 of a buffer resource
-__device__ __forceinline__ int interval_walk(__amdgpu_buffer_rsrc_t iv, uint32_t base, int start, int n, double u,
+// the same walk over the intervals of texel records base .. base + n - 1
+__device__ __forceinline__ int interval_walk(__amdgpu_buffer_rsrc_t rec, uint32_t base, int start, int n, double u,
                                              double2 &p) {
     int i = min(max(start, 0), n - 1);
-    p = buffer_double2(iv, base + i);
-    while (i > 0 && p.x > u) { --i; p = buffer_double2(iv, base + i); }
-    while (i < n - 1 && !(p.y > u)) { ++i; p = buffer_double2(iv, base + i); }
+    p = buffer_double2(rec, 2u * (base + i));
+    while (i > 0 && p.x > u) { --i; p = buffer_double2(rec, 2u * (base + i)); }
+    while (i < n - 1 && !(p.y > u)) { ++i; p = buffer_double2(rec, 2u * (base + i)); }
     return i;
 }
 
@@ -396,7 +403,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     // the CDF differences are formed in double, the in-texel fractions in float
     float fv = __fdividef((float)(u0 - pm.x), (float)(pm.y - pm.x));
     const uint32_t row = (uint32_t)i * (uint32_t)e.W;
-    int j = interval_walk(eb.cpair, row, e.gcond[row + min((int)(u1 * e.W), e.W - 1)], e.W, u1, pc);
+    int j = interval_walk(eb.rec, row, e.gcond[row + min((int)(u1 * e.W), e.W - 1)], e.W, u1, pc);
     float fu = __fdividef((float)(u1 - pc.x), (float)(pc.y - pc.x));
     float v = ((float)i + fv) / (float)e.H, u = ((float)j + fu) / (float)e.W;
     float st, ct, sp, cp;
@@ -405,7 +412,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     if (!(st > 0.0f)) return false;
     dir = V3{st * sp, ct, -st * cp};
     texel = i * e.W + j;
-    lp = buffer_float4(eb.lp, (uint32_t)texel);
+    lp = env_lp(eb, (uint32_t)texel);
     pdf = lp.w / st;
     return pdf > 0.0f;
 }

@@ -70,7 +70,7 @@ __device__ __forceinline__ float phat_at(const EnvTables &env, const PrimVtx &v,
     const V3 wl = to_local(v.S.F, y);
     if (!(wl.z > 0.0f)) return 0.0f;
     const V3 f = brdf_eval(v.L, wl);
-    const float4 lp = env.lp[env_texel_of(env, y)];
+    const float4 lp = env_lp(env, env_texel_of(env, y));
     return (lp.x * f.x + lp.y * f.y + lp.z * f.z) * (1.0f / 3.0f) * wl.z;
 }
 

@@ -374,18 +374,20 @@ __global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__r
     info[0] = acc;
 }
 
-// radiance + pdf table and the guide tables of both CDFs
+// texel records (conditional CDF interval, radiance + pdf), the marginal
+// intervals and the guide tables of both CDFs
 __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
                              const double *__restrict__ info, const double *__restrict__ marg,
-                             const double *__restrict__ cond, float4 *__restrict__ lp, int32_t *__restrict__ gmarg,
-                             int32_t *__restrict__ gcond, double2 *__restrict__ mpair, double2 *__restrict__ cpair,
+                             const double *__restrict__ cond, float4 *__restrict__ rec, int32_t *__restrict__ gmarg,
+                             int32_t *__restrict__ gcond, double2 *__restrict__ mpair,
                              double *__restrict__ rcos, double2 *__restrict__ csphi) {
     int i = blockIdx.x;
     double total = info[0];
+    double2 *riv = (double2 *)rec;   // record t: interval at riv[2 t], radiance + pdf at rec[2 t + 1]
     // the CDFs as intervals (cdf[t], cdf[t + 1])
     if (i < H) {
         const double *cr = cond + (size_t)i * (W + 1);
-        for (int j = threadIdx.x; j < W; j += blockDim.x) cpair[(size_t)i * W + j] = make_double2(cr[j], cr[j + 1]);
+        for (int j = threadIdx.x; j < W; j += blockDim.x) riv[2 * ((size_t)i * W + j)] = make_double2(cr[j], cr[j + 1]);
     } else {
         for (int t = threadIdx.x; t < H; t += blockDim.x) mpair[t] = make_double2(marg[t], marg[t + 1]);
     }
@@ -394,8 +396,8 @@ __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const 
         const double *cr = cond + (size_t)i * (W + 1);
         for (int j = threadIdx.x; j < W; j += blockDim.x) {
             const float *L = env + ((size_t)i * W + j) * 3;
-            lp[(size_t)i * W + j] = make_float4(fmaxf(L[0], 0.0f), fmaxf(L[1], 0.0f), fmaxf(L[2], 0.0f),
-                                                (float)(wts[(size_t)i * W + j] * scale));
+            rec[2 * ((size_t)i * W + j) + 1] = make_float4(fmaxf(L[0], 0.0f), fmaxf(L[1], 0.0f), fmaxf(L[2], 0.0f),
+                                                           (float)(wts[(size_t)i * W + j] * scale));
             double t = (double)j / W;
             int lo = 0, hi = W - 1;   // smallest c with cr[c + 1] > t
             while (lo < hi) { int mid = (lo + hi) >> 1; if (cr[mid + 1] > t) hi = mid; else lo = mid + 1; }
@@ -525,7 +527,7 @@ __device__ __forceinline__ void ris_candidate(const EnvTables &env, const EnvBuf
         dir = to_world(F, wl);
         tex = env_texel_of(env, dir);
         if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
-        lp = buffer_float4(eb.lp, (uint32_t)tex);
+        lp = env_lp(eb, (uint32_t)tex);
         qe = env_pdf_dir(env_ok, dir, lp);
     }
     if (!(wl.z > 0.0f)) return;
@@ -573,7 +575,7 @@ __device__ __forceinline__ void reused_sample(const EnvTables &env, const Lobe &
     const V3 wl = to_local(F, y);
     if (!(wl.z > 0.0f)) return;
     const int tex = env_texel_of(env, y);
-    const float4 lp = env.lp[tex];
+    const float4 lp = env_lp(env, tex);
     o.sel = 0; o.y = y; o.fy = brdf_eval(L, wl); o.Ly = V3{lp.x, lp.y, lp.z};
     o.ytex = tex; o.cos_y = wl.z; o.W = r.yw.w;
 }
@@ -652,7 +654,7 @@ __global__ __launch_bounds__(kShadeBlock) __attribute__((amdgpu_waves_per_eu(MRS
             int tex = -1;
             if (k == 1 && a.op.background == MRS_BG_ENV) {
                 tex = env_texel_of(a.s.env, d);
-                float4 L = a.s.env.lp[tex];
+                float4 L = env_lp(a.s.env, tex);
                 a.out[g - a.out_base] = make_float4(L.x, L.y, L.z, 0.0f);
             }
             hev = ev_miss((uint32_t)k);
@@ -1077,7 +1079,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
         if (ty.w > 0.0f) {
             V3 yl = to_local(S.F, xyz(ty));
             V3 f = brdf_eval(L, yl);
-            float4 lp = a.s.env.lp[__float_as_int(th.w)];
+            float4 lp = env_lp(a.s.env, __float_as_int(th.w));
             D = V3{lp.x, lp.y, lp.z} * f * (yl.z * ty.w);
         }
         Dk[k - 1] = D;
@@ -1129,7 +1131,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
             if (ty.w > 0.0f) {
                 V3 yl = to_local(S.F, xyz(ty));
                 int tex = __float_as_int(th.w);
-                float4 lp = a.s.env.lp[tex];
+                float4 lp = env_lp(a.s.env, tex);
                 V3 Lv = V3{lp.x, lp.y, lp.z};
                 float cw = yl.z * ty.w;
                 BrdfGrad bg = brdf_grad(L, m, yl);
