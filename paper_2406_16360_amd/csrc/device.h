@@ -276,11 +276,11 @@ struct EnvTables {
     const double2 *mpair;   // [H] marginal CDF over rows, as intervals
     // [H][W] 32-byte texel records: the interval of the row's conditional CDF
     // (cdf[j], cdf[j + 1]) as a double2, then (L_r, L_g, L_b clamped >= 0,
-    // pdf_uv / (2 pi^2)); an env candidate's last interval load and its
-    // radiance load then touch the same cache line
+    // guide g as int bits), g the first column whose bin ends above j / W.
+    // An env candidate's guide, interval and radiance loads then mostly touch
+    // one cache line; the pdf is formed from the two CDF intervals.
     const float4 *rec;
     const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
-    const int32_t *gcond;   // [H][W] guide per row
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
     const double *total;    // device: total sampling weight (no valid sample when 0)
@@ -330,12 +330,20 @@ __device__ __forceinline__ int env_texel_of(const EnvTables &e, V3 d) {
 // callers, so that the loads inside a candidate loop are not split by it)
 __device__ __forceinline__ bool env_valid(const EnvTables &e) { return *e.total > 0.0; }
 
-// solid-angle pdf of the env sampler at direction d, with its texel radiance;
-// ok = env_valid(e)
-__device__ __forceinline__ float env_pdf_dir(bool ok, V3 d, float4 lp) {
+// density of the env sampler over the unit square of texel coordinates,
+// divided by 2 pi^2: row probability x column probability x W H / (2 pi^2),
+// from the marginal interval pm of the row and the conditional interval pc
+// of the texel
+__device__ __forceinline__ float env_pdf_uv(double2 pm, double2 pc, int W, int H) {
+    return (float)((pm.y - pm.x) * (pc.y - pc.x) * ((double)W * (double)H * 0.050660591821168885));
+}
+
+// solid-angle pdf of the env sampler at direction d, from the pdf_uv / (2 pi^2)
+// of its texel; ok = env_valid(e)
+__device__ __forceinline__ float env_pdf_dir(bool ok, V3 d, float puv) {
     if (!ok) return 0.0f;
     float st = sqrtf(d.x * d.x + d.z * d.z);   // sin theta without the cancellation of 1 - d_y^2 near the poles
-    return st > 0.0f ? lp.w / st : 0.0f;
+    return st > 0.0f ? puv / st : 0.0f;
 }
 
 // 16-byte loads through a raw buffer resource over [base, base + bytes) (base
@@ -357,7 +365,7 @@ __device__ __forceinline__ double2 buffer_double2(__amdgpu_buffer_rsrc_t r, uint
     return make_double2(__hiloint2double((int)q.y, (int)q.x), __hiloint2double((int)q.w, (int)q.z));
 }
 
-// radiance and pdf entry of texel t
+// radiance entry of texel t (w: the guide bits)
 __device__ __forceinline__ float4 env_lp(const EnvTables &e, int t) { return e.rec[2 * (size_t)t + 1]; }
 
 // the env's texel records as a buffer resource (W H < 2^27 texels, so the
@@ -370,6 +378,10 @@ __device__ __forceinline__ EnvBufs env_bufs(const EnvTables &e) {
     return EnvBufs{buffer_rsrc(e.rec, bytes)};
 }
 __device__ __forceinline__ float4 env_lp(const EnvBufs &eb, uint32_t t) { return buffer_float4(eb.rec, 2u * t + 1u); }
+__device__ __forceinline__ double2 env_iv(const EnvBufs &eb, uint32_t t) { return buffer_double2(eb.rec, 2u * t); }
+__device__ __forceinline__ int env_guide(const EnvBufs &eb, uint32_t t) {
+    return __builtin_amdgcn_raw_buffer_load_b32(eb.rec, (2u * t + 1u) * 16u + 12u, 0, 0);
+}
 
 // smallest i with cdf[i + 1] > u (cdf[0] = 0 <= u < 1 = cdf[n]): the unique i
 // with cdf[i] <= u < cdf[i + 1], over the intervals iv[i] = (cdf[i], cdf[i + 1]).
@@ -403,7 +415,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     // the CDF differences are formed in double, the in-texel fractions in float
     float fv = __fdividef((float)(u0 - pm.x), (float)(pm.y - pm.x));
     const uint32_t row = (uint32_t)i * (uint32_t)e.W;
-    int j = interval_walk(eb.rec, row, e.gcond[row + min((int)(u1 * e.W), e.W - 1)], e.W, u1, pc);
+    int j = interval_walk(eb.rec, row, env_guide(eb, row + (uint32_t)min((int)(u1 * e.W), e.W - 1)), e.W, u1, pc);
     float fu = __fdividef((float)(u1 - pc.x), (float)(pc.y - pc.x));
     float v = ((float)i + fv) / (float)e.H, u = ((float)j + fu) / (float)e.W;
     float st, ct, sp, cp;
@@ -413,7 +425,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     dir = V3{st * sp, ct, -st * cp};
     texel = i * e.W + j;
     lp = env_lp(eb, (uint32_t)texel);
-    pdf = lp.w / st;
+    pdf = env_pdf_uv(pm, pc, e.W, e.H) / st;
     return pdf > 0.0f;
 }
 

@@ -379,8 +379,7 @@ __global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__r
 __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
                              const double *__restrict__ info, const double *__restrict__ marg,
                              const double *__restrict__ cond, float4 *__restrict__ rec, int32_t *__restrict__ gmarg,
-                             int32_t *__restrict__ gcond, double2 *__restrict__ mpair,
-                             double *__restrict__ rcos, double2 *__restrict__ csphi) {
+                             double2 *__restrict__ mpair, double *__restrict__ rcos, double2 *__restrict__ csphi) {
     int i = blockIdx.x;
     double total = info[0];
     double2 *riv = (double2 *)rec;   // record t: interval at riv[2 t], radiance + pdf at rec[2 t + 1]
@@ -391,17 +390,16 @@ __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const 
     } else {
         for (int t = threadIdx.x; t < H; t += blockDim.x) mpair[t] = make_double2(marg[t], marg[t + 1]);
     }
-    double scale = total > 0.0 ? (double)W * (double)H / (2.0 * 3.14159265358979323846 * 3.14159265358979323846 * total) : 0.0;
+    (void)total; (void)wts;
     if (i < H) {
         const double *cr = cond + (size_t)i * (W + 1);
         for (int j = threadIdx.x; j < W; j += blockDim.x) {
             const float *L = env + ((size_t)i * W + j) * 3;
-            rec[2 * ((size_t)i * W + j) + 1] = make_float4(fmaxf(L[0], 0.0f), fmaxf(L[1], 0.0f), fmaxf(L[2], 0.0f),
-                                                           (float)(wts[(size_t)i * W + j] * scale));
             double t = (double)j / W;
-            int lo = 0, hi = W - 1;   // smallest c with cr[c + 1] > t
+            int lo = 0, hi = W - 1;   // smallest c with cr[c + 1] > t: the guide of cell j
             while (lo < hi) { int mid = (lo + hi) >> 1; if (cr[mid + 1] > t) hi = mid; else lo = mid + 1; }
-            gcond[(size_t)i * W + j] = lo;
+            rec[2 * ((size_t)i * W + j) + 1] = make_float4(fmaxf(L[0], 0.0f), fmaxf(L[1], 0.0f), fmaxf(L[2], 0.0f),
+                                                           __int_as_float(lo));
         }
     } else {
         for (int t0 = threadIdx.x; t0 < H; t0 += blockDim.x) {
@@ -528,7 +526,8 @@ __device__ __forceinline__ void ris_candidate(const EnvTables &env, const EnvBuf
         tex = env_texel_of(env, dir);
         if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
         lp = env_lp(eb, (uint32_t)tex);
-        qe = env_pdf_dir(env_ok, dir, lp);
+        const double2 pc = env_iv(eb, (uint32_t)tex);
+        qe = env_pdf_dir(env_ok, dir, env_pdf_uv(marg.pair[tex / env.W], pc, env.W, env.H));
     }
     if (!(wl.z > 0.0f)) return;
     V3 f = brdf_eval_pdf(L, wl, qb);
