@@ -204,9 +204,12 @@ typedef struct {
 /* Builds a linear BVH (Karras, HPG 2012; the paper's LBVH, Appendix A) over
  * the triangles.  d_pos [nv][3] and d_faces [nf][3] are device arrays; the
  * BVH keeps its own copy of the triangles in leaf order, so the inputs may be
- * freed afterwards.  Degenerate triangles are kept and never hit.  Waits for
- * `stream` before returning.  Errors: MRS_EINVAL (null, nv/nf <= 0, nf >
- * 2^27), MRS_ENOMEM, MRS_EHIP. */
+ * freed afterwards.  Degenerate triangles are kept and never hit.  Rays
+ * traverse a collapse of the binary tree into nodes of up to four children
+ * chosen to minimise the summed surface area of the nodes.  Waits for
+ * `stream` before returning.  Errors: MRS_EINVAL (null, nv/nf <= 0, a face
+ * index outside [0, nv)), MRS_EOVERFLOW (nf > 2^27, or a tree so deep that a
+ * traversal could overflow its stack of 160 entries), MRS_ENOMEM, MRS_EHIP. */
 mrs_status mrs_build_bvh(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t nf,
                          void *stream, mrs_bvh **out);
 
@@ -215,7 +218,7 @@ enum {
     MRS_BVH_LBVH = 0,   /* Karras radix tree: what mrs_build_bvh builds */
     MRS_BVH_PLOC = 1    /* Meister and Bittner, "Parallel Locally-Ordered Clustering for Bounding
                            Volume Hierarchy Construction" (TVCG 2018): rounds that merge mutual
-                           nearest neighbours within 16 sorted positions by the surface area of
+                           nearest neighbours within 32 sorted positions by the surface area of
                            their union box.  Fewer node visits per ray, longer build. */
 };
 

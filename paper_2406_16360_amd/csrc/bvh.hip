@@ -492,14 +492,130 @@ __global__ void k_refit_nodes(int nnodes, BvhNode *__restrict__ nodes, const int
     }
 }
 
-// 1 for the binary nodes at even depth (the root at depth 0): the nodes that
-// get a traversal node.  Each thread climbs the parent links of its node.
-__global__ void k_wide_flags(const int32_t *__restrict__ npar, int nnodes, uint8_t *__restrict__ even) {
+// Traversal nodes: a collapse of the binary tree into nodes of up to four
+// children that minimises the summed surface area of the traversal nodes (the
+// expected number of node fetches per ray under the surface-area model).  For
+// a binary node n and j = 1..4 member slots of the traversal node above it,
+//   S(n, 1) = A(n) + D(n, 4)        n heads a traversal node of its own,
+//   S(n, j) = min(S(n, 1), D(n, j)) n may instead be opened, j >= 2,
+//   D(n, k) = min over k1 of S(l, k1) + S(r, k - k1),
+// with S = 0 for leaves and A(n) the surface area of n's box in its parent
+// (the collapse of Ylitie, Karras and Laine, HPG 2017, for four children).
+// The costs are computed bottom-up; the traversal nodes are then chosen from
+// the root down, one level per launch.  A member of a traversal node is a
+// binary node slot, (node << 1) | side, so that a refit takes its box and
+// reference from the refitted slot and keeps the collapse.
+__device__ __forceinline__ bool slot_of(const BvhNode &nd, int side, float &area, int &ref) {
+    const float4 a = side ? nd.n1 : nd.n0;
+    const float zl = side ? nd.n2.z : nd.n2.x, zh = side ? nd.n2.w : nd.n2.y;
+    ref = side ? nd.n3.y : nd.n3.x;
+    if (!(a.x <= a.y) || !(a.z <= a.w) || !(zl <= zh)) return false;   // empty slot
+    const float dx = a.y - a.x, dy = a.w - a.z, dz = zh - zl;
+    area = dx * dy + dy * dz + dz * dx;
+    return true;
+}
+__device__ __forceinline__ float4 cost_of(const float4 *S, int ref) {
+    return ref >= 0 ? S[ref] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+__device__ __forceinline__ float cost_j(float4 v, int j) { return j == 1 ? v.x : j == 2 ? v.y : j == 3 ? v.z : v.w; }
+// D(n, k) from the children's costs a and b, with the best k1
+__device__ __forceinline__ float split_cost(float4 a, float4 b, int k, int &k1) {
+    float best = INFINITY;
+    k1 = 1;
+    for (int q = 1; q < k; ++q) {
+        const float c = cost_j(a, q) + cost_j(b, k - q);
+        if (c < best) { best = c; k1 = q; }
+    }
+    return best;
+}
+
+// S(n, 1..4) of every binary node, bottom-up: a thread starts at every node
+// whose children are both leaves and climbs; a node is finished by the thread
+// that brings its last inner child (arrival counters, as in the refit).
+__global__ void k_wide_cost(int nnodes, const BvhNode *__restrict__ nodes, const int32_t *__restrict__ npar,
+                            float4 *__restrict__ S, int32_t *__restrict__ arrive) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nnodes) return;
-    int d = 0;
-    for (int p = npar[i]; p >= 0 && d < nnodes; p = npar[p >> 1]) ++d;
-    even[i] = (d & 1) == 0;
+    const int4 r0 = nodes[i].n3;
+    if (r0.x >= 0 || r0.y >= 0) return;
+    int node = i;
+    while (true) {
+        const BvhNode nd = nodes[node];
+        const float4 a = cost_of(S, nd.n3.x), b = cost_of(S, nd.n3.y);
+        float area = 0.0f;
+        int ref, k1;
+        const int p = npar[node];
+        if (p >= 0) (void)slot_of(nodes[p >> 1], p & 1, area, ref);
+        const float d2 = split_cost(a, b, 2, k1), d3 = split_cost(a, b, 3, k1), d4 = split_cost(a, b, 4, k1);
+        const float s1 = area + d4;
+        S[node] = make_float4(s1, fminf(s1, d2), fminf(s1, d3), fminf(s1, d4));
+        __threadfence();
+        if (p < 0) break;
+        const int parent = p >> 1;
+        const int4 pr = nodes[parent].n3;
+        const int need = (pr.x >= 0) + (pr.y >= 0);
+        if (atomicAdd(&arrive[parent], 1) + 1 < need) break;
+        __threadfence();
+        node = parent;
+    }
+}
+
+// level of the traversal node each binary node heads (-1: none); the root heads level 0
+__global__ void k_wide_init(int32_t *__restrict__ level, int nnodes) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnodes) level[i] = i == 0 ? 0 : -1;
+}
+
+// The members of every traversal node of level lv: the root's two slots share
+// four members as D(n, 4) chose, and an inner slot with budget j >= 2 is
+// opened when D(n, j) < S(n, 1) (depth first, left before right, so the
+// members keep the tree's order).  Inner members head traversal nodes of the
+// next level.  maxlv receives the deepest level.
+__global__ void k_wide_level(const BvhNode *__restrict__ nodes, const float4 *__restrict__ S, int nnodes, int lv,
+                             int32_t *__restrict__ level, int4 *__restrict__ cuts, int32_t *__restrict__ maxlv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnodes || level[i] != lv) return;
+    // every stacked slot holds a budget >= 1 and the budgets sum to at most 4
+    int st_slot[4], st_bud[4], sp = 0;
+    int slot[4], ref[4];
+    int n = 0;
+    {
+        const BvhNode nd = nodes[i];
+        int k1, rf;
+        float ar;
+        (void)split_cost(cost_of(S, nd.n3.x), cost_of(S, nd.n3.y), 4, k1);
+        const bool hl = slot_of(nd, 0, ar, rf), hr = slot_of(nd, 1, ar, rf);
+        if (hl && hr) {
+            st_slot[sp] = (i << 1) | 1; st_bud[sp++] = 4 - k1;
+            st_slot[sp] = (i << 1) | 0; st_bud[sp++] = k1;
+        } else if (hl || hr) {       // a one-triangle tree: the root has one slot
+            st_slot[sp] = (i << 1) | (hl ? 0 : 1); st_bud[sp++] = 4;
+        }
+    }
+    while (sp > 0) {
+        --sp;
+        const int sl = st_slot[sp], bud = st_bud[sp];
+        float ar;
+        int r;
+        (void)slot_of(nodes[sl >> 1], sl & 1, ar, r);
+        if (r < 0 || bud == 1 || cost_j(S[r], 1) <= cost_j(S[r], bud)) {
+            slot[n] = sl; ref[n] = r; ++n;
+            continue;
+        }
+        const BvhNode cn = nodes[r];
+        int q1;
+        (void)split_cost(cost_of(S, cn.n3.x), cost_of(S, cn.n3.y), bud, q1);
+        st_slot[sp] = (r << 1) | 1; st_bud[sp++] = bud - q1;
+        st_slot[sp] = (r << 1) | 0; st_bud[sp++] = q1;
+    }
+    int4 out = make_int4(-1, -1, -1, -1);
+    int *o = &out.x;
+    for (int c = 0; c < n; ++c) {
+        o[c] = slot[c];
+        if (ref[c] >= 0) level[ref[c]] = lv + 1;
+    }
+    cuts[i] = out;
+    atomicMax(maxlv, lv);
 }
 
 // the smallest k with 253 * 2^k >= extent and 2^k >= one float ulp of
@@ -512,36 +628,27 @@ __device__ int wide_exponent(double extent, double m) {
     return min(k, 127);
 }
 
-// Traversal node of every binary node at even depth: the children of its
-// two children (or a child itself when it is a leaf), boxes quantised
-// outwards against their union in double, one quantum of padding per side.
-__global__ void k_wide_build(const BvhNode *__restrict__ nodes, int nnodes, const uint8_t *__restrict__ even,
-                             WideNode *__restrict__ wn) {
+// Traversal node of every binary node that heads one: the boxes of its
+// members, quantised outwards against their union in double, one quantum of
+// padding per side.
+__global__ void k_wide_build(const BvhNode *__restrict__ nodes, int nnodes, const int32_t *__restrict__ level,
+                             const int4 *__restrict__ cuts, WideNode *__restrict__ wn) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nnodes || !even[i]) return;
+    if (i >= nnodes || level[i] < 0) return;
     float lo[4][3], hi[4][3];
     int ref[4];
     int nc = 0;
-    auto take = [&](const BvhNode &nd, int side) {
+    const int4 cut = cuts[i];
+    const int cs[4] = {cut.x, cut.y, cut.z, cut.w};
+    for (int c = 0; c < 4; ++c) {
+        if (cs[c] < 0) continue;
+        const BvhNode nd = nodes[cs[c] >> 1];
+        const int side = cs[c] & 1;
         const float4 a = side ? nd.n1 : nd.n0;
-        const float zl = side ? nd.n2.z : nd.n2.x, zh = side ? nd.n2.w : nd.n2.y;
-        const int r = side ? nd.n3.y : nd.n3.x;
-        if (!(a.x <= a.y) || !(a.z <= a.w) || !(zl <= zh)) return false;   // empty slot
-        lo[nc][0] = a.x; hi[nc][0] = a.y; lo[nc][1] = a.z; hi[nc][1] = a.w; lo[nc][2] = zl; hi[nc][2] = zh;
-        ref[nc] = r;
+        lo[nc][0] = a.x; hi[nc][0] = a.y; lo[nc][1] = a.z; hi[nc][1] = a.w;
+        lo[nc][2] = side ? nd.n2.z : nd.n2.x; hi[nc][2] = side ? nd.n2.w : nd.n2.y;
+        ref[nc] = side ? nd.n3.y : nd.n3.x;
         ++nc;
-        return true;
-    };
-    const BvhNode nd = nodes[i];
-    for (int side = 0; side < 2; ++side) {
-        const int r = side ? nd.n3.y : nd.n3.x;
-        const float4 a = side ? nd.n1 : nd.n0;
-        const float zl = side ? nd.n2.z : nd.n2.x, zh = side ? nd.n2.w : nd.n2.y;
-        if (!(a.x <= a.y) || !(a.z <= a.w) || !(zl <= zh)) continue;       // empty slot
-        if (r < 0) { take(nd, side); continue; }
-        const BvhNode c = nodes[r];
-        take(c, 0);
-        take(c, 1);
     }
     WideNode w;
     uint32_t meta = (uint32_t)nc << 24;
@@ -726,12 +833,6 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
         TRY(hip_check(hipMemcpyAsync(&h_depth, depth.p, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy"));
         TRY(hip_check(hipStreamSynchronize(s), "sync"));
         b->depth = h_depth;
-        // a traversal node pushes at most 3 children, and a root-to-leaf path
-        // meets at most depth / 2 + 1 traversal nodes
-        if (3 * (h_depth / 2 + 1) + 2 > kStackSize) {
-            st = fail(MRS_EOVERFLOW, "mrs_build_bvh: tree depth %d exceeds the traversal stack (%d)", h_depth, kStackSize);
-            goto done;
-        }
     }
     // state for mrs_bvh_refit
     TRY(b->npar.alloc(sizeof(int32_t) * b->nnodes));
@@ -742,12 +843,33 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
     k_node_parents<<<blocks(b->nnodes), 256, 0, s>>>((BvhNode *)b->nodes.p, b->nnodes, (int32_t *)b->npar.p);
     // traversal nodes
     TRY(b->wnodes.alloc(sizeof(WideNode) * b->nnodes));
-    TRY(b->weven.alloc(b->nnodes));
-    k_wide_flags<<<blocks(b->nnodes), 256, 0, s>>>((const int32_t *)b->npar.p, b->nnodes, (uint8_t *)b->weven.p);
-    k_wide_build<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, b->nnodes,
-                                                   (const uint8_t *)b->weven.p, (WideNode *)b->wnodes.p);
+    TRY(b->wlevel.alloc(sizeof(int32_t) * b->nnodes));
+    TRY(b->wcut.alloc(sizeof(int4) * b->nnodes));
+    // the collapse costs live in nlo until the first refit needs it
+    k_fill_i32<<<blocks(b->nnodes), 256, 0, s>>>((int32_t *)b->arrive.p, b->nnodes, 0);
+    k_wide_cost<<<blocks(b->nnodes), 256, 0, s>>>(b->nnodes, (const BvhNode *)b->nodes.p, (const int32_t *)b->npar.p,
+                                                  (float4 *)b->nlo.p, (int32_t *)b->arrive.p);
+    k_wide_init<<<blocks(b->nnodes), 256, 0, s>>>((int32_t *)b->wlevel.p, b->nnodes);
+    k_fill_i32<<<1, 1, 0, s>>>((int32_t *)bad.p, 1, 0);      // receives the deepest traversal level
+    for (int lv = 0; lv <= b->depth; ++lv)     // a level descends at least one binary level
+        k_wide_level<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, (const float4 *)b->nlo.p,
+                                                       b->nnodes, lv, (int32_t *)b->wlevel.p, (int4 *)b->wcut.p,
+                                                       (int32_t *)bad.p);
+    k_wide_build<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, b->nnodes, (const int32_t *)b->wlevel.p,
+                                                   (const int4 *)b->wcut.p, (WideNode *)b->wnodes.p);
     TRY(hip_check(hipGetLastError(), "bvh parents and traversal nodes"));
-    TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    {
+        int32_t h_lv = 0;
+        TRY(hip_check(hipMemcpyAsync(&h_lv, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy"));
+        TRY(hip_check(hipStreamSynchronize(s), "sync"));
+        // a traversal node stacks at most 3 children, and a root-to-leaf path
+        // meets at most h_lv + 1 traversal nodes
+        if (3 * (h_lv + 1) + 2 > kStackSize) {
+            st = fail(MRS_EOVERFLOW, "mrs_build_bvh: %d traversal levels exceed the traversal stack (%d entries)",
+                      h_lv + 1, kStackSize);
+            goto done;
+        }
+    }
 #undef TRY
 done:
     if (st != MRS_OK) { delete b; return st; }
@@ -785,8 +907,8 @@ extern "C" mrs_status mrs_bvh_refit(mrs_bvh *b, const float *d_pos, int32_t nv, 
     k_refit_nodes<<<blocks(b->nnodes), 256, 0, s>>>(b->nnodes, (BvhNode *)b->nodes.p, (const int32_t *)b->npar.p,
                                                     (const TriRec *)b->tris.p, (float4 *)b->nlo.p, (float4 *)b->nhi.p,
                                                     (int32_t *)b->arrive.p);
-    k_wide_build<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, b->nnodes,
-                                                   (const uint8_t *)b->weven.p, (WideNode *)b->wnodes.p);
+    k_wide_build<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, b->nnodes, (const int32_t *)b->wlevel.p,
+                                                   (const int4 *)b->wcut.p, (WideNode *)b->wnodes.p);
     return hip_check(hipGetLastError(), "mrs_bvh_refit launch");
 }
 

@@ -438,18 +438,20 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
 // ref >= 0: internal node; ref < 0: leaf ~(first << 3 | (count - 1)) over the
 // leaf-ordered triangle array.
 struct BvhNode { float4 n0, n1, n2; int4 n3; };
-// Traversal node: the up to four children of a binary node two levels below
-// it (a child that is a leaf stands for itself), their boxes quantised to 8
-// bits per bound against the union box, so one 64-byte fetch tests four
-// boxes where a binary node tests two.  On axis a, child c spans
+// Traversal node: up to four descendants of a binary node that together
+// cover its subtree (chosen by the build's surface-area collapse; a leaf
+// stands for itself), their boxes quantised to 8 bits per bound against the
+// union box, so one 64-byte fetch tests four boxes where a binary node tests
+// two.  On axis a, child c spans
 //   [o_a + qlo_a[c] 2^(e_a - 127), o_a + qhi_a[c] 2^(e_a - 127)],
 // which holds the child's float box with a quantum to spare on both sides.
 //   a = (o.x, o.y, o.z, bits e_x | e_y << 8 | e_z << 16 | count << 24)
 //   q = (qlo_x, qhi_x, qlo_y, qhi_y), byte c of a word for child c
 //   r = (qlo_z, qhi_z, ref_0, ref_1), s = (ref_2, ref_3, 0, 0)
-// Child c < count has ref_c: >= 0 the binary index of a node two levels
-// down, whose traversal node is stored at that same index; < 0 a leaf, as in
-// BvhNode.  Only binary nodes at even depth have a traversal node.
+// Child c < count has ref_c: >= 0 the binary index of a descendant node,
+// whose traversal node is stored at that same index; < 0 a leaf, as in
+// BvhNode.  Only the binary nodes that the collapse keeps have a traversal
+// node.
 struct WideNode { float4 a; uint4 q; uint4 r; uint4 s; };
 // Triangle in leaf order: v0 (w = original face id), v1, v2.
 struct TriRec { float4 a, b, c; };

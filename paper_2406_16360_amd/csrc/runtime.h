@@ -65,8 +65,9 @@ struct mrs_bvh {
     // root), unpadded node boxes and arrival counters for the bottom-up pass
     mrs::DevBuf npar, nlo, nhi, arrive;
     // traversal nodes (WideNode[nnodes], at the binary index of the node
-    // they stand for) and the flags of the binary nodes at even depth
-    mrs::DevBuf wnodes, weven;
+    // they stand for), the traversal level each binary node heads (-1: none)
+    // and each traversal node's members as binary node slots (int4)
+    mrs::DevBuf wnodes, wlevel, wcut;
 };
 
 struct mrs_tape {

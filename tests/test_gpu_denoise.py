@@ -49,6 +49,7 @@ def _buffers(seed, views):
 VIEW_SETS = {
     "uneven": [V(37, 29), V(64, 48), V(20, 33)],
     "tiny": [V(1, 1), V(3, 2), V(2, 7), V(16, 1)],     # views smaller than a tile or an apron
+    "full": [V(800, 800), V(333, 517)],                # the rendered views' size, and a ragged one
 }
 
 
