@@ -270,16 +270,18 @@ __device__ __forceinline__ BrdfGrad brdf_grad(const Lobe &L, const Mat &m, V3 wi
 // environment map (equirectangular, +y up): theta = acos(d_y),
 // phi = atan2(d_x, -d_z), u = phi / 2pi + 1/2, v = theta / pi; nearest texel
 // ----------------------------------------------------------------------------
-// The normalised CDFs are stored as intervals, entry i = (cdf[i], cdf[i + 1]),
-// so one aligned 16-byte load gives both ends of a bin.
+// The normalised marginal CDF is stored as intervals, entry i = (cdf[i],
+// cdf[i + 1]), so one aligned 16-byte load gives both ends of a bin; the
+// conditional CDFs sit in the texel records, one value per texel.
 struct EnvTables {
     const double2 *mpair;   // [H] marginal CDF over rows, as intervals
-    // [H][W] 32-byte texel records: the interval of the row's conditional CDF
-    // (cdf[j], cdf[j + 1]) as a double2, then (L_r, L_g, L_b clamped >= 0,
-    // guide g as int bits), g the first column whose bin ends above j / W.
-    // An env candidate's guide, interval and radiance loads then mostly touch
-    // one cache line; the pdf is formed from the two CDF intervals.
-    const float4 *rec;
+    // [H][W] 24-byte texel records (layout at env_rec): the row's conditional
+    // CDF at the texel's column, the radiance, and the guide g of the cell
+    // (the first column whose bin ends above j / W).  A candidate's guide,
+    // interval and radiance loads then mostly touch one cache line, and the
+    // table is three quarters the size of one that stores both interval ends;
+    // the pdf is formed from the two CDF intervals.
+    const char *rec;
     const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
@@ -351,36 +353,48 @@ __device__ __forceinline__ float env_pdf_dir(bool ok, V3 d, float puv) {
 // buffer_load_dwordx4: from a plain pointer it splits a 16-byte record into
 // narrower loads when its words are used on different paths, and every extra
 // scattered load instruction costs the memory pipeline one more cycle per
-// distinct cache line.  An offset at or past the end reads zeros.
+// distinct cache line.  Offsets need only be 4-byte aligned.  An offset at or
+// past the end reads zeros.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ float4 buffer_float4(__amdgpu_buffer_rsrc_t r, uint32_t index) {
-    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, index * 16u, 0, 0);
-    return make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z), __uint_as_float(q.w));
-}
-__device__ __forceinline__ double2 buffer_double2(__amdgpu_buffer_rsrc_t r, uint32_t index) {
-    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, index * 16u, 0, 0);
-    return make_double2(__hiloint2double((int)q.y, (int)q.x), __hiloint2double((int)q.w, (int)q.z));
-}
 
-// radiance entry of texel t (w: the guide bits)
-__device__ __forceinline__ float4 env_lp(const EnvTables &e, int t) { return e.rec[2 * (size_t)t + 1]; }
+// 24-byte texel records: texel t at byte 24 t holds cdf[j] (double, the
+// row's conditional CDF at its column j), L_r, L_g, L_b (clamped >= 0) and
+// the guide g of cell j (int bits); the upper end cdf[j + 1] is the next
+// record's first word, and 1 after a row's last texel (the build sets the
+// row's last CDF value to exactly 1).  16 bytes of padding follow the last
+// record, so that the second load of the last record stays in the buffer.
+constexpr uint32_t kEnvRecBytes = 24u;
+__device__ __forceinline__ float4 env_lp(const EnvTables &e, int t) {
+    return *(const float4 *)((const char *)e.rec + (size_t)kEnvRecBytes * t + 8);
+}
 
 // the env's texel records as a buffer resource (W H < 2^27 texels, so the
 // byte offsets fit in 32 bits)
 struct EnvBufs {
     __amdgpu_buffer_rsrc_t rec;
+    int W;
 };
 __device__ __forceinline__ EnvBufs env_bufs(const EnvTables &e) {
-    const uint32_t bytes = (uint32_t)e.W * (uint32_t)e.H * 32u;
-    return EnvBufs{buffer_rsrc(e.rec, bytes)};
+    const uint32_t bytes = (uint32_t)e.W * (uint32_t)e.H * kEnvRecBytes + 16u;
+    return EnvBufs{buffer_rsrc(e.rec, bytes), e.W};
 }
-__device__ __forceinline__ float4 env_lp(const EnvBufs &eb, uint32_t t) { return buffer_float4(eb.rec, 2u * t + 1u); }
-__device__ __forceinline__ double2 env_iv(const EnvBufs &eb, uint32_t t) { return buffer_double2(eb.rec, 2u * t); }
+__device__ __forceinline__ float4 env_lp(const EnvBufs &eb, uint32_t t) {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(eb.rec, kEnvRecBytes * t + 8u, 0, 0);
+    return make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z), __uint_as_float(q.w));
+}
+// the whole record of texel t (column j of its row): its CDF interval and radiance
+__device__ __forceinline__ void env_rec(const EnvBufs &eb, uint32_t t, int j, double2 &iv, float4 &lp) {
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(eb.rec, kEnvRecBytes * t, 0, 0);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(eb.rec, kEnvRecBytes * t + 16u, 0, 0);
+    iv = make_double2(__hiloint2double((int)a.y, (int)a.x),
+                      j == eb.W - 1 ? 1.0 : __hiloint2double((int)b.w, (int)b.z));
+    lp = make_float4(__uint_as_float(a.z), __uint_as_float(a.w), __uint_as_float(b.x), __uint_as_float(b.y));
+}
 __device__ __forceinline__ int env_guide(const EnvBufs &eb, uint32_t t) {
-    return __builtin_amdgcn_raw_buffer_load_b32(eb.rec, (2u * t + 1u) * 16u + 12u, 0, 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(eb.rec, kEnvRecBytes * t + 20u, 0, 0);
 }
 
 // smallest i with cdf[i + 1] > u (cdf[0] = 0 <= u < 1 = cdf[n]): the unique i
@@ -394,13 +408,14 @@ __device__ __forceinline__ int interval_walk(const double2 *iv, int start, int n
     while (i < n - 1 && !(p.y > u)) { ++i; p = iv[i]; }
     return i;
 }
-// the same walk over the intervals of texel records base .. base + n - 1
-__device__ __forceinline__ int interval_walk(__amdgpu_buffer_rsrc_t rec, uint32_t base, int start, int n, double u,
-                                             double2 &p) {
+// the same walk over the texel records of a row (base = its first texel),
+// which also gives the radiance of the texel found
+__device__ __forceinline__ int interval_walk(const EnvBufs &eb, uint32_t base, int start, int n, double u,
+                                             double2 &p, float4 &lp) {
     int i = min(max(start, 0), n - 1);
-    p = buffer_double2(rec, 2u * (base + i));
-    while (i > 0 && p.x > u) { --i; p = buffer_double2(rec, 2u * (base + i)); }
-    while (i < n - 1 && !(p.y > u)) { ++i; p = buffer_double2(rec, 2u * (base + i)); }
+    env_rec(eb, base + i, i, p, lp);
+    while (i > 0 && p.x > u) { --i; env_rec(eb, base + i, i, p, lp); }
+    while (i < n - 1 && !(p.y > u)) { ++i; env_rec(eb, base + i, i, p, lp); }
     return i;
 }
 
@@ -415,7 +430,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     // the CDF differences are formed in double, the in-texel fractions in float
     float fv = __fdividef((float)(u0 - pm.x), (float)(pm.y - pm.x));
     const uint32_t row = (uint32_t)i * (uint32_t)e.W;
-    int j = interval_walk(eb.rec, row, env_guide(eb, row + (uint32_t)min((int)(u1 * e.W), e.W - 1)), e.W, u1, pc);
+    int j = interval_walk(eb, row, env_guide(eb, row + (uint32_t)min((int)(u1 * e.W), e.W - 1)), e.W, u1, pc, lp);
     float fu = __fdividef((float)(u1 - pc.x), (float)(pc.y - pc.x));
     float v = ((float)i + fv) / (float)e.H, u = ((float)j + fu) / (float)e.W;
     float st, ct, sp, cp;
@@ -424,7 +439,6 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     if (!(st > 0.0f)) return false;
     dir = V3{st * sp, ct, -st * cp};
     texel = i * e.W + j;
-    lp = env_lp(eb, (uint32_t)texel);
     pdf = env_pdf_uv(pm, pc, e.W, e.H) / st;
     return pdf > 0.0f;
 }

@@ -376,7 +376,7 @@ mrs_status reserve_env(const mrs_scene *sc, Res &r) {
     TRY(r.marg.reserve(sizeof(double) * (H + 1)));
     TRY(r.rowsum.reserve(sizeof(double) * H));
     TRY(r.info.reserve(sizeof(double) * 2));
-    TRY(r.erec.reserve(2 * sizeof(float4) * nt));
+    TRY(r.erec.reserve(24 * nt + 16));
     TRY(r.gmarg.reserve(sizeof(int32_t) * H));
     TRY(r.mpair.reserve(sizeof(double2) * H));
     TRY(r.rcos.reserve(sizeof(double) * (H + 1)));
@@ -424,11 +424,11 @@ mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
         k_env_rows<<<H, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.cond.as<double>(), r.rowsum.as<double>());
         k_env_marg<<<1, 64, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
         k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.info.as<double>(), r.marg.as<double>(),
-                                            r.cond.as<double>(), r.erec.as<float4>(), r.gmarg.as<int32_t>(),
+                                            r.cond.as<double>(), r.erec.as<char>(), r.gmarg.as<int32_t>(),
                                             r.mpair.as<double2>(), r.rcos.as<double>(), r.csphi.as<double2>());
     }
     EnvTables &e = job.sd.env;
-    e.mpair = r.mpair.as<double2>(); e.rec = r.erec.as<float4>();
+    e.mpair = r.mpair.as<double2>(); e.rec = r.erec.as<char>();
     e.gmarg = r.gmarg.as<int32_t>();
     e.raw = sc->env; e.total = r.info.as<double>();
     e.rcos = r.rcos.as<double>(); e.csphi = r.csphi.as<double2>();

@@ -378,19 +378,10 @@ __global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__r
 // intervals and the guide tables of both CDFs
 __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
                              const double *__restrict__ info, const double *__restrict__ marg,
-                             const double *__restrict__ cond, float4 *__restrict__ rec, int32_t *__restrict__ gmarg,
+                             const double *__restrict__ cond, char *__restrict__ rec, int32_t *__restrict__ gmarg,
                              double2 *__restrict__ mpair, double *__restrict__ rcos, double2 *__restrict__ csphi) {
     int i = blockIdx.x;
-    double total = info[0];
-    double2 *riv = (double2 *)rec;   // record t: interval at riv[2 t], radiance + pdf at rec[2 t + 1]
-    // the CDFs as intervals (cdf[t], cdf[t + 1])
-    if (i < H) {
-        const double *cr = cond + (size_t)i * (W + 1);
-        for (int j = threadIdx.x; j < W; j += blockDim.x) riv[2 * ((size_t)i * W + j)] = make_double2(cr[j], cr[j + 1]);
-    } else {
-        for (int t = threadIdx.x; t < H; t += blockDim.x) mpair[t] = make_double2(marg[t], marg[t + 1]);
-    }
-    (void)total; (void)wts;
+    (void)info; (void)wts;
     if (i < H) {
         const double *cr = cond + (size_t)i * (W + 1);
         for (int j = threadIdx.x; j < W; j += blockDim.x) {
@@ -398,10 +389,15 @@ __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const 
             double t = (double)j / W;
             int lo = 0, hi = W - 1;   // smallest c with cr[c + 1] > t: the guide of cell j
             while (lo < hi) { int mid = (lo + hi) >> 1; if (cr[mid + 1] > t) hi = mid; else lo = mid + 1; }
-            rec[2 * ((size_t)i * W + j) + 1] = make_float4(fmaxf(L[0], 0.0f), fmaxf(L[1], 0.0f), fmaxf(L[2], 0.0f),
-                                                           __int_as_float(lo));
+            char *r = rec + (size_t)kEnvRecBytes * ((size_t)i * W + j);
+            *(double *)r = cr[j];
+            float *f = (float *)(r + 8);
+            f[0] = fmaxf(L[0], 0.0f); f[1] = fmaxf(L[1], 0.0f); f[2] = fmaxf(L[2], 0.0f);
+            *(int32_t *)(r + 20) = lo;
         }
+        if (i == H - 1 && threadIdx.x < 4) ((int32_t *)(rec + (size_t)kEnvRecBytes * W * H))[threadIdx.x] = 0;
     } else {
+        for (int t = threadIdx.x; t < H; t += blockDim.x) mpair[t] = make_double2(marg[t], marg[t + 1]);
         for (int t0 = threadIdx.x; t0 < H; t0 += blockDim.x) {
             double t = (double)t0 / H;
             int lo = 0, hi = H - 1;
@@ -525,9 +521,10 @@ __device__ __forceinline__ void ris_candidate(const EnvTables &env, const EnvBuf
         dir = to_world(F, wl);
         tex = env_texel_of(env, dir);
         if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
-        lp = env_lp(eb, (uint32_t)tex);
-        const double2 pc = env_iv(eb, (uint32_t)tex);
-        qe = env_pdf_dir(env_ok, dir, env_pdf_uv(marg.pair[tex / env.W], pc, env.W, env.H));
+        double2 pc;
+        const int trow = tex / env.W;
+        env_rec(eb, (uint32_t)tex, tex - trow * env.W, pc, lp);
+        qe = env_pdf_dir(env_ok, dir, env_pdf_uv(marg.pair[trow], pc, env.W, env.H));
     }
     if (!(wl.z > 0.0f)) return;
     V3 f = brdf_eval_pdf(L, wl, qb);
