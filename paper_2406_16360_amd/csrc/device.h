@@ -276,12 +276,15 @@ __device__ __forceinline__ BrdfGrad brdf_grad(const Lobe &L, const Mat &m, V3 wi
 struct EnvTables {
     const double2 *mpair;   // [H] marginal CDF over rows, as intervals
     // [H][W] 24-byte texel records (layout at env_rec): the row's conditional
-    // CDF at the texel's column, the radiance, and the guide g of the cell
-    // (the first column whose bin ends above j / W).  A candidate's guide,
-    // interval and radiance loads then mostly touch one cache line, and the
-    // table is three quarters the size of one that stores both interval ends;
-    // the pdf is formed from the two CDF intervals.
+    // CDF at the texel's column, the radiance and the texel's sampling
+    // density.  A BRDF candidate reads radiance and density with one 16-byte
+    // load; an env candidate's walk reads interval, radiance and density
+    // together.  The table is three quarters the size of one that stores both
+    // interval ends.
     const char *rec;
+    // [H][W] guides of the conditional CDFs: g[i][c] is the first column of
+    // row i whose bin ends above c / W
+    const int32_t *gcond;
     const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
@@ -362,10 +365,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 
 // 24-byte texel records: texel t at byte 24 t holds cdf[j] (double, the
 // row's conditional CDF at its column j), L_r, L_g, L_b (clamped >= 0) and
-// the guide g of cell j (int bits); the upper end cdf[j + 1] is the next
-// record's first word, and 1 after a row's last texel (the build sets the
-// row's last CDF value to exactly 1).  16 bytes of padding follow the last
-// record, so that the second load of the last record stays in the buffer.
+// env_pdf_uv of the texel (float, from its row's marginal interval and its
+// conditional interval); the upper end cdf[j + 1] is the next record's first
+// word, and 1 after a row's last texel (the build sets the row's last CDF
+// value to exactly 1).  16 bytes of padding follow the last record, so that
+// the second load of the last record stays in the buffer.  env_lp returns
+// (L_r, L_g, L_b, pdf_uv).
 constexpr uint32_t kEnvRecBytes = 24u;
 __device__ __forceinline__ float4 env_lp(const EnvTables &e, int t) {
     return *(const float4 *)((const char *)e.rec + (size_t)kEnvRecBytes * t + 8);
@@ -385,16 +390,14 @@ __device__ __forceinline__ float4 env_lp(const EnvBufs &eb, uint32_t t) {
     const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(eb.rec, kEnvRecBytes * t + 8u, 0, 0);
     return make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z), __uint_as_float(q.w));
 }
-// the whole record of texel t (column j of its row): its CDF interval and radiance
+// the whole record of texel t (column j of its row): its CDF interval, and
+// its radiance and pdf_uv as env_lp returns them
 __device__ __forceinline__ void env_rec(const EnvBufs &eb, uint32_t t, int j, double2 &iv, float4 &lp) {
     const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(eb.rec, kEnvRecBytes * t, 0, 0);
     const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(eb.rec, kEnvRecBytes * t + 16u, 0, 0);
     iv = make_double2(__hiloint2double((int)a.y, (int)a.x),
                       j == eb.W - 1 ? 1.0 : __hiloint2double((int)b.w, (int)b.z));
     lp = make_float4(__uint_as_float(a.z), __uint_as_float(a.w), __uint_as_float(b.x), __uint_as_float(b.y));
-}
-__device__ __forceinline__ int env_guide(const EnvBufs &eb, uint32_t t) {
-    return __builtin_amdgcn_raw_buffer_load_b32(eb.rec, kEnvRecBytes * t + 20u, 0, 0);
 }
 
 // smallest i with cdf[i + 1] > u (cdf[0] = 0 <= u < 1 = cdf[n]): the unique i
@@ -430,7 +433,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     // the CDF differences are formed in double, the in-texel fractions in float
     float fv = __fdividef((float)(u0 - pm.x), (float)(pm.y - pm.x));
     const uint32_t row = (uint32_t)i * (uint32_t)e.W;
-    int j = interval_walk(eb, row, env_guide(eb, row + (uint32_t)min((int)(u1 * e.W), e.W - 1)), e.W, u1, pc, lp);
+    int j = interval_walk(eb, row, e.gcond[row + (uint32_t)min((int)(u1 * e.W), e.W - 1)], e.W, u1, pc, lp);
     float fu = __fdividef((float)(u1 - pc.x), (float)(pc.y - pc.x));
     float v = ((float)i + fv) / (float)e.H, u = ((float)j + fu) / (float)e.W;
     float st, ct, sp, cp;
@@ -439,7 +442,7 @@ __device__ __forceinline__ bool env_sample(const EnvTables &e, const EnvBufs &eb
     if (!(st > 0.0f)) return false;
     dir = V3{st * sp, ct, -st * cp};
     texel = i * e.W + j;
-    pdf = env_pdf_uv(pm, pc, e.W, e.H) / st;
+    pdf = lp.w / st;
     return pdf > 0.0f;
 }
 

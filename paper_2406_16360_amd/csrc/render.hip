@@ -107,7 +107,7 @@ struct Chunk { uint64_t c0, c1, pix0, pix1; };
 // Device buffers one launch sequence works in: the library's shared
 // workspace for eager calls, or a plan's own set.
 struct Res {
-    DevBuf wts, cond, marg, rowsum, info, erec, gmarg, mpair, rcos, csphi;   // environment tables
+    DevBuf wts, cond, marg, rowsum, info, erec, gcond, gmarg, mpair, rcos, csphi;   // environment tables
     DevBuf views;                                              // ViewDev table
     DevBuf qa_o, qa_d, qa_t, qb_o, qb_d, qb_t, hits, so, sd, sc; // path pool queues
     DevBuf ctr, sched, out;                                    // iteration counters, scheduler, sample radiance
@@ -119,7 +119,7 @@ struct Res {
     DevBuf tpack;                                              // texture mode: interleaved texel records
     DevBuf dkey, dkey2, dval, dval2, dsort;                    // deterministic adjoint: pairs, sorted pairs, sort scratch
     void release_all() {
-        for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &erec, &gmarg, &mpair, &rcos, &csphi, &views, &qa_o, &qa_d, &qa_t, &qb_o,
+        for (DevBuf *b : {&wts, &cond, &marg, &rowsum, &info, &erec, &gcond, &gmarg, &mpair, &rcos, &csphi, &views, &qa_o, &qa_d, &qa_t, &qb_o,
                           &qb_d, &qb_t, &hits, &so, &sd, &sc, &ctr, &sched, &out, &ct_hit, &ct_y, &ct_rr, &ct_fm, &grec, &fm, &fvtx, &gvtx,
                           &rprim, &rfmat, &rr0, &rr1, &fkey, &fkey2, &fval, &fval2, &fsort, &tpack, &dkey, &dkey2, &dval, &dval2,
                           &dsort})
@@ -378,6 +378,7 @@ mrs_status reserve_env(const mrs_scene *sc, Res &r) {
     TRY(r.info.reserve(sizeof(double) * 2));
     TRY(r.erec.reserve(24 * nt + 16));
     TRY(r.gmarg.reserve(sizeof(int32_t) * H));
+    TRY(r.gcond.reserve(sizeof(int32_t) * nt));
     TRY(r.mpair.reserve(sizeof(double2) * H));
     TRY(r.rcos.reserve(sizeof(double) * (H + 1)));
     TRY(r.csphi.reserve(sizeof(double2) * (W + 1)));
@@ -424,12 +425,13 @@ mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
         k_env_rows<<<H, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.cond.as<double>(), r.rowsum.as<double>());
         k_env_marg<<<1, 64, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
         k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.info.as<double>(), r.marg.as<double>(),
-                                            r.cond.as<double>(), r.erec.as<char>(), r.gmarg.as<int32_t>(),
+                                            r.cond.as<double>(), r.erec.as<char>(), r.gcond.as<int32_t>(), r.gmarg.as<int32_t>(),
                                             r.mpair.as<double2>(), r.rcos.as<double>(), r.csphi.as<double2>());
     }
     EnvTables &e = job.sd.env;
     e.mpair = r.mpair.as<double2>(); e.rec = r.erec.as<char>();
     e.gmarg = r.gmarg.as<int32_t>();
+    e.gcond = r.gcond.as<int32_t>();
     e.raw = sc->env; e.total = r.info.as<double>();
     e.rcos = r.rcos.as<double>(); e.csphi = r.csphi.as<double2>();
     e.W = W; e.H = H;

@@ -374,11 +374,12 @@ __global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__r
     info[0] = acc;
 }
 
-// texel records (conditional CDF interval, radiance + pdf), the marginal
+// texel records (conditional CDF value, radiance, pdf_uv), the marginal
 // intervals and the guide tables of both CDFs
 __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
                              const double *__restrict__ info, const double *__restrict__ marg,
-                             const double *__restrict__ cond, char *__restrict__ rec, int32_t *__restrict__ gmarg,
+                             const double *__restrict__ cond, char *__restrict__ rec, int32_t *__restrict__ gcond,
+                             int32_t *__restrict__ gmarg,
                              double2 *__restrict__ mpair, double *__restrict__ rcos, double2 *__restrict__ csphi) {
     int i = blockIdx.x;
     (void)info; (void)wts;
@@ -393,7 +394,8 @@ __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const 
             *(double *)r = cr[j];
             float *f = (float *)(r + 8);
             f[0] = fmaxf(L[0], 0.0f); f[1] = fmaxf(L[1], 0.0f); f[2] = fmaxf(L[2], 0.0f);
-            *(int32_t *)(r + 20) = lo;
+            *(float *)(r + 20) = env_pdf_uv(make_double2(marg[i], marg[i + 1]), make_double2(cr[j], cr[j + 1]), W, H);
+            gcond[(size_t)i * W + j] = lo;
         }
         if (i == H - 1 && threadIdx.x < 4) ((int32_t *)(rec + (size_t)kEnvRecBytes * W * H))[threadIdx.x] = 0;
     } else {
@@ -521,10 +523,8 @@ __device__ __forceinline__ void ris_candidate(const EnvTables &env, const EnvBuf
         dir = to_world(F, wl);
         tex = env_texel_of(env, dir);
         if (want_hash) o.hev ^= ev_cand((uint32_t)k, (uint32_t)s, (uint32_t)lb, (uint32_t)tex);
-        double2 pc;
-        const int trow = tex / env.W;
-        env_rec(eb, (uint32_t)tex, tex - trow * env.W, pc, lp);
-        qe = env_pdf_dir(env_ok, dir, env_pdf_uv(marg.pair[trow], pc, env.W, env.H));
+        lp = env_lp(eb, (uint32_t)tex);
+        qe = env_pdf_dir(env_ok, dir, lp.w);
     }
     if (!(wl.z > 0.0f)) return;
     V3 f = brdf_eval_pdf(L, wl, qb);
