@@ -124,7 +124,7 @@ typedef struct {
     const float   *rough;                 /* [th][tw] */
     const float   *metal;                 /* [th][tw] */
     int32_t        tw, th;
-    const float   *env;                   /* [eh][ew][3], fewer than 2^27 texels */
+    const float   *env;                   /* [eh][ew][3], fewer than 2^27 texels, ew <= 65536 */
     int32_t        ew, eh;
     mrs_field      field;                 /* the material source for MRS_MAT_FIELD */
 } mrs_scene;
@@ -261,7 +261,7 @@ mrs_status mrs_trace(const mrs_bvh *bvh, const float *d_orig, const float *d_dir
  * mrs_render_backward (else *tape_out = NULL).  Errors: MRS_EINVAL (bad
  * sizes, options, or a BVH built for another triangle count), MRS_EOVERFLOW
  * (more than 2^32 - 1 samples, parameter arrays beyond their limits, an env
- * of 2^27 texels or more), MRS_ENOMEM, MRS_EHIP. */
+ * of 2^27 texels or more or wider than 65536 texels), MRS_ENOMEM, MRS_EHIP. */
 mrs_status mrs_render(const mrs_scene *scene, const mrs_view *views, int32_t n_views,
                       const mrs_options *opt, float *d_image, mrs_tape **tape_out, void *stream);
 

@@ -283,8 +283,9 @@ struct EnvTables {
     // interval ends.
     const char *rec;
     // [H][W] guides of the conditional CDFs: g[i][c] is the first column of
-    // row i whose bin ends above c / W
-    const int32_t *gcond;
+    // row i whose bin ends above c / W (16 bits: W <= 65536).  Env candidates
+    // read them at uniformly spread cells, so their size counts.
+    const uint16_t *gcond;
     const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
     const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;

@@ -234,9 +234,11 @@ mrs_status validate(const mrs_scene *sc, const mrs_view *views, int32_t n_views,
         return fail(MRS_EINVAL, "unknown mat_mode %d", sc->mat_mode);
     }
     if (!sc->env || sc->ew <= 0 || sc->eh <= 0) return fail(MRS_EINVAL, "bad environment map %dx%d", sc->ew, sc->eh);
-    // the env's 32-byte texel records are addressed with 32-bit byte offsets
+    // the env's 24-byte texel records are addressed with 32-bit byte offsets,
+    // and its column guides are 16-bit
     if ((int64_t)sc->ew * sc->eh >= (1ll << 27))
         return fail(MRS_EOVERFLOW, "environment map %dx%d has 2^27 texels or more", sc->ew, sc->eh);
+    if (sc->ew > 65536) return fail(MRS_EOVERFLOW, "environment map %dx%d is wider than 65536 texels", sc->ew, sc->eh);
     // gradient elements are addressed with 29-bit indices
     if (3ll * sc->ew * sc->eh >= (1ll << 29) || 5ll * sc->nv >= (1ll << 29) ||
         (sc->mat_mode == MRS_MAT_TEXTURE && 3ll * sc->tw * sc->th >= (1ll << 29)))
@@ -378,7 +380,7 @@ mrs_status reserve_env(const mrs_scene *sc, Res &r) {
     TRY(r.info.reserve(sizeof(double) * 2));
     TRY(r.erec.reserve(24 * nt + 16));
     TRY(r.gmarg.reserve(sizeof(int32_t) * H));
-    TRY(r.gcond.reserve(sizeof(int32_t) * nt));
+    TRY(r.gcond.reserve(sizeof(uint16_t) * nt));
     TRY(r.mpair.reserve(sizeof(double2) * H));
     TRY(r.rcos.reserve(sizeof(double) * (H + 1)));
     TRY(r.csphi.reserve(sizeof(double2) * (W + 1)));
@@ -425,13 +427,13 @@ mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
         k_env_rows<<<H, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.cond.as<double>(), r.rowsum.as<double>());
         k_env_marg<<<1, 64, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
         k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.info.as<double>(), r.marg.as<double>(),
-                                            r.cond.as<double>(), r.erec.as<char>(), r.gcond.as<int32_t>(), r.gmarg.as<int32_t>(),
+                                            r.cond.as<double>(), r.erec.as<char>(), r.gcond.as<uint16_t>(), r.gmarg.as<int32_t>(),
                                             r.mpair.as<double2>(), r.rcos.as<double>(), r.csphi.as<double2>());
     }
     EnvTables &e = job.sd.env;
     e.mpair = r.mpair.as<double2>(); e.rec = r.erec.as<char>();
     e.gmarg = r.gmarg.as<int32_t>();
-    e.gcond = r.gcond.as<int32_t>();
+    e.gcond = r.gcond.as<uint16_t>();
     e.raw = sc->env; e.total = r.info.as<double>();
     e.rcos = r.rcos.as<double>(); e.csphi = r.csphi.as<double2>();
     e.W = W; e.H = H;

@@ -378,7 +378,7 @@ __global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__r
 // intervals and the guide tables of both CDFs
 __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const double *__restrict__ wts,
                              const double *__restrict__ info, const double *__restrict__ marg,
-                             const double *__restrict__ cond, char *__restrict__ rec, int32_t *__restrict__ gcond,
+                             const double *__restrict__ cond, char *__restrict__ rec, uint16_t *__restrict__ gcond,
                              int32_t *__restrict__ gmarg,
                              double2 *__restrict__ mpair, double *__restrict__ rcos, double2 *__restrict__ csphi) {
     int i = blockIdx.x;
@@ -395,7 +395,7 @@ __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const 
             float *f = (float *)(r + 8);
             f[0] = fmaxf(L[0], 0.0f); f[1] = fmaxf(L[1], 0.0f); f[2] = fmaxf(L[2], 0.0f);
             *(float *)(r + 20) = env_pdf_uv(make_double2(marg[i], marg[i + 1]), make_double2(cr[j], cr[j + 1]), W, H);
-            gcond[(size_t)i * W + j] = lo;
+            gcond[(size_t)i * W + j] = (uint16_t)lo;
         }
         if (i == H - 1 && threadIdx.x < 4) ((int32_t *)(rec + (size_t)kEnvRecBytes * W * H))[threadIdx.x] = 0;
     } else {

@@ -443,3 +443,19 @@ def test_binding_rejects_mismatched_buffers(mr):
     img = torch.empty((npix, 3), device="cuda")
     st = mr.lib().mrs_render(C.byref(sc_s), C.addressof(vs), 1, C.byref(op), img.data_ptr(), None, None)
     assert st == mr.MRS_EINVAL and b"overlaps" in mr.lib().mrs_last_error()
+
+
+def test_env_size_limits_rejected(mr):
+    """An env wider than the 16-bit column guides can address is refused
+    before any launch, with MRS_EOVERFLOW; the widest one still renders."""
+    w = _textured()
+    sc = mr.GpuScene.from_synth(w.scene)
+    wide = mr.GpuScene(sc.pos, sc.faces, torch.ones((1, 65537, 3), device="cuda"), bvh=sc.bvh, uv=sc.uv,
+                       albedo=sc.albedo, rough=sc.rough, metal=sc.metal)
+    with pytest.raises(mr.MirresError, match="wider than 65536") as e:
+        mr.render(wide, w.views, w.opts)
+    assert e.value.code == mr.MRS_EOVERFLOW
+    ok = mr.GpuScene(sc.pos, sc.faces, torch.ones((2, 65536, 3), device="cuda"), bvh=sc.bvh, uv=sc.uv,
+                     albedo=sc.albedo, rough=sc.rough, metal=sc.metal)
+    img = mr.render(ok, w.views, w.opts)
+    assert torch.isfinite(img).all()
