@@ -309,17 +309,42 @@ constexpr int kWorkParts = 64;
 constexpr int kClaimStride = 32;
 constexpr int kClaimWords = kWorkParts * kClaimStride;
 static_assert(MRS_REFILL >= 1 && MRS_REFILL <= 64, "a refill needs between 1 and 64 idle lanes");
+static_assert(kWorkParts == 64, "a wavefront reads the partition counters one per lane");
+#ifndef MRS_SMALL_QUEUE
+#define MRS_SMALL_QUEUE (1u << 19)
+#endif
+constexpr uint32_t kSmallQueue = MRS_SMALL_QUEUE;
 
 // Persistent traversal of queue entries [0, n).  Each lane traces one ray at
 // a time; once at least MRS_REFILL lanes of the wavefront have finished, the
 // idle lanes claim the next unclaimed entries of the wavefront's current
 // partition with one atomic per wavefront, so a wavefront runs until the
 // queue is drained instead of as long as its slowest ray (ray replacement,
-// after Aila and Laine, HPG 2009).  A drained partition sends the wavefront on
-// to the next one; after seeing all of them drained it stops.  claim points at
+// after Aila and Laine, HPG 2009).  When its partition runs dry the wavefront
+// moves on.  On a large queue it steps to the next partition and stops after
+// seeing every one of them at its end.  On a small queue (at most
+// kSmallQueue entries), where those steps, one atomic round trip each, would
+// be most of the launch, it reads all partition counters at once (lane p
+// reads partition p) and moves to the next partition with entries left, or
+// stops when none has any.  Counters only grow, and a claim that reaches a
+// partition's end has seen it drained for good, so either way a wavefront
+// claims from at most kWorkParts drained partitions.  claim points at
 // kClaimWords zeroed words.  load(i, o, d) fetches entry i's ray;
 // done(i, hit, occluded) stores its result.  Every lane of the launch must
 // call this (block sizes are multiples of 64).
+// The next partition after `part` (cyclically) that still has unclaimed
+// entries, or -1: lane p reads partition p's counter.  Kept out of line so
+// that this rare step does not take registers from the traversal loop.
+__device__ __attribute__((noinline)) int next_open_part(const uint32_t *claim, uint32_t n, int part) {
+    const uint32_t lane = __lane_id();
+    const uint64_t plo = (uint64_t)n * lane / kWorkParts, phi = (uint64_t)n * (lane + 1) / kWorkParts;
+    const uint32_t c = __hip_atomic_load(claim + lane * kClaimStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t open = __ballot((int)lane != part && plo + c < phi);
+    if (open == 0) return -1;
+    const uint64_t after = part == kWorkParts - 1 ? 0ull : open & (~0ull << (part + 1));
+    return __ffsll((long long)(after ? after : open)) - 1;
+}
+
 template <bool kAny, class Load, class Done>
 __device__ __forceinline__ void persistent_trace(const WideNode *__restrict__ nodes, const TriRec *__restrict__ tris,
                                                  uint32_t n, uint32_t *claim, void *lds, Load load, Done done) {
@@ -336,9 +361,10 @@ __device__ __forceinline__ void persistent_trace(const WideNode *__restrict__ no
     // partition p is first worked on by the XCD p % 8
     const uint32_t wave = blockIdx.x / 8 * (blockDim.x / 64) + threadIdx.x / 64;
     int part = (int)(blockIdx.x % 8 + 8 * (wave % (kWorkParts / 8)));
-    int seen = 0;                  // drained partitions seen (wave-uniform)
+    bool claiming = true;          // some partition may hold entries (wave-uniform)
+    int seen = 0;                  // partition ends seen, stepping one partition at a time
     while (true) {
-        if (seen < kWorkParts) {
+        if (claiming) {
             uint64_t idle = __ballot(item < 0);
             uint32_t nidle = (uint32_t)__popcll(idle);
             if (nidle >= MRS_REFILL) {
@@ -347,8 +373,13 @@ __device__ __forceinline__ void persistent_trace(const WideNode *__restrict__ no
                 if (lane == 0) base = atomicAdd(claim + part * kClaimStride, nidle);
                 base = __builtin_amdgcn_readfirstlane(base);
                 if (lo + base + nidle >= hi) {
-                    part = part + 1 == kWorkParts ? 0 : part + 1;
-                    ++seen;
+                    if (n <= kSmallQueue) {
+                        part = next_open_part(claim, n, part);
+                        claiming = part >= 0;
+                    } else {
+                        part = part + 1 == kWorkParts ? 0 : part + 1;
+                        claiming = ++seen < kWorkParts;
+                    }
                 }
                 if (item < 0) {
                     uint64_t idx = lo + base + (uint64_t)__popcll(idle & below);
@@ -365,7 +396,7 @@ __device__ __forceinline__ void persistent_trace(const WideNode *__restrict__ no
                 }
             }
         }
-        if (__ballot(item >= 0) == 0 && seen >= kWorkParts) break;
+        if (__ballot(item >= 0) == 0 && !claiming) break;
         trace_iter<kAny>(nodes, tris, item >= 0, r, h, occl, st, node);
         if (item >= 0 && node == kNone) {
             done((uint32_t)item, h, occl);
