@@ -425,7 +425,7 @@ mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
     {
         PROF(KID_ENV, s);
         k_env_rows<<<H, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.cond.as<double>(), r.rowsum.as<double>());
-        k_env_marg<<<1, 64, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
+        k_env_marg<<<1, kMargThreads, 0, s>>>(r.rowsum.as<double>(), H, r.marg.as<double>(), r.info.as<double>());
         k_env_finish<<<H + 1, 256, 0, s>>>(sc->env, W, H, r.wts.as<double>(), r.info.as<double>(), r.marg.as<double>(),
                                             r.cond.as<double>(), r.erec.as<char>(), r.gcond.as<uint16_t>(), r.gmarg.as<int32_t>(),
                                             r.mpair.as<double2>(), r.rcos.as<double>(), r.csphi.as<double2>());

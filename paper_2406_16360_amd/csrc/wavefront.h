@@ -364,14 +364,35 @@ __global__ void k_env_rows(const float *__restrict__ env, int W, int H, double *
     if (threadIdx.x == 0) { cr[W] = 1.0; rowsum[i] = carry; }
 }
 
-__global__ void k_env_marg(const double *__restrict__ rowsum, int H, double *__restrict__ marg, double *__restrict__ info) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double acc = 0.0;
-    marg[0] = 0.0;
-    for (int i = 0; i < H; ++i) { acc += rowsum[i]; marg[i + 1] = acc; }
-    for (int i = 1; i <= H; ++i) marg[i] = acc > 0.0 ? marg[i] / acc : marg[i];
-    marg[H] = 1.0;
-    info[0] = acc;
+// Marginal CDF over the rows, normalised, with marg[H] = 1 exactly, and the
+// total weight in info[0].  One block of kMargThreads threads: each sums a
+// contiguous run of rows, the run sums are scanned in LDS, and each thread
+// then writes its rows' prefix sums (the serial loop it replaces waited on
+// one load per row).
+constexpr int kMargThreads = 256;
+__global__ void __launch_bounds__(kMargThreads) k_env_marg(const double *__restrict__ rowsum, int H,
+                                                            double *__restrict__ marg, double *__restrict__ info) {
+    __shared__ double part[kMargThreads];
+    const int t = threadIdx.x;
+    const int chunk = (H + kMargThreads - 1) / kMargThreads;
+    const int a = min(H, t * chunk), b = min(H, a + chunk);
+    double s = 0.0;
+    for (int i = a; i < b; ++i) s += rowsum[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kMargThreads; off <<= 1) {      // inclusive Hillis-Steele scan
+        const double v = t >= off ? part[t - off] : 0.0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const double total = part[kMargThreads - 1];
+    double acc = t > 0 ? part[t - 1] : 0.0;
+    for (int i = a; i < b; ++i) {
+        acc += rowsum[i];
+        marg[i + 1] = i + 1 == H ? 1.0 : (total > 0.0 ? acc / total : acc);
+    }
+    if (t == 0) { marg[0] = 0.0; info[0] = total; }
 }
 
 // texel records (conditional CDF value, radiance, pdf_uv), the marginal
