@@ -650,6 +650,21 @@ __global__ void k_wide_build(const BvhNode *__restrict__ nodes, int nnodes, cons
         ref[nc] = side ? nd.n3.y : nd.n3.x;
         ++nc;
     }
+    // members by surface area, largest first: any-hit traversal takes the
+    // first hit member next, and a large one is the likelier to hold the
+    // occluder (closest hit sorts the hit members by distance anyway)
+    auto area = [&](int c) {
+        const float dx = hi[c][0] - lo[c][0], dy = hi[c][1] - lo[c][1], dz = hi[c][2] - lo[c][2];
+        return dx * dy + dy * dz + dz * dx;
+    };
+    for (int x = 1; x < nc; ++x)
+        for (int y = x; y > 0 && area(y) > area(y - 1); --y) {
+            for (int q = 0; q < 3; ++q) {
+                float t = lo[y][q]; lo[y][q] = lo[y - 1][q]; lo[y - 1][q] = t;
+                t = hi[y][q]; hi[y][q] = hi[y - 1][q]; hi[y - 1][q] = t;
+            }
+            const int r = ref[y]; ref[y] = ref[y - 1]; ref[y - 1] = r;
+        }
     WideNode w;
     uint32_t meta = (uint32_t)nc << 24;
     uint32_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
