@@ -287,7 +287,6 @@ struct EnvTables {
     // read them at uniformly spread cells, so their size counts.
     const uint16_t *gcond;
     const int32_t *gmarg;   // [H] guide: first candidate row for u0 in [t/H, (t+1)/H)
-    const float *raw;       // [H][W][3] the caller's env (for gradient masks)
     int W, H;
     const double *total;    // device: total sampling weight (no valid sample when 0)
     const double *rcos;     // [H + 1] cos(i pi / H): the direction's y at the edge above row i
@@ -365,7 +364,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 }
 
 // 24-byte texel records: texel t at byte 24 t holds cdf[j] (double, the
-// row's conditional CDF at its column j), L_r, L_g, L_b (clamped >= 0) and
+// row's conditional CDF at its column j), L_r, L_g, L_b (env_store) and
 // env_pdf_uv of the texel (float, from its row's marginal interval and its
 // conditional interval); the upper end cdf[j + 1] is the next record's first
 // word, and 1 after a row's last texel (the build sets the row's last CDF
@@ -373,6 +372,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 // the second load of the last record stays in the buffer.  env_lp returns
 // (L_r, L_g, L_b, pdf_uv).
 constexpr uint32_t kEnvRecBytes = 24u;
+// a radiance channel as the records hold it: max(0, L), where L < 0 or NaN
+// gives a negative zero.  Its sign bit is then the adjoint's mask (the
+// derivative of max(0, L) is taken as 1 for L >= 0), so the adjoint needs
+// no read of the caller's env.
+__device__ __forceinline__ float env_store(float L) { return L >= 0.0f ? L + 0.0f : -0.0f; }
 __device__ __forceinline__ float4 env_lp(const EnvTables &e, int t) {
     return *(const float4 *)((const char *)e.rec + (size_t)kEnvRecBytes * t + 8);
 }

@@ -434,7 +434,7 @@ mrs_status env_tables(const mrs_scene *sc, Job &job, Res &r, hipStream_t s) {
     e.mpair = r.mpair.as<double2>(); e.rec = r.erec.as<char>();
     e.gmarg = r.gmarg.as<int32_t>();
     e.gcond = r.gcond.as<uint16_t>();
-    e.raw = sc->env; e.total = r.info.as<double>();
+    e.total = r.info.as<double>();
     e.rcos = r.rcos.as<double>(); e.csphi = r.csphi.as<double2>();
     e.W = W; e.H = H;
     return MRS_OK;

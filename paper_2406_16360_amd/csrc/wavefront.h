@@ -414,7 +414,8 @@ __global__ void k_env_finish(const float *__restrict__ env, int W, int H, const 
             char *r = rec + (size_t)kEnvRecBytes * ((size_t)i * W + j);
             *(double *)r = cr[j];
             float *f = (float *)(r + 8);
-            f[0] = fmaxf(L[0], 0.0f); f[1] = fmaxf(L[1], 0.0f); f[2] = fmaxf(L[2], 0.0f);
+            // max(0, L), a negative zero where L < 0 or NaN: the adjoint's gradient mask
+            f[0] = env_store(L[0]); f[1] = env_store(L[1]); f[2] = env_store(L[2]);
             *(float *)(r + 20) = env_pdf_uv(make_double2(marg[i], marg[i + 1]), make_double2(cr[j], cr[j + 1]), W, H);
             gcond[(size_t)i * W + j] = (uint16_t)lo;
         }
@@ -1130,6 +1131,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
         ip.n = 0;
         int etex = miss ? miss_tex : -1;
         V3 ge = gp;
+        float4 elp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // record of etex (its radiance signs mask the gradient)
         if (has) {
             uint64_t ti = (uint64_t)(k - 1) * a.tape.S + (g - a.tape.base);
             float4 th = a.tape.hit[ti];
@@ -1149,6 +1151,7 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
                 V3 yl = to_local(S.F, xyz(ty));
                 int tex = __float_as_int(th.w);
                 float4 lp = env_lp(a.s.env, tex);
+                elp = lp;
                 V3 Lv = V3{lp.x, lp.y, lp.z};
                 float cw = yl.z * ty.w;
                 BrdfGrad bg = brdf_grad(L, m, yl);
@@ -1194,9 +1197,9 @@ __device__ __forceinline__ void adjoint_sample(const AdjArgs &a, bool valid, uin
                  env_rec ? a.env_base + kEnvRec * (uint32_t)etex : kAggEmpty);
         if (has && a.mat_on) put_material(ws, ip, 0, gm);
         if (env_rec) {
-            const float *raw = a.s.env.raw + 3 * (size_t)etex;
-            const float v[kEnvChannels] = {raw[0] >= 0.0f ? ge.x : 0.0f, raw[1] >= 0.0f ? ge.y : 0.0f,
-                                           raw[2] >= 0.0f ? ge.z : 0.0f};
+            if (!has) elp = env_lp(a.s.env, etex);   // a camera ray's miss
+            const float v[kEnvChannels] = {signbit(elp.x) ? 0.0f : ge.x, signbit(elp.y) ? 0.0f : ge.y,
+                                           signbit(elp.z) ? 0.0f : ge.z};
             ws.add(a.env_base + kEnvRec * (uint32_t)etex, 1.0f, v);
         }
         ws.flush();
