@@ -183,14 +183,15 @@ __device__ __forceinline__ int inner_step(const WideNode *__restrict__ nodes, co
         t[c] = (c < nc && tn <= tf * 1.0000008f) ? tn : INFINITY;
     }
     if (kAny) {
-        // any hit ends the ray, so the order of the hit children only moves
-        // the work around: the first hit child is next, the others stacked
+        // any hit ends the ray: the members are stored largest first, so the
+        // first hit one is next and the others are stacked to pop in member
+        // order
         int next = kNone;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 3; c >= 0; --c) {
             if (t[c] == INFINITY) continue;
-            if (next == kNone) next = ref[c];
-            else st.push(ref[c]);
+            if (next != kNone) st.push(next);
+            next = ref[c];
         }
         if (next != kNone) return next;
         return st.sp > 0 ? st.pop() : kNone;
