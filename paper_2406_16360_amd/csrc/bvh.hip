@@ -848,6 +848,16 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
         TRY(hip_check(hipMemcpyAsync(&h_depth, depth.p, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy"));
         TRY(hip_check(hipStreamSynchronize(s), "sync"));
         b->depth = h_depth;
+        // a traversal node's members lie at most three binary levels below
+        // it, and a triangle with d ancestors sits in a leaf at least d - 1
+        // levels down, so its path meets at least ceil((d - 1) / 3) traversal
+        // nodes; a tree that must overflow the stack is refused before the
+        // collapse
+        if (3 * ((h_depth + 1) / 3) + 2 > kStackSize) {
+            st = fail(MRS_EOVERFLOW, "mrs_build_bvh: tree depth %d exceeds the traversal stack (%d entries)", h_depth,
+                      kStackSize);
+            goto done;
+        }
     }
     // state for mrs_bvh_refit
     TRY(b->npar.alloc(sizeof(int32_t) * b->nnodes));
