@@ -243,10 +243,10 @@ __device__ __forceinline__ int any_leaf(const TriRec *__restrict__ tris, const R
 // closest-hit traversal (closest-hit leaves cost more: their hits keep the
 // ray going, so batching more of them pays)
 #ifndef MRS_LEAF_BATCH
-#define MRS_LEAF_BATCH 8
+#define MRS_LEAF_BATCH 2
 #endif
 #ifndef MRS_LEAF_BATCH_CLOSEST
-#define MRS_LEAF_BATCH_CLOSEST 12
+#define MRS_LEAF_BATCH_CLOSEST 8
 #endif
 
 // One traversal iteration of a wavefront (while-while traversal with
