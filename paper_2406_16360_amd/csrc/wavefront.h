@@ -866,7 +866,7 @@ constexpr int kScatSlots = 13;       // staged form: pairs a lane stages per flu
 constexpr int kAggBits = 8;
 constexpr int kAggSlots = 1 << kAggBits;   // merged form: hash slots per wavefront
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
-constexpr int kAdjBlock = 256;
+constexpr int kAdjBlock = 64;
 // The largest flush of a lane: kEntriesPerFlush material records and one env
 // record.  The staged form drops pairs past kScatSlots and the merged form
 // needs free slots to end its probing, so these bounds keep the scatter lossless.
