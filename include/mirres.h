@@ -151,7 +151,7 @@ typedef struct {
     int32_t  grad_mode;      /* MRS_GRAD_*: FULL (all vertices) or PRIMARY (Sec. 4.2 detach) */
     int32_t  tape_mode;      /* MRS_TAPE_*: keep per-vertex records for the adjoint or recompute */
     int64_t  tape_budget;    /* bytes the tape may use in AUTO mode; 0 = half of free device memory */
-    int32_t  pool;           /* paths in flight; 0 = library default (2^26, a whole output chunk) */
+    int32_t  pool;           /* paths in flight; 0 = library default (2^27, a whole output chunk) */
     int32_t  block;          /* threads per block of the trace/shade kernels: 0 = default (64),
                                 else a multiple of 64 in [64, 256] */
     float   *debug_sample_rgb;   /* nullable device [S][3]: per-sample radiance, S = sum W*H*spp */

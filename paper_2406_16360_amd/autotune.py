@@ -19,7 +19,7 @@ import torch
 
 from . import mirres
 
-DEFAULT_POOLS = (1 << 22, 1 << 23, 1 << 24, 1 << 25, 1 << 26)
+DEFAULT_POOLS = (1 << 22, 1 << 23, 1 << 24, 1 << 25, 1 << 26, 1 << 27)
 DEFAULT_BLOCKS = (64, 128, 256)
 
 

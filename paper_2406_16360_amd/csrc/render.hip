@@ -95,8 +95,8 @@ struct ProfScope {
 // ============================================================================
 // jobs and buffers
 // ============================================================================
-constexpr uint64_t kOutChunkMax = 1ull << 26;   // samples per super-chunk of the output buffer
-constexpr uint32_t kPoolDefault = 1u << 26;      // paths in flight: a whole output chunk (160 B each: 10.7 GB)
+constexpr uint64_t kOutChunkMax = 1ull << 27;   // samples per super-chunk of the output buffer
+constexpr uint32_t kPoolDefault = 1u << 27;      // paths in flight: a whole output chunk (160 B each: 21.5 GB)
 constexpr int kBlockDefault = 64;                // threads per workgroup of the trace and shade kernels
 constexpr uint64_t kTapeRecBytes = 36;           // tape bytes per path vertex
 constexpr uint64_t kTapeFieldBytes = 16;         // and, in field mode, the field's output at the vertex
