@@ -18,8 +18,6 @@
 #include <cstdio>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
-
 #include "device.h"
 #include "runtime.h"
 
@@ -701,6 +699,98 @@ __global__ void k_check_faces(const int32_t *__restrict__ faces, int nf, int nv,
     }
 }
 
+// Exclusive prefix sums of two int32 flag arrays at once (the merge and keep
+// flags of a PLOC round): per-tile sums, one block scanning the tile sums,
+// then each tile's outputs.  A thread owns kScanItems consecutive entries.
+constexpr int kScanThreads = 256, kScanItems = 8, kScanTile = kScanThreads * kScanItems;
+__device__ __forceinline__ int2 add2(int2 u, int2 v) { return make_int2(u.x + v.x, u.y + v.y); }
+
+// in-place inclusive scan of sh[0 .. kScanThreads) (every thread of the block calls it)
+__device__ __forceinline__ void block_scan2(int2 *sh) {
+    const int t = threadIdx.x;
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int2 u = t >= off ? sh[t - off] : make_int2(0, 0);
+        __syncthreads();
+        sh[t] = add2(sh[t], u);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan2_tiles(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                                                              int n, int2 *__restrict__ part) {
+    __shared__ int2 sh[kScanThreads];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int2 v = make_int2(0, 0);
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < n) { v.x += a[base + q]; v.y += b[base + q]; }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    block_scan2(sh);
+    if (threadIdx.x == kScanThreads - 1) part[blockIdx.x] = sh[kScanThreads - 1];
+}
+
+// exclusive scan of the nb tile sums in place, one block
+__global__ void __launch_bounds__(kScanThreads) k_scan2_top(int2 *__restrict__ part, int nb) {
+    __shared__ int2 sh[kScanThreads];
+    int2 carry = make_int2(0, 0);
+    for (int c = 0; c < nb; c += kScanThreads) {
+        const int i = c + threadIdx.x;
+        const int2 v = i < nb ? part[i] : make_int2(0, 0);
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        block_scan2(sh);
+        const int2 incl = sh[threadIdx.x], total = sh[kScanThreads - 1];
+        if (i < nb) part[i] = make_int2(carry.x + incl.x - v.x, carry.y + incl.y - v.y);
+        carry = add2(carry, total);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan2_out(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                                                            int n, const int2 *__restrict__ part,
+                                                            int32_t *__restrict__ oa, int32_t *__restrict__ ob) {
+    __shared__ int2 sh[kScanThreads];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int2 v = make_int2(0, 0);
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < n) { v.x += a[base + q]; v.y += b[base + q]; }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    block_scan2(sh);
+    int2 run = add2(part[blockIdx.x], make_int2(sh[threadIdx.x].x - v.x, sh[threadIdx.x].y - v.y));
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < n) {
+            oa[base + q] = run.x; ob[base + q] = run.y;
+            run.x += a[base + q]; run.y += b[base + q];
+        }
+}
+
+// the same exclusive sums for a short array, in one launch of one block
+// that walks it tile by tile with a carry
+constexpr int kScanOneMax = 1 << 16;
+__global__ void __launch_bounds__(kScanThreads) k_scan2_one(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                                                            int n, int32_t *__restrict__ oa, int32_t *__restrict__ ob) {
+    __shared__ int2 sh[kScanThreads];
+    int2 carry = make_int2(0, 0);
+    for (int c = 0; c < n; c += kScanTile) {
+        const int base = c + threadIdx.x * kScanItems;
+        int2 v = make_int2(0, 0);
+        for (int q = 0; q < kScanItems; ++q)
+            if (base + q < n) { v.x += a[base + q]; v.y += b[base + q]; }
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        block_scan2(sh);
+        int2 run = add2(carry, make_int2(sh[threadIdx.x].x - v.x, sh[threadIdx.x].y - v.y));
+        carry = add2(carry, sh[kScanThreads - 1]);
+        __syncthreads();
+        for (int q = 0; q < kScanItems; ++q)
+            if (base + q < n) {
+                oa[base + q] = run.x; ob[base + q] = run.y;
+                run.x += a[base + q]; run.y += b[base + q];
+            }
+    }
+}
+
 inline int blocks(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -801,10 +891,7 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
         TRY(cnt.alloc(sizeof(int32_t) * nn2));
         for (DevBuf *d : {&clus, &clus2, &nn, &mflag, &kflag, &mo, &ko, &slot}) TRY(d->alloc(sizeof(int32_t) * n));
         TRY(tot.alloc(sizeof(int32_t) * 2));
-        size_t tmp_bytes = 0;
-        TRY(hip_check(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, (int32_t *)mflag.p, (int32_t *)mo.p, n, s),
-                      "scan size"));
-        TRY(scan_tmp.alloc(std::max<size_t>(tmp_bytes, 16)));
+        TRY(scan_tmp.alloc(sizeof(int2) * (size_t)blocks(n, kScanTile)));
         float4 *nlo = (float4 *)blo.p, *nhi = (float4 *)bhi.p;
         k_ploc_init<<<blocks(n), 256, 0, s>>>((float4 *)tlo.p, (float4 *)thi.p, (uint32_t *)ids.p, n, nlo, nhi,
                                               (int32_t *)clus.p, (int32_t *)cnt.p);
@@ -812,10 +899,16 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
         while (count > 1) {
             k_ploc_nn<<<blocks(count, kPlocBlock), kPlocBlock, 0, s>>>((int32_t *)clus.p, count, nlo, nhi, (int32_t *)nn.p);
             k_ploc_flags<<<blocks(count), 256, 0, s>>>((int32_t *)nn.p, count, (int32_t *)mflag.p, (int32_t *)kflag.p);
-            TRY(hip_check(hipcub::DeviceScan::ExclusiveSum(scan_tmp.p, tmp_bytes, (int32_t *)mflag.p, (int32_t *)mo.p,
-                                                           count, s), "scan"));
-            TRY(hip_check(hipcub::DeviceScan::ExclusiveSum(scan_tmp.p, tmp_bytes, (int32_t *)kflag.p, (int32_t *)ko.p,
-                                                           count, s), "scan"));
+            if (count <= kScanOneMax) {   // exclusive sums of the merge and keep flags
+                k_scan2_one<<<1, kScanThreads, 0, s>>>((int32_t *)mflag.p, (int32_t *)kflag.p, count, (int32_t *)mo.p,
+                                                       (int32_t *)ko.p);
+            } else {
+                const int nb = blocks(count, kScanTile);
+                k_scan2_tiles<<<nb, kScanThreads, 0, s>>>((int32_t *)mflag.p, (int32_t *)kflag.p, count, (int2 *)scan_tmp.p);
+                k_scan2_top<<<1, kScanThreads, 0, s>>>((int2 *)scan_tmp.p, nb);
+                k_scan2_out<<<nb, kScanThreads, 0, s>>>((int32_t *)mflag.p, (int32_t *)kflag.p, count,
+                                                        (const int2 *)scan_tmp.p, (int32_t *)mo.p, (int32_t *)ko.p);
+            }
             k_ploc_totals<<<1, 64, 0, s>>>((int32_t *)mflag.p, (int32_t *)mo.p, (int32_t *)kflag.p, (int32_t *)ko.p,
                                            count, (int32_t *)tot.p);
             k_ploc_merge<<<blocks(count), 256, 0, s>>>((int32_t *)clus.p, (int32_t *)nn.p, count, (int32_t *)mflag.p,

@@ -1,6 +1,6 @@
 // BVH traversal for gfx950: closest hit and any hit over the traversal nodes
-// (four 8-bit quantised child boxes per 64-byte node, built from the binary
-// tree two levels at a time), with the watertight
+// (four 8-bit quantised child boxes per 64-byte node, a surface-area
+// collapse of the binary tree), with the watertight
 // ray-triangle test of Woop, Benthin and Wald (JCGT 2013): edges count as
 // inside, only t > 0 hits, degenerate triangles never hit, equal t resolves
 // to the lower original face id.
