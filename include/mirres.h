@@ -49,6 +49,7 @@
  */
 #ifndef MIRRES_H
 #define MIRRES_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -404,6 +405,20 @@ typedef struct {
 } mrs_kernel_time;
 mrs_status mrs_profile_begin(void);
 mrs_status mrs_profile_end(mrs_kernel_time *out, int32_t cap, int32_t *n);
+
+/* Stable radix sort of n (32-bit key, 32-bit value) pairs by key, ascending,
+ * equal keys in their input order: the sort the library runs to put the
+ * field pull-back's points in Morton order (App. A, material field) and to
+ * group the deterministic adjoint's gradient pairs by record.  d_keys_in,
+ * d_vals_in: device uint32 [n], read only; d_keys_out, d_vals_out: device
+ * uint32 [n], written (they must not be the inputs); d_tmp: caller-owned
+ * device scratch of at least mrs_sort_pairs_tmp_bytes(n) bytes (nothing is
+ * allocated).  Enqueued on `stream` without waiting.  Errors: MRS_EINVAL
+ * (n < 0, a null buffer, an output equal to its input, too little scratch),
+ * MRS_EOVERFLOW (n > 2^31 - 1), MRS_EHIP. */
+size_t     mrs_sort_pairs_tmp_bytes(int64_t n);
+mrs_status mrs_sort_pairs_u32(const uint32_t *d_keys_in, uint32_t *d_keys_out, const uint32_t *d_vals_in,
+                              uint32_t *d_vals_out, int64_t n, void *d_tmp, size_t tmp_bytes, void *stream);
 
 /* Frees the library's internal device workspace and the spare tape buffers
  * (they regrow on demand). */

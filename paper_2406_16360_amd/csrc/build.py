@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 LIB = os.path.join(PKG, "libmirres.so")
-SOURCES = ["bvh.hip", "render.hip", "denoise.hip", "field.hip"]
+SOURCES = ["bvh.hip", "render.hip", "denoise.hip", "field.hip", "sort.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -5,33 +5,8 @@
 
 #include <algorithm>
 
-#include <hipcub/hipcub.hpp>
-
 #include "field.h"
 #include "runtime.h"
-
-namespace mrs {
-
-size_t sort_pairs_tmp_bytes(size_t n) {
-    size_t bytes = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                           (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n) != hipSuccess)
-        return 0;
-    return bytes;
-}
-
-mrs_status sort_pairs_u32(const uint32_t *keys_in, uint32_t *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
-                          size_t n, DevBuf &tmp, hipStream_t s) {
-    if (n > 0x7FFFFFFFull) return fail(MRS_EOVERFLOW, "sort of more than 2^31 - 1 pairs");
-    size_t bytes = sort_pairs_tmp_bytes(n);
-    mrs_status st = tmp.reserve(std::max<size_t>(bytes, 16));
-    if (st != MRS_OK) return st;
-    return hip_check(hipcub::DeviceRadixSort::SortPairs(tmp.p, bytes, keys_in, keys_out, vals_in, vals_out, (int)n, 0,
-                                                        32, s),
-                     "radix sort");
-}
-
-}  // namespace mrs
 
 namespace mrs {
 namespace {

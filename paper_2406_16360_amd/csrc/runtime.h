@@ -47,9 +47,9 @@ struct DevBuf {
     template <class T> T *as() const { return (T *)p; }
 };
 
-// Radix sort of n (32-bit key, 32-bit value) pairs by key on stream s, with
-// hipcub; tmp holds the scratch space, sized by sort_pairs_tmp_bytes(n) (so
-// a caller that reserves it first can run this under graph capture).
+// Stable radix sort of n (32-bit key, 32-bit value) pairs by key on stream s
+// (sort.hip); tmp holds the scratch space, sized by sort_pairs_tmp_bytes(n)
+// (so a caller that reserves it first can run this under graph capture).
 size_t sort_pairs_tmp_bytes(size_t n);
 mrs_status sort_pairs_u32(const uint32_t *keys_in, uint32_t *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
                           size_t n, DevBuf &tmp, hipStream_t s);

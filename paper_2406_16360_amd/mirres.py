@@ -88,7 +88,7 @@ EXPORTS = ["mrs_build_bvh", "mrs_build_bvh_with", "mrs_bvh_refit", "mrs_bvh_dest
            "mrs_plan_create", "mrs_plan_forward", "mrs_plan_backward", "mrs_plan_info", "mrs_plan_destroy",
            "mrs_tape_bytes", "mrs_tape_destroy", "mrs_gbuffer", "mrs_denoise_work_bytes", "mrs_denoise",
            "mrs_denoise_backward", "mrs_denoise_noalloc", "mrs_field_eval", "mrs_field_backward", "mrs_profile_begin", "mrs_profile_end",
-           "mrs_release_workspace", "mrs_last_error"]
+           "mrs_sort_pairs_tmp_bytes", "mrs_sort_pairs_u32", "mrs_release_workspace", "mrs_last_error"]
 
 
 class _KernelTime(C.Structure):
@@ -148,6 +148,10 @@ def _load():
     lib.mrs_plan_info.restype = i32
     lib.mrs_plan_info.argtypes = [p, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
     lib.mrs_plan_destroy.argtypes = [p]
+    lib.mrs_sort_pairs_tmp_bytes.restype = C.c_size_t
+    lib.mrs_sort_pairs_tmp_bytes.argtypes = [i64]
+    lib.mrs_sort_pairs_u32.restype = i32
+    lib.mrs_sort_pairs_u32.argtypes = [p, p, p, p, i64, p, C.c_size_t, p]
     lib.mrs_last_error.restype = C.c_char_p
     return lib
 
@@ -761,6 +765,20 @@ def denoise_noalloc(views: Sequence, color: torch.Tensor, normal: torch.Tensor, 
     _check(_lib.mrs_denoise_noalloc(C.addressof(vs), len(views), C.byref(params), color.data_ptr(),
                                     normal.data_ptr(), position.data_ptr(), out.data_ptr(), _stream(stream)))
     return out
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor):
+    """Stable sort of (key, value) pairs by key (uint32 bits in int32 GPU
+    tensors of one length): returns the sorted keys and values (new tensors)."""
+    n = keys.numel()
+    for t, name in ((keys, "keys"), (vals, "vals")):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"mirres: {name} must be a contiguous int32 GPU tensor of {n} entries")
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    tmp = torch.empty(max(int(_lib.mrs_sort_pairs_tmp_bytes(n)), 16), dtype=torch.uint8, device=keys.device)
+    _check(_lib.mrs_sort_pairs_u32(keys.data_ptr(), ko.data_ptr(), vals.data_ptr(), vo.data_ptr(), n, tmp.data_ptr(),
+                                   tmp.numel(), _stream()))
+    return ko, vo
 
 
 class _DenoiseFn(torch.autograd.Function):

@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2406_16360_amd", "libmirres.so")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mrs_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(mrs_[a-z0-9_]+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")
