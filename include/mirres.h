@@ -220,7 +220,10 @@ enum {
     MRS_BVH_PLOC = 1    /* Meister and Bittner, "Parallel Locally-Ordered Clustering for Bounding
                            Volume Hierarchy Construction" (TVCG 2018): rounds that merge mutual
                            nearest neighbours within 32 sorted positions by the surface area of
-                           their union box.  Fewer node visits per ray, longer build. */
+                           their union box, then one bottom-up sweep of treelet restructuring
+                           (Karras and Aila, HPG 2013: the best binary topology over up to 7
+                           subtrees by the surface area heuristic).  Fewer node visits per ray,
+                           longer build. */
 };
 
 /* As mrs_build_bvh, with the hierarchy chosen by `builder` (an MRS_BVH_*

@@ -6,7 +6,8 @@
 //     octrees and k-d trees", HPG 2012): binary radix tree from longest
 //     common prefixes, bottom-up boxes with per-node arrival counters; or
 //   - PLOC (Meister and Bittner, TVCG 2018): rounds of nearest-neighbour
-//     merging over the same order;
+//     merging over the same order, then a bottom-up sweep of treelet
+//     restructuring (Karras and Aila, HPG 2013; treelet.h);
 //   -> node layout with both child boxes per node, small subtrees collapsed
 //   into leaves of <= kLeafMax triangles, triangles copied in leaf order;
 //   then the traversal nodes (four quantised child boxes) over that tree.
@@ -20,6 +21,7 @@
 
 #include "device.h"
 #include "runtime.h"
+#include "treelet.h"
 
 namespace mrs {
 
@@ -270,11 +272,6 @@ __global__ void k_depth(const int32_t *__restrict__ parent, int n, int leaf_base
 constexpr int kPlocRadius = 32;
 constexpr int kPlocBlock = 256;
 
-__device__ __forceinline__ float half_area(float4 l, float4 h) {
-    float dx = h.x - l.x, dy = h.y - l.y, dz = h.z - l.z;
-    return dx * dy + dy * dz + dz * dx;
-}
-
 __global__ void k_ploc_init(const float4 *__restrict__ tlo, const float4 *__restrict__ thi,
                             const uint32_t *__restrict__ ids, int n, float4 *__restrict__ nlo,
                             float4 *__restrict__ nhi, int32_t *__restrict__ clus, int32_t *__restrict__ cnt) {
@@ -310,7 +307,7 @@ __global__ __launch_bounds__(kPlocBlock) void k_ploc_nn(const int32_t *__restric
         int j = i + d;
         if (d == 0 || j < 0 || j >= count) continue;
         float4 l2 = slo[s + d], h2 = shi[s + d];
-        float a = half_area(make_float4(fminf(l.x, l2.x), fminf(l.y, l2.y), fminf(l.z, l2.z), 0.f),
+        float a = box_half_area(make_float4(fminf(l.x, l2.x), fminf(l.y, l2.y), fminf(l.z, l2.z), 0.f),
                             make_float4(fmaxf(h.x, h2.x), fmaxf(h.y, h2.y), fmaxf(h.z, h2.z), 0.f));
         if (a < best) { best = a; bj = j; }
     }
@@ -358,6 +355,38 @@ __global__ void k_ploc_merge(const int32_t *__restrict__ clus, const int32_t *__
         clus_next[ko[i]] = id;
     } else if (keep[i]) {
         clus_next[ko[i]] = clus[i];
+    }
+}
+
+// One bottom-up sweep of treelet restructuring over PLOC's merge tree: a
+// thread starts at every triangle and climbs; the second child to arrive at
+// a node finishes it, its whole subtree being final then (arrival counters,
+// as in the refit).  Nodes of at least kTreeletLeaves triangles are treelet
+// roots; the others only take their cost.  The search tables live in LDS,
+// entry S of a thread at [S][thread].
+// One sweep by default: a second and third lowered traversal time by no more
+// than run-to-run noise and cost a sweep's time each.
+constexpr int kTreeletBlock = 64;
+#ifndef MRS_TREELET_PASSES
+#define MRS_TREELET_PASSES 1
+#endif
+__global__ void __launch_bounds__(kTreeletBlock) k_treelet(MergeTree t, int32_t *__restrict__ arrive) {
+    __shared__ float s_cost[kTreeletSets * kTreeletBlock];
+    __shared__ uint8_t s_split[kTreeletSets * kTreeletBlock];
+    const int k = blockIdx.x * kTreeletBlock + threadIdx.x;
+    if (k >= t.n) return;
+    const TreeletScratch w{s_cost + threadIdx.x, s_split + threadIdx.x, kTreeletBlock};
+    t.cost[k] = subtree_cost(box_half_area(t.lo[k], t.hi[k]), 1, 0.0f, 0.0f);
+    for (int node = t.parent[k]; node >= 0; node = t.parent[node]) {
+        __threadfence();
+        if (atomicAdd(&arrive[node - t.n], 1) == 0) return;
+        __threadfence();
+        if (t.cnt[node] >= kTreeletLeaves) {
+            treelet_optimize(t, node, w);
+        } else {
+            const int2 c = t.child[node];
+            t.cost[node] = subtree_cost(box_half_area(t.lo[node], t.hi[node]), t.cnt[node], t.cost[c.x], t.cost[c.y]);
+        }
     }
 }
 
@@ -813,7 +842,7 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
     int npow2 = 1024;
     while (npow2 < n) npow2 *= 2;
     DevBuf tlo, thi, keys, ids, child, parent, range, flags, blo, bhi, part, depth, bad;
-    DevBuf pchild, cnt, clus, clus2, nn, mflag, kflag, mo, ko, tot, slot, scan_tmp;   // PLOC
+    DevBuf pchild, cnt, clus, clus2, nn, mflag, kflag, mo, ko, tot, slot, scan_tmp, tcost, tarrive;   // PLOC
     const bool ploc = builder == MRS_BVH_PLOC && nf > 1;
     mrs_bvh *b = new mrs_bvh();
     b->nf = nf;
@@ -927,6 +956,18 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
             next_id += h_tot[0];
             count = h_tot[1];
             std::swap(clus.p, clus2.p);
+        }
+        // treelet restructuring of the merge tree: the clustering only pairs
+        // nearby clusters, and a sweep rearranges small subtrees where that
+        // left the surface-area cost high
+        if (MRS_TREELET_PASSES > 0 && n >= kTreeletLeaves) {
+            TRY(tcost.alloc(sizeof(float) * nn2));
+            TRY(tarrive.alloc(sizeof(int32_t) * (n - 1)));
+            const MergeTree mt{(int2 *)pchild.p, (int32_t *)parent.p, (int32_t *)cnt.p, nlo, nhi, (float *)tcost.p, n};
+            for (int pass = 0; pass < MRS_TREELET_PASSES; ++pass) {
+                k_fill_i32<<<blocks(n - 1), 256, 0, s>>>((int32_t *)tarrive.p, n - 1, 0);
+                k_treelet<<<blocks(n, kTreeletBlock), kTreeletBlock, 0, s>>>(mt, (int32_t *)tarrive.p);
+            }
         }
         k_ploc_slots<<<blocks(n), 256, 0, s>>>((int32_t *)parent.p, (int2 *)pchild.p, (int32_t *)cnt.p, n,
                                                (int32_t *)slot.p);
