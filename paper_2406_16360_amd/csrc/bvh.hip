@@ -362,31 +362,65 @@ __global__ void k_ploc_merge(const int32_t *__restrict__ clus, const int32_t *__
 // thread starts at every triangle and climbs; the second child to arrive at
 // a node finishes it, its whole subtree being final then (arrival counters,
 // as in the refit).  Nodes of at least kTreeletLeaves triangles are treelet
-// roots; the others only take their cost.  The search tables live in LDS,
-// entry S of a thread at [S][thread].
+// roots, the others only take their cost.  A block is one wavefront, and its
+// lanes search the subsets of each treelet root together, one root after
+// another: the subsets of one size at a time (each needs only smaller ones),
+// about 120 dependent steps per treelet instead of about 1000 for one lane
+// alone.  The split choices are those of the one-thread search.
 // One sweep by default: a second and third lowered traversal time by no more
-// than run-to-run noise and cost a sweep's time each.
+// than run-to-run noise.
 constexpr int kTreeletBlock = 64;
 #ifndef MRS_TREELET_PASSES
 #define MRS_TREELET_PASSES 1
 #endif
 __global__ void __launch_bounds__(kTreeletBlock) k_treelet(MergeTree t, int32_t *__restrict__ arrive) {
-    __shared__ float s_cost[kTreeletSets * kTreeletBlock];
-    __shared__ uint8_t s_split[kTreeletSets * kTreeletBlock];
-    const int k = blockIdx.x * kTreeletBlock + threadIdx.x;
-    if (k >= t.n) return;
-    const TreeletScratch w{s_cost + threadIdx.x, s_split + threadIdx.x, kTreeletBlock};
-    t.cost[k] = subtree_cost(box_half_area(t.lo[k], t.hi[k]), 1, 0.0f, 0.0f);
-    for (int node = t.parent[k]; node >= 0; node = t.parent[node]) {
+    __shared__ float s_cost[kTreeletSets];
+    __shared__ uint8_t s_split[kTreeletSets];
+    __shared__ float4 s_llo[kTreeletLeaves], s_lhi[kTreeletLeaves];   // the current treelet's leaves
+    __shared__ int s_lcnt[kTreeletLeaves];
+    const TreeletScratch w{s_cost, s_split, 1};
+    const int lane = threadIdx.x;
+    const int k = blockIdx.x * kTreeletBlock + lane;
+    int node = -1;
+    if (k < t.n) {
+        t.cost[k] = subtree_cost(box_half_area(t.lo[k], t.hi[k]), 1, 0.0f, 0.0f);
+        node = t.parent[k];
+    }
+    // every lane stays in the loop until the wavefront is done: the subset
+    // search needs all of them
+    while (__ballot(node >= 0) != 0) {
         __threadfence();
-        if (atomicAdd(&arrive[node - t.n], 1) == 0) return;
+        if (node >= 0 && atomicAdd(&arrive[node - t.n], 1) == 0) node = -1;   // the first arrival stops
         __threadfence();
-        if (t.cnt[node] >= kTreeletLeaves) {
-            treelet_optimize(t, node, w);
-        } else {
+        const bool root = node >= 0 && t.cnt[node] >= kTreeletLeaves;
+        if (node >= 0 && !root) {
             const int2 c = t.child[node];
             t.cost[node] = subtree_cost(box_half_area(t.lo[node], t.hi[node]), t.cnt[node], t.cost[c.x], t.cost[c.y]);
         }
+        // the roots of this step lie in disjoint subtrees
+        for (uint64_t roots = __ballot(root); roots != 0; roots &= roots - 1) {
+            const int r = __shfl(node, __ffsll((unsigned long long)roots) - 1);
+            Treelet tl;
+            treelet_form(t, r, tl);
+            if (lane == 0) {   // the leaves' boxes from LDS, not from each lane's private copy
+#pragma unroll
+                for (int q = 0; q < kTreeletLeaves; ++q) {
+                    s_llo[q] = tl.llo[q];
+                    s_lhi[q] = tl.lhi[q];
+                    s_lcnt[q] = tl.lcnt[q];
+                }
+            }
+            __syncthreads();
+            const uint32_t nsets = 1u << tl.nl;
+            for (int size = 1; size <= tl.nl; ++size) {
+                for (uint32_t s = (uint32_t)lane + 1; s < nsets; s += kTreeletBlock)
+                    if (__popc(s) == size) treelet_subset(t, tl, s_llo, s_lhi, s_lcnt, s, w);
+                __syncthreads();
+            }
+            if (lane == 0) treelet_finish(t, r, tl, treelet_keep_cost(t, r), w);
+            __syncthreads();   // the tables serve the next root
+        }
+        if (node >= 0) node = t.parent[node];
     }
 }
 
