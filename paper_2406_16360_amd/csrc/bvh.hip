@@ -519,38 +519,41 @@ __device__ __forceinline__ void leaf_box(const TriRec *__restrict__ tris, int re
 // brings its last internal child (arrival counters, as in the build).  Child
 // boxes are stored padded, as the build stores them; the unpadded node boxes
 // feed the level above.
-__global__ void k_refit_nodes(int nnodes, BvhNode *__restrict__ nodes, const int32_t *__restrict__ npar,
-                              const TriRec *__restrict__ tris, float4 *__restrict__ nlo, float4 *__restrict__ nhi,
-                              int32_t *__restrict__ arrive) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nnodes) return;
-    int4 r0 = nodes[i].n3;
-    if (r0.x >= 0 || r0.y >= 0) return;
-    int node = i;
-    while (true) {
-        int4 r = nodes[node].n3;
-        int refs[2] = {r.x, r.y};
-        float4 lo[2], hi[2];
-        for (int q = 0; q < 2; ++q) {
-            if (refs[q] < 0) leaf_box(tris, refs[q], lo[q], hi[q]);
-            else { lo[q] = nlo[refs[q]]; hi[q] = nhi[refs[q]]; }
-        }
-        BvhNode &nd = nodes[node];
-        nd.n0 = make_float4(pad_lo(lo[0].x), pad_hi(hi[0].x), pad_lo(lo[0].y), pad_hi(hi[0].y));
-        nd.n1 = make_float4(pad_lo(lo[1].x), pad_hi(hi[1].x), pad_lo(lo[1].y), pad_hi(hi[1].y));
-        nd.n2 = make_float4(pad_lo(lo[0].z), pad_hi(hi[0].z), pad_lo(lo[1].z), pad_hi(hi[1].z));
-        nlo[node] = make_float4(fminf(lo[0].x, lo[1].x), fminf(lo[0].y, lo[1].y), fminf(lo[0].z, lo[1].z), 0.f);
-        nhi[node] = make_float4(fmaxf(hi[0].x, hi[1].x), fmaxf(hi[0].y, hi[1].y), fmaxf(hi[0].z, hi[1].z), 0.f);
-        __threadfence();
-        int p = npar[node];
-        if (p < 0) break;
-        int parent = p >> 1;
-        int4 pr = nodes[parent].n3;
-        int need = (pr.x >= 0) + (pr.y >= 0);
-        if (atomicAdd(&arrive[parent], 1) + 1 < need) break;
-        __threadfence();
-        node = parent;
+// One height of the refit: the nodes of height h (1 + the larger height of
+// their inner children, leaves 0) take their boxes from their leaves'
+// triangles and from their inner children, which earlier launches (smaller
+// heights) have refitted; the launch boundary orders the levels, so no
+// thread waits on another.  order[0, count) lists the level's node slots.
+__global__ void k_refit_level(const int32_t *__restrict__ order, int count, BvhNode *__restrict__ nodes,
+                              const TriRec *__restrict__ tris, float4 *__restrict__ nlo, float4 *__restrict__ nhi) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int node = order[t];
+    const int4 r = nodes[node].n3;
+    const int refs[2] = {r.x, r.y};
+    float4 lo[2], hi[2];
+    for (int q = 0; q < 2; ++q) {
+        if (refs[q] < 0) leaf_box(tris, refs[q], lo[q], hi[q]);
+        else { lo[q] = nlo[refs[q]]; hi[q] = nhi[refs[q]]; }
     }
+    BvhNode &nd = nodes[node];
+    nd.n0 = make_float4(pad_lo(lo[0].x), pad_hi(hi[0].x), pad_lo(lo[0].y), pad_hi(hi[0].y));
+    nd.n1 = make_float4(pad_lo(lo[1].x), pad_hi(hi[1].x), pad_lo(lo[1].y), pad_hi(hi[1].y));
+    nd.n2 = make_float4(pad_lo(lo[0].z), pad_hi(hi[0].z), pad_lo(lo[1].z), pad_hi(hi[1].z));
+    nlo[node] = make_float4(fminf(lo[0].x, lo[1].x), fminf(lo[0].y, lo[1].y), fminf(lo[0].z, lo[1].z), 0.f);
+    nhi[node] = make_float4(fmaxf(hi[0].x, hi[1].x), fmaxf(hi[0].y, hi[1].y), fmaxf(hi[0].z, hi[1].z), 0.f);
+}
+
+// first position of every height in the height-sorted node list (heights
+// run without gaps from 1 to the root's)
+__global__ void k_height_starts(const uint32_t *__restrict__ h, int n, int32_t *__restrict__ start) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (i == 0 || h[i] != h[i - 1])) start[h[i]] = i;
+}
+
+__global__ void k_iota(uint32_t *__restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (uint32_t)i;
 }
 
 // Traversal nodes: a collapse of the binary tree into nodes of up to four
@@ -590,11 +593,11 @@ __device__ __forceinline__ float split_cost(float4 a, float4 b, int k, int &k1) 
     return best;
 }
 
-// S(n, 1..4) of every binary node, bottom-up: a thread starts at every node
+// S(n, 1..4) and the height of every binary node, bottom-up: a thread starts at every node
 // whose children are both leaves and climbs; a node is finished by the thread
 // that brings its last inner child (arrival counters, as in the refit).
 __global__ void k_wide_cost(int nnodes, const BvhNode *__restrict__ nodes, const int32_t *__restrict__ npar,
-                            float4 *__restrict__ S, int32_t *__restrict__ arrive) {
+                            float4 *__restrict__ S, int32_t *__restrict__ arrive, uint32_t *__restrict__ height) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nnodes) return;
     const int4 r0 = nodes[i].n3;
@@ -610,6 +613,7 @@ __global__ void k_wide_cost(int nnodes, const BvhNode *__restrict__ nodes, const
         const float d2 = split_cost(a, b, 2, k1), d3 = split_cost(a, b, 3, k1), d4 = split_cost(a, b, 4, k1);
         const float s1 = area + d4;
         S[node] = make_float4(s1, fminf(s1, d2), fminf(s1, d3), fminf(s1, d4));
+        height[node] = 1u + max(nd.n3.x >= 0 ? height[nd.n3.x] : 0u, nd.n3.y >= 0 ? height[nd.n3.y] : 0u);
         __threadfence();
         if (p < 0) break;
         const int parent = p >> 1;
@@ -876,6 +880,7 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
     int npow2 = 1024;
     while (npow2 < n) npow2 *= 2;
     DevBuf tlo, thi, keys, ids, child, parent, range, flags, blo, bhi, part, depth, bad;
+    DevBuf arrive, hgt, hsorted, hiota, hstart, sort_tmp;   // bottom-up passes, the refit's height order
     DevBuf pchild, cnt, clus, clus2, nn, mflag, kflag, mo, ko, tot, slot, scan_tmp, tcost, tarrive;   // PLOC
     const bool ploc = builder == MRS_BVH_PLOC && nf > 1;
     mrs_bvh *b = new mrs_bvh();
@@ -1031,7 +1036,7 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
     TRY(b->npar.alloc(sizeof(int32_t) * b->nnodes));
     TRY(b->nlo.alloc(sizeof(float4) * b->nnodes));
     TRY(b->nhi.alloc(sizeof(float4) * b->nnodes));
-    TRY(b->arrive.alloc(sizeof(int32_t) * b->nnodes));
+    TRY(arrive.alloc(sizeof(int32_t) * b->nnodes));
     TRY(hip_check(hipMemsetAsync(b->npar.p, 0xFF, sizeof(int32_t) * b->nnodes, s), "memset"));
     k_node_parents<<<blocks(b->nnodes), 256, 0, s>>>((BvhNode *)b->nodes.p, b->nnodes, (int32_t *)b->npar.p);
     // traversal nodes
@@ -1039,9 +1044,31 @@ mrs_status build(const float *d_pos, int32_t nv, const int32_t *d_faces, int32_t
     TRY(b->wlevel.alloc(sizeof(int32_t) * b->nnodes));
     TRY(b->wcut.alloc(sizeof(int4) * b->nnodes));
     // the collapse costs live in nlo until the first refit needs it
-    k_fill_i32<<<blocks(b->nnodes), 256, 0, s>>>((int32_t *)b->arrive.p, b->nnodes, 0);
+    k_fill_i32<<<blocks(b->nnodes), 256, 0, s>>>((int32_t *)arrive.p, b->nnodes, 0);
+    TRY(hgt.alloc(sizeof(uint32_t) * b->nnodes));
     k_wide_cost<<<blocks(b->nnodes), 256, 0, s>>>(b->nnodes, (const BvhNode *)b->nodes.p, (const int32_t *)b->npar.p,
-                                                  (float4 *)b->nlo.p, (int32_t *)b->arrive.p);
+                                                  (float4 *)b->nlo.p, (int32_t *)arrive.p, (uint32_t *)hgt.p);
+    {   // the refit's order: node slots by height (stable, so slot order within a height)
+        TRY(b->horder.alloc(sizeof(int32_t) * b->nnodes));
+        TRY(hsorted.alloc(sizeof(uint32_t) * b->nnodes));
+        TRY(hiota.alloc(sizeof(uint32_t) * b->nnodes));
+        k_iota<<<blocks(b->nnodes), 256, 0, s>>>((uint32_t *)hiota.p, b->nnodes);
+        TRY(sort_pairs_u32((const uint32_t *)hgt.p, (uint32_t *)hsorted.p, (const uint32_t *)hiota.p,
+                           (uint32_t *)b->horder.p, (size_t)b->nnodes, sort_tmp, s));
+        uint32_t h_top = 0;
+        TRY(hip_check(hipMemcpyAsync(&h_top, (const uint32_t *)hsorted.p + (b->nnodes - 1), sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, s), "copy"));
+        TRY(hip_check(hipStreamSynchronize(s), "sync"));
+        if (h_top < 1 || h_top > (uint32_t)b->nnodes) { st = fail(MRS_EHIP, "mrs_build_bvh: bad node heights"); goto done; }
+        TRY(hstart.alloc(sizeof(int32_t) * (h_top + 2)));
+        k_fill_i32<<<blocks(h_top + 2), 256, 0, s>>>((int32_t *)hstart.p, (int)h_top + 2, 0);
+        k_height_starts<<<blocks(b->nnodes), 256, 0, s>>>((const uint32_t *)hsorted.p, b->nnodes, (int32_t *)hstart.p);
+        b->hstart.assign(h_top + 2, 0);
+        TRY(hip_check(hipMemcpyAsync(b->hstart.data(), hstart.p, sizeof(int32_t) * (h_top + 1), hipMemcpyDeviceToHost, s),
+                      "copy"));
+        TRY(hip_check(hipStreamSynchronize(s), "sync"));
+        b->hstart[h_top + 1] = b->nnodes;
+    }
     k_wide_init<<<blocks(b->nnodes), 256, 0, s>>>((int32_t *)b->wlevel.p, b->nnodes);
     k_fill_i32<<<1, 1, 0, s>>>((int32_t *)bad.p, 1, 0);      // receives the deepest traversal level
     for (int lv = 0; lv <= b->depth; ++lv)     // a level descends at least one binary level
@@ -1096,10 +1123,12 @@ extern "C" mrs_status mrs_bvh_refit(mrs_bvh *b, const float *d_pos, int32_t nv, 
     if (nv != b->nv) return fail(MRS_EINVAL, "mrs_bvh_refit: %d vertices, the BVH was built for %d", nv, b->nv);
     hipStream_t s = (hipStream_t)stream;
     k_refit_tris<<<blocks(b->nf), 256, 0, s>>>(d_pos, (const int32_t *)b->faces.p, b->nf, (TriRec *)b->tris.p);
-    k_fill_i32<<<blocks(b->nnodes), 256, 0, s>>>((int32_t *)b->arrive.p, b->nnodes, 0);
-    k_refit_nodes<<<blocks(b->nnodes), 256, 0, s>>>(b->nnodes, (BvhNode *)b->nodes.p, (const int32_t *)b->npar.p,
-                                                    (const TriRec *)b->tris.p, (float4 *)b->nlo.p, (float4 *)b->nhi.p,
-                                                    (int32_t *)b->arrive.p);
+    for (size_t h = 1; h + 1 < b->hstart.size(); ++h) {   // one launch per height, leaves up
+        const int first = b->hstart[h], count = b->hstart[h + 1] - first;
+        k_refit_level<<<blocks(count), 256, 0, s>>>((const int32_t *)b->horder.p + first, count,
+                                                    (BvhNode *)b->nodes.p, (const TriRec *)b->tris.p,
+                                                    (float4 *)b->nlo.p, (float4 *)b->nhi.p);
+    }
     k_wide_build<<<blocks(b->nnodes), 256, 0, s>>>((const BvhNode *)b->nodes.p, b->nnodes, (const int32_t *)b->wlevel.p,
                                                    (const int4 *)b->wcut.p, (WideNode *)b->wnodes.p);
     return hip_check(hipGetLastError(), "mrs_bvh_refit launch");

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/mirres.h"
 
@@ -61,9 +62,12 @@ struct mrs_bvh {
     mrs::DevBuf nodes;   // BvhNode[nnodes]
     mrs::DevBuf tris;    // TriRec[nf], leaf order
     mrs::DevBuf faces;   // int32 [nf][3], validated copy used for shading
-    // refit state: parent of every node slot ((slot << 1) | side, -1 at the
-    // root), unpadded node boxes and arrival counters for the bottom-up pass
-    mrs::DevBuf npar, nlo, nhi, arrive;
+    // parent of every node slot ((slot << 1) | side, -1 at the root), unpadded
+    // node boxes; for the refit, the node slots ordered by height (leaves 0, a
+    // node one above its higher inner child) and the first position of each
+    // height 1..H in that order (hstart[H + 1] = nnodes)
+    mrs::DevBuf npar, nlo, nhi, horder;
+    std::vector<int32_t> hstart;
     // traversal nodes (WideNode[nnodes], at the binary index of the node
     // they stand for), the traversal level each binary node heads (-1: none)
     // and each traversal node's members as binary node slots (int4)
