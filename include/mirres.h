@@ -236,7 +236,8 @@ void       mrs_bvh_destroy(mrs_bvh *bvh);
 
 /* Refits the BVH to new positions of the same vertices (faces unchanged):
  * the triangle records and every node box are recomputed bottom-up over the
- * unchanged tree.  This is the per-iteration update of the acceleration
+ * unchanged tree, one launch per node height (the order is fixed at build).
+ * This is the per-iteration update of the acceleration
  * structure while vertices move (the paper rebuilds its LBVH every
  * iteration, Appendix A "Visibility estimation").  Hit results stay exact for
  * any motion; only the tree quality degrades with large motion, when a
