@@ -360,8 +360,8 @@ __global__ void k_ploc_merge(const int32_t *__restrict__ clus, const int32_t *__
 
 // One bottom-up sweep of treelet restructuring over PLOC's merge tree: a
 // thread starts at every triangle and climbs; the second child to arrive at
-// a node finishes it, its whole subtree being final then (arrival counters,
-// as in the refit).  Nodes of at least kTreeletLeaves triangles are treelet
+// a node finishes it, its whole subtree being final then (per-node arrival
+// counters, as for the LBVH boxes).  Nodes of at least kTreeletLeaves triangles are treelet
 // roots, the others only take their cost.  A block is one wavefront, and its
 // lanes search the subsets of each treelet root together, one root after
 // another: the subsets of one size at a time (each needs only smaller ones),
@@ -595,7 +595,7 @@ __device__ __forceinline__ float split_cost(float4 a, float4 b, int k, int &k1) 
 
 // S(n, 1..4) and the height of every binary node, bottom-up: a thread starts at every node
 // whose children are both leaves and climbs; a node is finished by the thread
-// that brings its last inner child (arrival counters, as in the refit).
+// that brings its last inner child (per-node arrival counters).
 __global__ void k_wide_cost(int nnodes, const BvhNode *__restrict__ nodes, const int32_t *__restrict__ npar,
                             float4 *__restrict__ S, int32_t *__restrict__ arrive, uint32_t *__restrict__ height) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;

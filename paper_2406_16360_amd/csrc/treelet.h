@@ -33,7 +33,8 @@ struct MergeTree {
     int n;
 };
 
-// per-thread tables of the subset search, entry S at [S * stride]
+// tables of the subset search (one thread's, or a wavefront's shared in
+// LDS), entry S at [S * stride]
 struct TreeletScratch {
     float *cost;
     uint8_t *split;
@@ -56,8 +57,8 @@ __host__ __device__ inline int lowest_bit(uint32_t s) {
 }
 
 // union box and triangle count of the treelet leaves in set s
-__host__ __device__ __forceinline__ void set_box(uint32_t s, const float4 *llo, const float4 *lhi, const int *lcnt, float4 &lo,
-                                        float4 &hi, int &cnt) {
+__host__ __device__ __forceinline__ void set_box(uint32_t s, const float4 *llo, const float4 *lhi, const int *lcnt,
+                                                 float4 &lo, float4 &hi, int &cnt) {
     lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
     cnt = 0;
