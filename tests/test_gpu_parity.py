@@ -368,6 +368,37 @@ def test_bvh_refit_moved_vertices(mr, orc_mod, builder):
     assert np.mean(h_ref[:, 3].view(np.int32) == p) >= 0.9995
 
 
+@pytest.mark.parametrize("builder", [0, 1], ids=["lbvh", "ploc"])
+@pytest.mark.parametrize("nf", [1, 2, 9, 300])
+def test_bvh_refit_small_trees_and_back(mr, builder, nf):
+    """The refit's height order on the smallest trees (a single node of
+    height 1 upwards): after a move the hits equal a fresh build's, and a
+    refit back to the build's positions restores the build's hits exactly."""
+    rng = np.random.default_rng(11 + nf)
+    c = np.column_stack([rng.random(nf), rng.random(nf), rng.random(nf)])
+    pos = (c[:, None, :] + rng.normal(scale=0.08, size=(nf, 3, 3))).reshape(-1, 3).astype(np.float32)
+    faces = np.arange(3 * nf, dtype=np.int32).reshape(nf, 3)
+    moved = (pos + rng.normal(scale=0.05, size=pos.shape)).astype(np.float32)
+    n = 20000
+    o = np.column_stack([rng.uniform(-0.2, 1.2, n), rng.uniform(-0.2, 1.2, n), np.full(n, 3.0)]).astype(np.float32)
+    d = np.tile(np.array([[0.0, 0.0, -1.0]], np.float32), (n, 1))
+    d[:, :2] = rng.normal(scale=0.05, size=(n, 2))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    ot, dt = torch.tensor(o, device="cuda"), torch.tensor(d, device="cuda")
+    fc = torch.tensor(faces, device="cuda")
+    bvh = mr.build_bvh(torch.tensor(pos, device="cuda"), fc, builder=builder)
+    h0 = bvh.trace(ot, dt).cpu().numpy()
+    assert (h0[:, 3].view(np.int32) >= 0).any()
+    bvh.refit(torch.tensor(moved, device="cuda"))
+    h1 = bvh.trace(ot, dt).cpu().numpy()
+    h_fresh = mr.build_bvh(torch.tensor(moved, device="cuda"), fc, builder=builder).trace(ot, dt).cpu().numpy()
+    assert np.array_equal(h1[:, 3].view(np.int32), h_fresh[:, 3].view(np.int32))
+    assert np.array_equal(h1[:, :3], h_fresh[:, :3])
+    bvh.refit(torch.tensor(pos, device="cuda"))
+    h2 = bvh.trace(ot, dt).cpu().numpy()
+    assert np.array_equal(h2.view(np.int32), h0.view(np.int32))   # bitwise (a miss's face id reads as NaN)
+
+
 # ------------------------------------------------------------- edge inputs
 def _edge_workload(kind):
     """The textured scene with inputs an optimiser can produce: env texels
